@@ -1,0 +1,189 @@
+"""CPU oracle for the lot-sizing VNS — TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this package.  The product
+library never calls it and has no fallback to it.  It wraps the plain C in `vns_oracle.c` (built into
+`liboracle.so` by `oracle/build.py`) with numpy marshalling; it shares no code with the HIP path.
+
+Parity status per function (what pins it, see tests/test_oracle_pins.py):
+  decode         brute force vs Wagner-Whitin DP and per-pattern LP(z) equality when R = 0; LP(z) <= decode
+                 and MILP <= min decode when R > 0; closed forms; hand-worked golden examples; flow-balance
+                 invariants on random instances.
+  price_all      brute-force table of all 2^(2T) patterns (K = 1, T <= 6): every slot's price.
+  vnd            local optimality of the result, monotone objective, per-product independence.
+  philox         numpy.random.Philox (the library's Philox4x64-10).
+  shake          slots derived from numpy.random.Philox outputs; feasibility of every applied flip.
+  gvns           acceptance rule, k schedule, best tracking, resume equivalence, objective recomputation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from pathlib import Path
+
+import numpy as np
+
+INF = np.iinfo(np.int64).max
+_HERE = Path(__file__).resolve().parent
+_LIB = None
+
+RECORD_DTYPE = np.dtype([("iter", np.int32), ("k", np.int32), ("accepted", np.int32), ("pad", np.int32),
+                         ("F_shaken", np.int64), ("F_local", np.int64), ("F_best", np.int64)])
+
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_u8p = np.ctypeslib.ndpointer(dtype=np.uint8, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+_recp = np.ctypeslib.ndpointer(dtype=RECORD_DTYPE, flags="C_CONTIGUOUS")
+
+
+def lib():
+    """Load liboracle.so, building it first if it is missing."""
+    global _LIB
+    if _LIB is None:
+        path = _HERE / "liboracle.so"
+        if not path.exists():
+            from . import build as _build
+            _build.build()
+        L = ctypes.CDLL(str(path))
+        c = ctypes
+        inst = [_i32p, _i32p, _i32p, _i32p, _i32p, _i32p]
+        L.orc_decode.restype = c.c_int64
+        L.orc_decode.argtypes = [c.c_int, _i32p, _i32p, c.c_int64, c.c_int64, c.c_int64, c.c_int64,
+                                 _u8p, _u8p, _i64p, _i64p, _i64p, _i64p]
+        L.orc_objective.restype = c.c_int64
+        L.orc_objective.argtypes = [c.c_int, c.c_int] + inst + [_u8p, _u8p, _i64p]
+        L.orc_apply_slot.restype = c.c_int
+        L.orc_apply_slot.argtypes = [c.c_int, _u8p, _u8p, c.c_int]
+        L.orc_price_all.restype = c.c_int64
+        L.orc_price_all.argtypes = [c.c_int, c.c_int] + inst + [_u8p, _u8p, c.c_uint32, _i64p]
+        L.orc_argmin.restype = c.c_int64
+        L.orc_argmin.argtypes = [c.c_int64, _i64p, c.POINTER(c.c_int64)]
+        L.orc_vnd.restype = c.c_int64
+        L.orc_vnd.argtypes = [c.c_int, c.c_int] + inst + [_u8p, _u8p, _i32p, c.c_int, c.POINTER(c.c_int64)]
+        L.orc_philox4x64_10.restype = None
+        L.orc_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
+        L.orc_draw.restype = c.c_int64
+        L.orc_draw.argtypes = [c.c_uint64] * 5
+        L.orc_shake.restype = c.c_int
+        L.orc_shake.argtypes = [c.c_int, c.c_int] + inst + [_u8p, _u8p, c.c_int, c.c_uint64, c.c_uint64,
+                                                            c.c_uint64, _i32p]
+        L.orc_gvns.restype = c.c_int64
+        L.orc_gvns.argtypes = ([c.c_int, c.c_int] + inst +
+                               [_u8p, _u8p, _i32p, c.c_int, c.c_int, c.c_uint64, c.c_uint64, c.c_int64,
+                                c.c_int64, c.POINTER(c.c_int32), c.POINTER(c.c_int64), _recp,
+                                c.POINTER(c.c_int64)])
+        _LIB = L
+    return _LIB
+
+
+def _inst(inst):
+    return inst.arrays()
+
+
+def _rows(z, K, T):
+    a = np.ascontiguousarray(np.asarray(z, dtype=np.uint8).reshape(K, T))
+    return a
+
+
+def decode(T, D, R, kM, kR, hM, hR, zM, zR):
+    """Decode one product: returns (cost, xM, xR, yM, yR); cost is INF when infeasible."""
+    xM, xR, yM, yR = (np.zeros(T, np.int64) for _ in range(4))
+    c = lib().orc_decode(int(T), np.ascontiguousarray(D, np.int32), np.ascontiguousarray(R, np.int32),
+                         int(kM), int(kR), int(hM), int(hR), np.ascontiguousarray(zM, np.uint8),
+                         np.ascontiguousarray(zR, np.uint8), xM, xR, yM, yR)
+    return int(c), xM, xR, yM, yR
+
+
+def objective(inst, zM, zR):
+    """(F, cost per product) of a solution given as [K, T] bit rows."""
+    cost = np.zeros(inst.K, np.int64)
+    F = lib().orc_objective(inst.K, inst.T, *_inst(inst), _rows(zM, inst.K, inst.T),
+                            _rows(zR, inst.K, inst.T), cost)
+    return int(F), cost
+
+
+def apply_slot(T, zM_row, zR_row, l):
+    """Apply local slot l to copies of one product's rows; returns (valid, zM, zR)."""
+    a = np.ascontiguousarray(zM_row, np.uint8).copy()
+    b = np.ascontiguousarray(zR_row, np.uint8).copy()
+    ok = lib().orc_apply_slot(int(T), a, b, int(l))
+    return bool(ok), a, b
+
+
+def price_all(inst, zM, zR, nb_mask=7):
+    """Prices of all 4KT slots (INF where not a priced move) and the number of move-evaluations."""
+    price = np.zeros(4 * inst.K * inst.T, np.int64)
+    n = lib().orc_price_all(inst.K, inst.T, *_inst(inst), _rows(zM, inst.K, inst.T),
+                            _rows(zR, inst.K, inst.T), int(nb_mask), price)
+    return price, int(n)
+
+
+def argmin(price):
+    """Lexicographic (price, slot) minimum; (INF, -1) when nothing is priced."""
+    p = np.ascontiguousarray(price, np.int64)
+    s = ctypes.c_int64(0)
+    v = lib().orc_argmin(len(p), p, ctypes.byref(s))
+    return int(v), int(s.value)
+
+
+def vnd(inst, zM, zR, nb_list=(1, 2, 4)):
+    """VND (Algorithm 1) from the given solution; returns (F, zM, zR, move-evaluations)."""
+    a = _rows(zM, inst.K, inst.T).copy()
+    b = _rows(zR, inst.K, inst.T).copy()
+    ev = ctypes.c_int64(0)
+    nb = np.ascontiguousarray(nb_list, np.int32)
+    F = lib().orc_vnd(inst.K, inst.T, *_inst(inst), a, b, nb, len(nb), ctypes.byref(ev))
+    return int(F), a, b, int(ev.value)
+
+
+def philox4x64_10(key, ctr):
+    """One Philox4x64-10 block for key (2 words) and counter (4 words)."""
+    out = np.zeros(4, np.uint64)
+    lib().orc_philox4x64_10(np.asarray(key, np.uint64), np.asarray(ctr, np.uint64), out)
+    return out
+
+
+def draw(seed, chain, it, j, n):
+    return int(lib().orc_draw(seed, chain, it, j, n))
+
+
+def shake(inst, zM, zR, k, seed, chain, it):
+    """Shake(x, k): returns (zM, zR, applied flags per draw)."""
+    a = _rows(zM, inst.K, inst.T).copy()
+    b = _rows(zR, inst.K, inst.T).copy()
+    applied = np.zeros(max(k, 1), np.int32)
+    lib().orc_shake(inst.K, inst.T, *_inst(inst), a, b, int(k), seed, chain, it, applied)
+    return a, b, applied[:k]
+
+
+class Chain:
+    """One GVNS chain of the oracle: state (x, k, best) and resumable runs."""
+
+    def __init__(self, inst, seed, chain, nb_list=(1, 2, 4), k_max=5):
+        self.inst = inst
+        self.seed = int(seed)
+        self.chain = int(chain)
+        self.nb = np.ascontiguousarray(nb_list, np.int32)
+        self.k_max = int(k_max)
+        self.zM = np.ones((inst.K, inst.T), np.uint8)
+        self.zR = np.zeros((inst.K, inst.T), np.uint8)
+        self.k = 1
+        self.it = 0
+        self.F, _ = objective(inst, self.zM, self.zR)
+        self.F_best = self.F
+        self.evals = 0
+
+    def run(self, iters):
+        rec = np.zeros(max(int(iters), 1), RECORD_DTYPE)
+        k = ctypes.c_int32(self.k)
+        fb = ctypes.c_int64(self.F_best)
+        ev = ctypes.c_int64(0)
+        inst = self.inst
+        self.F = int(lib().orc_gvns(inst.K, inst.T, *_inst(inst), self.zM, self.zR, self.nb, len(self.nb),
+                                    self.k_max, self.seed, self.chain, self.it, int(iters), ctypes.byref(k),
+                                    ctypes.byref(fb), rec, ctypes.byref(ev)))
+        self.k = int(k.value)
+        self.F_best = int(fb.value)
+        self.it += int(iters)
+        self.evals += int(ev.value)
+        return rec[:int(iters)]
