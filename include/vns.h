@@ -1,0 +1,180 @@
+/*
+ * vns.h — C ABI of the MI355X (gfx950) variable neighbourhood search for the uncapacitated multi-item
+ * economic lot-sizing problem with remanufacturing (Antoniadis & Sifaleras 2017).
+ *
+ * Problem (Section 2 of the paper): K products, T periods; per product k and period t a demand D(k,t) and
+ * a quantity of returns R(k,t) that can be remanufactured and sold as new; per product the setup costs
+ * kM(k) (manufacturing) and kR(k) (remanufacturing) and the unit holding costs hM(k) (serviceable stock)
+ * and hR(k) (recoverable stock).  A solution is a pair of setup bit rows zM(k,t), zR(k,t); its lots and
+ * inventories follow from the decode (a setup covers demand until the next setup of either type, returns
+ * are used first, a remanufacture-only shortfall is made by the last manufacturing lot) and its cost is
+ * setups plus holding, an exact int64.
+ *
+ * The search (Section 3): VND (Algorithm 1) applies, per product and per neighbourhood, the best move when
+ * it strictly improves, until a pass changes nothing; GVNS (Algorithm 2, with the accept-if-better rule of
+ * Section 1) shakes k random setup flips, runs the VND and accepts the result if it is cheaper.
+ *
+ * Moves: product k owns 4T slots — [0,T) flip zM(t); [T,2T) flip zR(t); [2T,3T-1) move a manufacturing
+ * setup one period (swap zM(t), zM(t+1), a move only if they differ); 3T-1 pad; [3T,4T-1) the same for zR;
+ * 4T-1 pad.  The global slot of local slot l of product k is 4T*k + l.
+ *
+ * Conventions for every call:
+ *   - Input arrays are host pointers, read during the call and copied: the caller keeps ownership.
+ *   - Output arrays are host pointers allocated by the caller, written only when the call returns VNS_OK.
+ *   - Work runs on the context's stream (its own, or the one given to vns_bind_stream); every call that
+ *     returns results waits for them before returning.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - After a VNS_EDEVICE error only vns_destroy and vns_last_error are valid (others return VNS_ESTATE).
+ */
+#ifndef VNS_H
+#define VNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vns_ctx vns_ctx;
+
+typedef enum vns_status {
+    VNS_OK = 0,
+    VNS_EINVAL = -1,   /* bad argument: NULL required pointer, size out of range, negative input */
+    VNS_ENOMEM = -2,   /* device or host allocation failed                                       */
+    VNS_EDEVICE = -3,  /* a HIP call failed (message in vns_last_error); the context is dead    */
+    VNS_ERANGE = -4,   /* the exact-cost bounds cannot be guaranteed, or an infeasible solution  */
+    VNS_ESTATE = -5    /* call not valid in the context's state                                  */
+} vns_status;
+
+/* Neighbourhood ids (bit masks). */
+enum { VNS_NB_FLIP_M = 1, VNS_NB_FLIP_R = 2, VNS_NB_SHIFT = 4 };
+
+#define VNS_T_MAX 128          /* periods per instance                                  */
+#define VNS_K_MAX 1048576      /* products per instance                                 */
+#define VNS_KSHAKE_MAX 64      /* largest shake size k_max                              */
+#define VNS_ALL_CHAINS (-1)    /* chain argument of vns_eval_neighbourhood: every chain  */
+#define VNS_PRICE_INF INT64_MAX
+
+/* Options (vns_set_option / vns_get_option). */
+enum vns_option {
+    VNS_OPT_CHAINS = 1,   /* chains per instance, 1..65536 (default 1); setting it resets every chain    */
+    VNS_OPT_KMAX = 2,     /* largest shake size k_max, 1..VNS_KSHAKE_MAX (default 5)                    */
+    VNS_OPT_NB_LIST = 3,  /* VND neighbourhood order, one id per 4-bit nibble, lowest nibble first,
+                             up to 4 entries (default 0x421 = flip zM, flip zR, shift)                   */
+    VNS_OPT_TRACE = 4,    /* 1 = vns_run keeps one record per chain and iteration (default 1)           */
+    VNS_OPT_RUN_WAVES = 5 /* wavefronts per workgroup of the search kernel, 1..16 (default 8)           */
+};
+
+/* One GVNS iteration of one chain. */
+typedef struct vns_record {
+    int32_t iter;      /* absolute iteration index (continues across vns_run calls)                     */
+    int32_t k;         /* shake size used                                                               */
+    int32_t accepted;  /* 1 if the VND result replaced the current solution                             */
+    int32_t pad;
+    int64_t F_shaken;  /* objective after the shake                                                     */
+    int64_t F_local;   /* objective after the VND                                                       */
+    int64_t F_best;    /* best objective of the chain so far                                            */
+} vns_record;
+
+typedef struct vns_stats {
+    int64_t iterations;      /* GVNS iterations run per chain since creation or the last reset            */
+    int64_t move_evals;      /* exactly priced moves (valid slots) in all chains since creation            */
+    int64_t last_run_evals;  /* move-evaluations of the last vns_run call                                 */
+    double last_run_ms;      /* device time of the last vns_run call (HIP events on the context stream)  */
+    int64_t last_eval_evals; /* move-evaluations of the last vns_eval_neighbourhood call                  */
+    double last_eval_ms;     /* device time of the pricing kernel of that call                           */
+} vns_stats;
+
+/*
+ * vns_create — one instance (Section 2 data).
+ *   K in [1, VNS_K_MAX], T in [1, VNS_T_MAX].
+ *   D, R: [K*T] int32, row-major [k][t], all >= 0 and < 2^24.
+ *   kM, kR, hM, hR: [K] int32, all >= 0.
+ *   seed: Philox key word 0 for every chain (word 1 is the chain index).
+ * The context starts with 1 chain whose solution is zM = 1, zR = 0 (every period manufactures its own
+ * demand), shake size 1, iteration 0.  Returns VNS_ERANGE if a product's cost or the int32 accumulators of
+ * the decode could overflow (per product: sum(D)*T and sum(R)*T must stay below 2^31, the worst-case cost
+ * below 2^47).  *out receives the context (NULL on error).
+ */
+vns_status vns_create(int32_t K, int32_t T, const int32_t *D, const int32_t *R, const int32_t *kM,
+                      const int32_t *kR, const int32_t *hM, const int32_t *hR, uint64_t seed, vns_ctx **out);
+
+/*
+ * vns_create_batch — n_inst independent instances in one context (same rules as vns_create for each).
+ *   K, T: [n_inst] sizes.  D, R: concatenation of the instances' [K_i*T_i] rows.  kM, kR, hM, hR:
+ *   concatenation of the [K_i] vectors.  Chain c of instance i has the global chain index
+ *   i*n_chains + c, which is also its Philox key word 1.
+ */
+vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const int32_t *T, const int32_t *D,
+                            const int32_t *R, const int32_t *kM, const int32_t *kR, const int32_t *hM,
+                            const int32_t *hR, uint64_t seed, vns_ctx **out);
+
+/* vns_destroy — frees every device and host resource of the context; NULL is accepted. */
+void vns_destroy(vns_ctx *ctx);
+
+/* vns_set_option / vns_get_option — see enum vns_option.  VNS_EINVAL for an unknown key or a value out of
+ * range. */
+vns_status vns_set_option(vns_ctx *ctx, int32_t key, int64_t value);
+vns_status vns_get_option(const vns_ctx *ctx, int32_t key, int64_t *value);
+
+/* vns_bind_stream — run all later work on `hip_stream` (a hipStream_t; NULL = the context's own stream).
+ * The caller keeps ownership and must keep it alive while the context uses it. */
+vns_status vns_bind_stream(vns_ctx *ctx, void *hip_stream);
+
+/*
+ * vns_eval_neighbourhood — exact pricing of every move of the neighbourhoods in nb_mask (an OR of VNS_NB_*)
+ * for the current solution of one chain, or of every chain (chain = VNS_ALL_CHAINS).  For a move of product
+ * k, price = F - cost_k + cost_k(after the move), the objective the move would give (Section 3: the new
+ * objective value of each product is computed independently).  Pads, swaps of equal bits, slots outside
+ * nb_mask and moves that make the product infeasible get VNS_PRICE_INF.
+ * Outputs (each may be NULL; per chain, chains concatenated in global chain order for VNS_ALL_CHAINS):
+ *   slot_price     [4*K*T] int64 per chain
+ *   prod_best      [K] int64: the lowest price of each product (VNS_PRICE_INF if none)
+ *   prod_best_slot [K] int32: its local slot (lowest on ties), -1 if none
+ *   best           [1] int64: the lowest price over the instance
+ *   best_slot      [1] int32: its global slot 4T*k + l (lowest on ties), -1 if none
+ */
+vns_status vns_eval_neighbourhood(vns_ctx *ctx, uint32_t nb_mask, int32_t chain, int64_t *slot_price,
+                                  int64_t *prod_best, int32_t *prod_best_slot, int64_t *best,
+                                  int32_t *best_slot);
+
+/*
+ * vns_run — every chain advances `iters` GVNS iterations (Algorithm 2): Shake(x, k) with Philox4x64-10
+ * (key (seed, chain), counter (iteration, draw, 0, 0)), VND (Algorithm 1) with the neighbourhood list,
+ * accept if F strictly drops (k = 1), else k = k + 1 wrapping after k_max.  iters >= 0.  The whole run is
+ * one device launch; with VNS_OPT_TRACE the records of this call replace those of the previous one.
+ */
+vns_status vns_run(vns_ctx *ctx, int32_t iters);
+
+/* vns_get_cost — current objective F and the best objective seen, of one chain (either may be NULL). */
+vns_status vns_get_cost(vns_ctx *ctx, int32_t chain, int64_t *F, int64_t *F_best);
+
+/* vns_get_solution — current setup rows of one chain, [K*T] uint8 0/1 each, row-major [k][t]. */
+vns_status vns_get_solution(vns_ctx *ctx, int32_t chain, uint8_t *zM, uint8_t *zR);
+
+/* vns_set_solution — replace the current solution of one chain ([K*T] uint8, nonzero = setup).  The
+ * chain's best objective is reset to the new F and its shake size to 1.  VNS_ERANGE (nothing changed) if
+ * a product would be infeasible. */
+vns_status vns_set_solution(vns_ctx *ctx, int32_t chain, const uint8_t *zM, const uint8_t *zR);
+
+/* vns_get_trajectory — records of the last vns_run for one chain: up to `cap` records into `rec`, the
+ * number available into *n (both may be NULL/0 to query the count). */
+vns_status vns_get_trajectory(vns_ctx *ctx, int32_t chain, vns_record *rec, int64_t cap, int64_t *n);
+
+/* vns_get_stats — counters and device times, see vns_stats. */
+vns_status vns_get_stats(const vns_ctx *ctx, vns_stats *out);
+
+/* vns_instance_size — K and T of instance `inst`; vns_num_chains — total number of chains. */
+vns_status vns_instance_size(const vns_ctx *ctx, int32_t inst, int32_t *K, int32_t *T);
+int64_t vns_num_chains(const vns_ctx *ctx);
+
+/* vns_last_error — text of the last error of the context (or of the last failed create when ctx is NULL);
+ * valid until the next call on the same context. */
+const char *vns_last_error(const vns_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VNS_H */

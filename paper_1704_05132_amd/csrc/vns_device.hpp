@@ -1,0 +1,172 @@
+// Device building blocks of the lot-sizing VNS for gfx950 (64-lane wavefronts).
+//
+// The hot loop is decode_cost(): the exact cost of one product's setup pattern, evaluated by one lane in
+// one forward pass over the T periods.  It is the same cost the look-ahead decode defines (Section 2
+// quantities: lots x_M, x_R and inventories y_M, y_R; setup plus holding cost), rewritten so that no
+// period needs to look ahead to the next setup:
+//   * a unit of demand consumed at tau and produced at p spends tau - p periods in serviceable stock;
+//   * a unit remanufactured at s leaves recoverable stock for the T - s remaining periods;
+//   * demand is served from the capacity fixed at the last remanufacturing setup lsR (all returns so far
+//     minus those used, PR(lsR) - XR) first, the rest by the last manufacturing setup lastM (in its own
+//     interval, or carried back to it from a remanufacture-only interval);
+//   * a manufacturing setup closes the remanufacturing capacity (its interval makes everything new).
+// With A1 = sum u*lsR (u = units remanufactured) and A2 = sum r*lastM (r = units manufactured):
+//   cost = kM*nM + kR*nR + hM*(sum t*D - A1 - A2) + hR*(sum PR - T*XR + A1).
+// Every period-step is 14 int32 operations; masks come from sign-extended bit extracts so that all the
+// setup-dependent updates are bitwise selects, and the two products use the full-rate 24-bit multiply.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vns_types.hpp"
+
+namespace vns {
+
+__device__ __forceinline__ int32_t sel(int32_t mask, int32_t a, int32_t b) { return (mask & a) | (~mask & b); }
+
+__device__ __forceinline__ uint32_t word_bit(int pos, int j) {
+    return ((pos >> 5) == j) ? (1u << (pos & 31)) : 0u;
+}
+
+__device__ __forceinline__ bool test_bit(const uint32_t (&w)[kWords], int pos) {
+    uint32_t v = 0;
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) v |= w[j] & word_bit(pos, j);
+    return v != 0u;
+}
+
+__device__ __forceinline__ void flip_bit(uint32_t (&w)[kWords], int pos) {
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) w[j] ^= word_bit(pos, j);
+}
+
+// Apply local slot l of a product with T periods to b.  Slots: [0,T) flip zM(t); [T,2T) flip zR(t);
+// [2T,3T-1) swap zM(t),zM(t+1); [3T,4T-1) swap zR(t),zR(t+1); 3T-1 and 4T-1 are pads.  Returns false,
+// leaving b unchanged, for a pad or a swap of two equal bits.
+__device__ __forceinline__ bool apply_move(Bits &b, int l, int T) {
+    const int blk = (l >= T) + (l >= 2 * T) + (l >= 3 * T);
+    const int t = l - blk * T;
+    if (blk == 0) { flip_bit(b.m, t); return true; }
+    if (blk == 1) { flip_bit(b.r, t); return true; }
+    if (t >= T - 1) return false;
+    uint32_t (&z)[kWords] = (blk == 2) ? b.m : b.r;
+    if (test_bit(z, t) == test_bit(z, t + 1)) return false;
+    flip_bit(z, t);
+    flip_bit(z, t + 1);
+    return true;
+}
+
+// Exact cost of one product's pattern (kInf when infeasible).  row points at the product's (D, PR) pairs;
+// it may be an LDS or a global pointer (after inlining the address space is known).
+template <class RowPtr>
+__device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T, const ProdParams &pp) {
+    int32_t lim = 0, XR = 0, lsR = 0, lastM = 0, A1 = 0, A2 = 0;
+    int32_t nolast = -1, bad = 0;
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) {
+        if (32 * j >= T) break;
+        const uint32_t m = b.m[j], r = b.r[j];
+        const int nb = min(32, T - 32 * j);
+        for (int q = 0; q < nb; ++q) {
+            const int tau = 32 * j + q;
+            const int2 dp = row[tau];
+            const int32_t sm = __builtin_amdgcn_sbfe((int32_t)m, q, 1);   // 0 or -1
+            const int32_t sr = __builtin_amdgcn_sbfe((int32_t)r, q, 1);
+            lim = sel(sm, XR, lim);        // a manufacturing setup closes the remanufacturing capacity
+            lastM = sel(sm, tau, lastM);
+            nolast &= ~sm;
+            lim = sel(sr, dp.y, lim);      // a remanufacturing setup may use every return so far
+            lsR = sel(sr, tau, lsR);
+            const int32_t xn = min(XR + dp.x, lim);
+            const int32_t u = xn - XR;     // units remanufactured at lsR for period tau
+            XR = xn;
+            A1 += (int32_t)__umul24((uint32_t)u, (uint32_t)lsR);
+            const int32_t rr = dp.x - u;   // units manufactured at lastM for period tau
+            A2 += (int32_t)__umul24((uint32_t)rr, (uint32_t)lastM);
+            bad |= rr & nolast;            // demand with no manufacturing setup at or before it
+        }
+    }
+    if (bad) return kInf;
+    int32_t nM = 0, nR = 0;
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) {
+        nM += __popc(b.m[j]);
+        nR += __popc(b.r[j]);
+    }
+    return (int64_t)pp.kM * nM + (int64_t)pp.kR * nR + (int64_t)pp.hM * (pp.S_tD - (int64_t)A1 - (int64_t)A2) +
+           (int64_t)pp.hR * (pp.S_PR - (int64_t)T * XR + (int64_t)A1);
+}
+
+// Feasibility of a pattern: only the periods before the first manufacturing setup can fail (afterwards
+// every shortfall is made by a manufacturing lot).  Uniform use by a whole wave.
+template <class RowPtr>
+__device__ __forceinline__ bool feasible(const Bits &b, RowPtr row, int T) {
+    int32_t lim = 0, XR = 0;
+    for (int tau = 0; tau < T; ++tau) {
+        const int j = tau >> 5, q = tau & 31;
+        uint32_t m = 0, r = 0;
+#pragma unroll
+        for (int w = 0; w < kWords; ++w) {
+            m = (w == j) ? b.m[w] : m;
+            r = (w == j) ? b.r[w] : r;
+        }
+        if ((m >> q) & 1u) return true;
+        const int2 dp = row[tau];
+        if ((r >> q) & 1u) lim = dp.y;
+        const int32_t xn = min(XR + dp.x, lim);
+        if (dp.x - (xn - XR) > 0) return false;
+        XR = xn;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds, each two 64x64 -> 128-bit products with
+// the published multipliers, the key advanced by the published Weyl increments.  Returns word 0.
+// ---------------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t philox_word0(uint64_t key0, uint64_t key1, uint64_t c0, uint64_t c1,
+                                                 uint64_t c2, uint64_t c3) {
+    constexpr uint64_t kMulA = 0xD2E7470EE14C6C93ull, kMulB = 0xCA5A826395121157ull;
+    constexpr uint64_t kWeylA = 0x9E3779B97F4A7C15ull, kWeylB = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t hiA = __umul64hi(kMulA, c0), loA = kMulA * c0;
+        const uint64_t hiB = __umul64hi(kMulB, c2), loB = kMulB * c2;
+        const uint64_t n0 = hiB ^ c1 ^ key0;
+        const uint64_t n2 = hiA ^ c3 ^ key1;
+        c0 = n0;
+        c1 = loB;
+        c2 = n2;
+        c3 = loA;
+        key0 += kWeylA;
+        key1 += kWeylB;
+    }
+    return c0;
+}
+
+// Index in [0, n) of draw j of iteration it for the chain keyed (seed, chain): multiply-shift of the high
+// 32 bits of Philox word 0.
+__device__ __forceinline__ uint32_t shake_draw(uint64_t seed, uint64_t chain, uint64_t it, uint64_t j, uint64_t n) {
+    const uint64_t w = philox_word0(seed, chain, it, j, 0, 0);
+    return (uint32_t)(((w >> 32) * n) >> 32);
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Wave reductions (64 lanes).
+// ---------------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace vns

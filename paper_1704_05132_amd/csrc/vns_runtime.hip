@@ -1,0 +1,647 @@
+// Host runtime of the lot-sizing VNS: the C ABI declared in include/vns.h.
+//
+// A context owns, for its whole life, every array of the search in device memory (instance rows, product
+// parameters, current and working solutions of every chain, costs, records); calls move only their
+// arguments and results across PCIe.  All work is queued on one stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "vns.h"
+#include "vns_launch.hpp"
+#include "vns_types.hpp"
+
+using namespace vns;
+
+static_assert(sizeof(Record) == sizeof(vns_record), "record layout");
+static_assert(sizeof(Bits) == 32, "bits layout");
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct vns_ctx {
+    // instance data (host)
+    int32_t n_inst = 0;
+    std::vector<int32_t> K, T, prod0;
+    int64_t n_prod = 0;
+    uint64_t seed = 0;
+    int device = 0;
+
+    // options
+    int64_t chains_per_inst = 1;
+    int32_t kmax = 5;
+    uint32_t nb_list = 0x421;
+    int32_t n_nb = 3;
+    int32_t trace = 1;
+    int32_t run_waves = 8;
+
+    // chains (host mirror)
+    std::vector<ChainInfo> chains;
+    std::vector<int64_t> price_off;
+    int64_t total_cp = 0;
+    int64_t total_slots = 0;
+
+    // device arrays
+    int2 *d_rows = nullptr;
+    ProdParams *d_prod = nullptr;
+    ChainInfo *d_chains = nullptr;
+    int32_t *d_cp_chain = nullptr;
+    int64_t *d_price_off = nullptr;
+    Bits *d_cur = nullptr, *d_work = nullptr;
+    int64_t *d_cur_cost = nullptr, *d_work_cost = nullptr;
+    ChainState *d_cs = nullptr;
+    uint64_t *d_prod_key = nullptr;
+    int64_t *d_prod_price = nullptr;
+    int32_t *d_prod_slot = nullptr;
+    int64_t *d_best = nullptr;
+    int32_t *d_best_slot = nullptr;
+    unsigned long long *d_evals = nullptr;
+    int64_t *d_slot_price = nullptr;
+    size_t slot_price_cap = 0;
+    Record *d_trace = nullptr;
+    size_t trace_cap = 0;
+    int32_t trace_iters = 0;
+
+    hipStream_t own_stream = nullptr, stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    // progress and stats
+    int64_t iteration = 0;
+    vns_stats stats{};
+
+    std::string err;
+    bool dead = false;
+};
+
+// ---------------------------------------------------------------------------------------------------
+// error helpers
+// ---------------------------------------------------------------------------------------------------
+static vns_status fail(vns_ctx *c, vns_status s, const std::string &msg) {
+    if (c) {
+        c->err = msg;
+        if (s == VNS_EDEVICE) c->dead = true;
+    } else {
+        g_create_error = msg;
+    }
+    return s;
+}
+
+static vns_status hip_fail(vns_ctx *c, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return fail(c, VNS_ENOMEM, m);
+    return fail(c, VNS_EDEVICE, m);
+}
+
+#define VNS_HIP(ctx, expr)                                          \
+    do {                                                            \
+        hipError_t e_ = (expr);                                     \
+        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);    \
+    } while (0)
+
+#define VNS_LIVE(ctx)                                                                          \
+    do {                                                                                       \
+        if (!(ctx)) return fail(nullptr, VNS_EINVAL, "null context");                          \
+        if ((ctx)->dead) return fail((ctx), VNS_ESTATE, "context is dead after a device error"); \
+        VNS_HIP((ctx), hipSetDevice((ctx)->device));                                          \
+    } while (0)
+
+template <class T>
+static hipError_t dmalloc(T **p, size_t n) {
+    *p = nullptr;
+    if (n == 0) n = 1;
+    return hipMalloc((void **)p, n * sizeof(T));
+}
+
+template <class T>
+static void dfree(T *&p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+static void free_chains(vns_ctx *c) {
+    dfree(c->d_chains);
+    dfree(c->d_cp_chain);
+    dfree(c->d_price_off);
+    dfree(c->d_cur);
+    dfree(c->d_work);
+    dfree(c->d_cur_cost);
+    dfree(c->d_work_cost);
+    dfree(c->d_cs);
+    dfree(c->d_prod_key);
+    dfree(c->d_prod_price);
+    dfree(c->d_prod_slot);
+    dfree(c->d_best);
+    dfree(c->d_best_slot);
+    dfree(c->d_slot_price);
+    c->slot_price_cap = 0;
+    dfree(c->d_trace);
+    c->trace_cap = 0;
+    c->trace_iters = 0;
+}
+
+static void free_all(vns_ctx *c) {
+    free_chains(c);
+    dfree(c->d_rows);
+    dfree(c->d_prod);
+    dfree(c->d_evals);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    c->ev0 = c->ev1 = nullptr;
+    c->own_stream = c->stream = nullptr;
+}
+
+// Initial solution of every chain: manufacture in every period (always feasible).
+static Bits initial_bits(int T) {
+    Bits b{};
+    for (int t = 0; t < T; ++t) b.m[t >> 5] |= 1u << (t & 31);
+    return b;
+}
+
+// (Re)build the chain arrays for chains_per_inst chains per instance and reset every chain.
+static vns_status setup_chains(vns_ctx *c) {
+    free_chains(c);
+    const int64_t G = (int64_t)c->n_inst * c->chains_per_inst;
+    if (G > (int64_t)INT32_MAX) return fail(c, VNS_EINVAL, "too many chains");
+    c->chains.assign((size_t)G, ChainInfo{});
+    c->price_off.assign((size_t)G, 0);
+    int64_t cp = 0, slots = 0;
+    for (int32_t i = 0; i < c->n_inst; ++i) {
+        for (int64_t j = 0; j < c->chains_per_inst; ++j) {
+            const int64_t g = (int64_t)i * c->chains_per_inst + j;
+            ChainInfo &ci = c->chains[(size_t)g];
+            ci.inst = i;
+            ci.K = c->K[(size_t)i];
+            ci.T = c->T[(size_t)i];
+            ci.prod0 = c->prod0[(size_t)i];
+            ci.cp0 = cp;
+            c->price_off[(size_t)g] = slots;
+            cp += ci.K;
+            slots += 4LL * ci.K * ci.T;
+        }
+    }
+    c->total_cp = cp;
+    c->total_slots = slots;
+    std::vector<int32_t> cp_chain((size_t)cp);
+    std::vector<Bits> bits((size_t)cp);
+    for (int64_t g = 0; g < G; ++g) {
+        const ChainInfo &ci = c->chains[(size_t)g];
+        const Bits b0 = initial_bits(ci.T);
+        for (int32_t p = 0; p < ci.K; ++p) {
+            cp_chain[(size_t)(ci.cp0 + p)] = (int32_t)g;
+            bits[(size_t)(ci.cp0 + p)] = b0;
+        }
+    }
+    VNS_HIP(c, dmalloc(&c->d_chains, (size_t)G));
+    VNS_HIP(c, dmalloc(&c->d_cp_chain, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_price_off, (size_t)G));
+    VNS_HIP(c, dmalloc(&c->d_cur, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_work, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_cur_cost, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_work_cost, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_cs, (size_t)G));
+    VNS_HIP(c, dmalloc(&c->d_prod_key, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_prod_price, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_prod_slot, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_best, (size_t)G));
+    VNS_HIP(c, dmalloc(&c->d_best_slot, (size_t)G));
+    VNS_HIP(c, hipMemcpyAsync(c->d_chains, c->chains.data(), sizeof(ChainInfo) * (size_t)G, hipMemcpyHostToDevice, c->stream));
+    VNS_HIP(c, hipMemcpyAsync(c->d_cp_chain, cp_chain.data(), sizeof(int32_t) * (size_t)cp, hipMemcpyHostToDevice, c->stream));
+    VNS_HIP(c, hipMemcpyAsync(c->d_price_off, c->price_off.data(), sizeof(int64_t) * (size_t)G, hipMemcpyHostToDevice, c->stream));
+    VNS_HIP(c, hipMemcpyAsync(c->d_cur, bits.data(), sizeof(Bits) * (size_t)cp, hipMemcpyHostToDevice, c->stream));
+    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs, 0};
+    VNS_HIP(c, launch_init(ia, (int)G, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    c->iteration = 0;
+    c->stats = vns_stats{};
+    return VNS_OK;
+}
+
+static vns_status check_chain(vns_ctx *c, int32_t chain) {
+    if (chain < 0 || (size_t)chain >= c->chains.size()) return fail(c, VNS_EINVAL, "chain index out of range");
+    return VNS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// creation
+// ---------------------------------------------------------------------------------------------------
+extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const int32_t *T, const int32_t *D,
+                                       const int32_t *R, const int32_t *kM, const int32_t *kR, const int32_t *hM,
+                                       const int32_t *hR, uint64_t seed, vns_ctx **out) {
+    if (!out) return fail(nullptr, VNS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_inst < 1) return fail(nullptr, VNS_EINVAL, "n_inst must be >= 1");
+    if (!K || !T || !D || !R || !kM || !kR || !hM || !hR) return fail(nullptr, VNS_EINVAL, "NULL input array");
+    int64_t n_prod = 0, n_rows = 0;
+    for (int32_t i = 0; i < n_inst; ++i) {
+        if (K[i] < 1 || K[i] > VNS_K_MAX) return fail(nullptr, VNS_EINVAL, "K out of range");
+        if (T[i] < 1 || T[i] > VNS_T_MAX) return fail(nullptr, VNS_EINVAL, "T out of range");
+        n_prod += K[i];
+        n_rows += (int64_t)K[i] * T[i];
+    }
+    if (n_prod > (int64_t)INT32_MAX / 2) return fail(nullptr, VNS_EINVAL, "too many products");
+    if (n_rows * 4 > (int64_t)INT32_MAX) return fail(nullptr, VNS_EINVAL, "too many periods in total");
+
+    std::vector<int2> rows((size_t)n_rows);
+    std::vector<ProdParams> prod((size_t)n_prod);
+    std::vector<int32_t> prod0((size_t)n_inst);
+    int64_t p = 0, r = 0;
+    for (int32_t i = 0; i < n_inst; ++i) {
+        prod0[(size_t)i] = (int32_t)p;
+        __int128 F_bound = 0;
+        for (int32_t k = 0; k < K[i]; ++k, ++p) {
+            const int Ti = T[i];
+            if (kM[p] < 0 || kR[p] < 0 || hM[p] < 0 || hR[p] < 0)
+                return fail(nullptr, VNS_EINVAL, "negative cost");
+            int64_t sumD = 0, sumR = 0, maxD = 0, S_tD = 0, S_PR = 0;
+            for (int t = 0; t < Ti; ++t) {
+                const int64_t d = D[r + t], q = R[r + t];
+                if (d < 0 || q < 0) return fail(nullptr, VNS_EINVAL, "negative demand or returns");
+                if (d >= (1 << 24) || q >= (1 << 24)) return fail(nullptr, VNS_ERANGE, "demand or returns >= 2^24");
+                sumD += d;
+                sumR += q;
+                maxD = std::max(maxD, d);
+                S_tD += (int64_t)t * d;
+                S_PR += sumR;
+                rows[(size_t)(r + t)] = make_int2((int)d, (int)sumR);
+            }
+            // int32 accumulators of the forward decode: A2 <= sum D * (T-1), A1 <= sum R * (T-1),
+            // XR + D <= sum R + max D.
+            if (sumD * Ti >= (1LL << 31) || sumR * Ti >= (1LL << 31) || sumR + maxD >= (1LL << 31))
+                return fail(nullptr, VNS_ERANGE, "a product's demand or returns over the horizon are too large");
+            const __int128 bound = (__int128)Ti * ((__int128)kM[p] + kR[p]) + (__int128)hM[p] * sumD * Ti +
+                                   (__int128)hR[p] * sumR * Ti;
+            if (bound >= ((__int128)1 << 47)) return fail(nullptr, VNS_ERANGE, "a product's cost could reach 2^47");
+            F_bound += bound;
+            ProdParams &pp = prod[(size_t)p];
+            pp.kM = kM[p];
+            pp.kR = kR[p];
+            pp.hM = hM[p];
+            pp.hR = hR[p];
+            pp.S_tD = S_tD;
+            pp.S_PR = S_PR;
+            pp.T = Ti;
+            pp.row = (int32_t)r;
+            r += Ti;
+        }
+        if (F_bound >= ((__int128)1 << 62)) return fail(nullptr, VNS_ERANGE, "an instance's objective could reach 2^62");
+    }
+
+    vns_ctx *c = new (std::nothrow) vns_ctx();
+    if (!c) return fail(nullptr, VNS_ENOMEM, "host allocation failed");
+    c->n_inst = n_inst;
+    c->K.assign(K, K + n_inst);
+    c->T.assign(T, T + n_inst);
+    c->prod0 = prod0;
+    c->n_prod = n_prod;
+    c->seed = seed;
+    vns_status st = VNS_OK;
+    auto bail = [&](vns_status s) {
+        g_create_error = c->err;
+        free_all(c);
+        delete c;
+        return s;
+    };
+#define VNS_CREATE_HIP(expr)                                     \
+    do {                                                         \
+        hipError_t e_ = (expr);                                  \
+        if (e_ != hipSuccess) return bail(hip_fail(c, e_, #expr)); \
+    } while (0)
+    VNS_CREATE_HIP(hipGetDevice(&c->device));
+    VNS_CREATE_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+    c->stream = c->own_stream;
+    VNS_CREATE_HIP(hipEventCreate(&c->ev0));
+    VNS_CREATE_HIP(hipEventCreate(&c->ev1));
+    VNS_CREATE_HIP(dmalloc(&c->d_rows, (size_t)n_rows));
+    VNS_CREATE_HIP(dmalloc(&c->d_prod, (size_t)n_prod));
+    VNS_CREATE_HIP(dmalloc(&c->d_evals, 1));
+    VNS_CREATE_HIP(hipMemcpyAsync(c->d_rows, rows.data(), sizeof(int2) * (size_t)n_rows, hipMemcpyHostToDevice, c->stream));
+    VNS_CREATE_HIP(hipMemcpyAsync(c->d_prod, prod.data(), sizeof(ProdParams) * (size_t)n_prod, hipMemcpyHostToDevice, c->stream));
+#undef VNS_CREATE_HIP
+    st = setup_chains(c);
+    if (st != VNS_OK) return bail(st);
+    *out = c;
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_create(int32_t K, int32_t T, const int32_t *D, const int32_t *R, const int32_t *kM,
+                                 const int32_t *kR, const int32_t *hM, const int32_t *hR, uint64_t seed, vns_ctx **out) {
+    return vns_create_batch(1, &K, &T, D, R, kM, kR, hM, hR, seed, out);
+}
+
+extern "C" void vns_destroy(vns_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (!c->dead && c->stream) (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// options
+// ---------------------------------------------------------------------------------------------------
+extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
+    VNS_LIVE(c);
+    switch (key) {
+        case VNS_OPT_CHAINS:
+            if (v < 1 || v > 65536) return fail(c, VNS_EINVAL, "chains out of range");
+            c->chains_per_inst = v;
+            return setup_chains(c);
+        case VNS_OPT_KMAX:
+            if (v < 1 || v > VNS_KSHAKE_MAX) return fail(c, VNS_EINVAL, "k_max out of range");
+            c->kmax = (int32_t)v;
+            return VNS_OK;
+        case VNS_OPT_NB_LIST: {
+            int n = 0;
+            uint64_t x = (uint64_t)v;
+            if (v <= 0 || x > 0xFFFFu) return fail(c, VNS_EINVAL, "neighbourhood list out of range");
+            while (x) {
+                const uint64_t nb = x & 0xF;
+                if (nb != VNS_NB_FLIP_M && nb != VNS_NB_FLIP_R && nb != VNS_NB_SHIFT)
+                    return fail(c, VNS_EINVAL, "unknown neighbourhood id in list");
+                ++n;
+                x >>= 4;
+            }
+            c->nb_list = (uint32_t)v;
+            c->n_nb = n;
+            return VNS_OK;
+        }
+        case VNS_OPT_TRACE:
+            if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "trace must be 0 or 1");
+            c->trace = (int32_t)v;
+            return VNS_OK;
+        case VNS_OPT_RUN_WAVES:
+            if (v < 1 || v > kMaxWaves) return fail(c, VNS_EINVAL, "run waves out of range");
+            c->run_waves = (int32_t)v;
+            return VNS_OK;
+        default:
+            return fail(c, VNS_EINVAL, "unknown option");
+    }
+}
+
+extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) {
+    if (!c || !v) return fail(nullptr, VNS_EINVAL, "null argument");
+    switch (key) {
+        case VNS_OPT_CHAINS: *v = c->chains_per_inst; return VNS_OK;
+        case VNS_OPT_KMAX: *v = c->kmax; return VNS_OK;
+        case VNS_OPT_NB_LIST: *v = c->nb_list; return VNS_OK;
+        case VNS_OPT_TRACE: *v = c->trace; return VNS_OK;
+        case VNS_OPT_RUN_WAVES: *v = c->run_waves; return VNS_OK;
+        default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
+    }
+}
+
+extern "C" vns_status vns_bind_stream(vns_ctx *c, void *s) {
+    VNS_LIVE(c);
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    c->stream = s ? (hipStream_t)s : c->own_stream;
+    return VNS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// pricing
+// ---------------------------------------------------------------------------------------------------
+extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32_t chain, int64_t *slot_price,
+                                             int64_t *prod_best, int32_t *prod_best_slot, int64_t *best,
+                                             int32_t *best_slot) {
+    VNS_LIVE(c);
+    if (nb_mask == 0 || (nb_mask & ~7u)) return fail(c, VNS_EINVAL, "bad neighbourhood mask");
+    int32_t g0, ng;
+    if (chain == VNS_ALL_CHAINS) {
+        g0 = 0;
+        ng = (int32_t)c->chains.size();
+    } else {
+        vns_status s = check_chain(c, chain);
+        if (s != VNS_OK) return s;
+        g0 = chain;
+        ng = 1;
+    }
+    const ChainInfo &first = c->chains[(size_t)g0];
+    const ChainInfo &last = c->chains[(size_t)(g0 + ng - 1)];
+    const int64_t cp_begin = first.cp0, n_cp = last.cp0 + last.K - first.cp0;
+    const int64_t slot_begin = c->price_off[(size_t)g0];
+    const int64_t n_slots = c->price_off[(size_t)(g0 + ng - 1)] + 4LL * last.K * last.T - slot_begin;
+    if (slot_price && (size_t)n_slots > c->slot_price_cap) {
+        dfree(c->d_slot_price);
+        c->slot_price_cap = 0;
+        VNS_HIP(c, dmalloc(&c->d_slot_price, (size_t)n_slots));
+        c->slot_price_cap = (size_t)n_slots;
+    }
+    EvalArgs ea{};
+    ea.chains = c->d_chains;
+    ea.prod = c->d_prod;
+    ea.rows = c->d_rows;
+    ea.cur = c->d_cur;
+    ea.cur_cost = c->d_cur_cost;
+    ea.cstate = c->d_cs;
+    ea.slot_price = slot_price ? c->d_slot_price - slot_begin : nullptr;
+    ea.price_off = c->d_price_off;
+    ea.prod_key = c->d_prod_key;
+    ea.evals = c->d_evals;
+    ea.nb_mask = nb_mask;
+    ea.chain0 = g0;
+    VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long), c->stream));
+    VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
+    VNS_HIP(c, launch_eval(ea, cp_begin, n_cp, c->d_cp_chain, c->stream));
+    VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
+    ChainBestArgs cb{c->d_chains, c->d_cs, c->d_cur_cost, c->d_prod_key, c->d_prod_price, c->d_prod_slot,
+                     c->d_best, c->d_best_slot, g0};
+    VNS_HIP(c, launch_chain_best(cb, ng, c->stream));
+    if (slot_price)
+        VNS_HIP(c, hipMemcpyAsync(slot_price, c->d_slot_price, sizeof(int64_t) * (size_t)n_slots, hipMemcpyDeviceToHost, c->stream));
+    if (prod_best)
+        VNS_HIP(c, hipMemcpyAsync(prod_best, c->d_prod_price + cp_begin, sizeof(int64_t) * (size_t)n_cp, hipMemcpyDeviceToHost, c->stream));
+    if (prod_best_slot)
+        VNS_HIP(c, hipMemcpyAsync(prod_best_slot, c->d_prod_slot + cp_begin, sizeof(int32_t) * (size_t)n_cp, hipMemcpyDeviceToHost, c->stream));
+    if (best) VNS_HIP(c, hipMemcpyAsync(best, c->d_best, sizeof(int64_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
+    if (best_slot)
+        VNS_HIP(c, hipMemcpyAsync(best_slot, c->d_best_slot, sizeof(int32_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
+    unsigned long long ev = 0;
+    VNS_HIP(c, hipMemcpyAsync(&ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->stats.last_eval_evals = (int64_t)ev;
+    c->stats.last_eval_ms = ms;
+    return VNS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// search
+// ---------------------------------------------------------------------------------------------------
+extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
+    VNS_LIVE(c);
+    if (iters < 0) return fail(c, VNS_EINVAL, "iters must be >= 0");
+    if (c->iteration + iters > (int64_t)INT32_MAX) return fail(c, VNS_ERANGE, "iteration counter would overflow");
+    if (iters == 0) return VNS_OK;
+    const int64_t G = (int64_t)c->chains.size();
+    if (c->trace) {
+        const size_t need = (size_t)G * (size_t)iters;
+        if (need > c->trace_cap) {
+            dfree(c->d_trace);
+            c->trace_cap = 0;
+            VNS_HIP(c, dmalloc(&c->d_trace, need));
+            c->trace_cap = need;
+        }
+        c->trace_iters = iters;
+    } else {
+        c->trace_iters = 0;
+    }
+    RunArgs ra{};
+    ra.chains = c->d_chains;
+    ra.prod = c->d_prod;
+    ra.rows = c->d_rows;
+    ra.cur = c->d_cur;
+    ra.cur_cost = c->d_cur_cost;
+    ra.work = c->d_work;
+    ra.work_cost = c->d_work_cost;
+    ra.cstate = c->d_cs;
+    ra.trace = c->trace ? c->d_trace : nullptr;
+    ra.seed = c->seed;
+    ra.it0 = c->iteration;
+    ra.iters = iters;
+    ra.kmax = c->kmax;
+    ra.nb_list = c->nb_list;
+    ra.n_nb = c->n_nb;
+    VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
+    VNS_HIP(c, launch_run(ra, (int)G, c->run_waves, c->stream));
+    VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
+    std::vector<ChainState> cs((size_t)G);
+    VNS_HIP(c, hipMemcpyAsync(cs.data(), c->d_cs, sizeof(ChainState) * (size_t)G, hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    int64_t ev = 0;
+    int32_t err = 0;
+    for (const ChainState &s : cs) {
+        ev += s.evals;
+        err |= s.err;
+    }
+    if (err) return fail(c, VNS_EDEVICE, "a VND exceeded its pass guard (inconsistent costs)");
+    c->iteration += iters;
+    c->stats.iterations = c->iteration;
+    c->stats.last_run_evals = ev;
+    c->stats.move_evals += ev;
+    c->stats.last_run_ms = ms;
+    return VNS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// state access
+// ---------------------------------------------------------------------------------------------------
+extern "C" vns_status vns_get_cost(vns_ctx *c, int32_t chain, int64_t *F, int64_t *F_best) {
+    VNS_LIVE(c);
+    vns_status s = check_chain(c, chain);
+    if (s != VNS_OK) return s;
+    ChainState cs;
+    VNS_HIP(c, hipMemcpyAsync(&cs, c->d_cs + chain, sizeof(cs), hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    if (F) *F = cs.F;
+    if (F_best) *F_best = cs.F_best;
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_get_solution(vns_ctx *c, int32_t chain, uint8_t *zM, uint8_t *zR) {
+    VNS_LIVE(c);
+    vns_status s = check_chain(c, chain);
+    if (s != VNS_OK) return s;
+    if (!zM || !zR) return fail(c, VNS_EINVAL, "NULL output");
+    const ChainInfo &ci = c->chains[(size_t)chain];
+    std::vector<Bits> b((size_t)ci.K);
+    VNS_HIP(c, hipMemcpyAsync(b.data(), c->d_cur + ci.cp0, sizeof(Bits) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    for (int32_t k = 0; k < ci.K; ++k)
+        for (int32_t t = 0; t < ci.T; ++t) {
+            zM[(size_t)k * ci.T + t] = (uint8_t)((b[(size_t)k].m[t >> 5] >> (t & 31)) & 1u);
+            zR[(size_t)k * ci.T + t] = (uint8_t)((b[(size_t)k].r[t >> 5] >> (t & 31)) & 1u);
+        }
+    return VNS_OK;
+}
+
+static vns_status reinit_chain(vns_ctx *c, int32_t chain) {
+    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs, chain};
+    VNS_HIP(c, launch_init(ia, 1, c->stream));
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_set_solution(vns_ctx *c, int32_t chain, const uint8_t *zM, const uint8_t *zR) {
+    VNS_LIVE(c);
+    vns_status s = check_chain(c, chain);
+    if (s != VNS_OK) return s;
+    if (!zM || !zR) return fail(c, VNS_EINVAL, "NULL input");
+    const ChainInfo &ci = c->chains[(size_t)chain];
+    std::vector<Bits> nb((size_t)ci.K), old((size_t)ci.K);
+    for (int32_t k = 0; k < ci.K; ++k) {
+        Bits b{};
+        for (int32_t t = 0; t < ci.T; ++t) {
+            if (zM[(size_t)k * ci.T + t]) b.m[t >> 5] |= 1u << (t & 31);
+            if (zR[(size_t)k * ci.T + t]) b.r[t >> 5] |= 1u << (t & 31);
+        }
+        nb[(size_t)k] = b;
+    }
+    VNS_HIP(c, hipMemcpyAsync(old.data(), c->d_cur + ci.cp0, sizeof(Bits) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    VNS_HIP(c, hipMemcpyAsync(c->d_cur + ci.cp0, nb.data(), sizeof(Bits) * (size_t)ci.K, hipMemcpyHostToDevice, c->stream));
+    s = reinit_chain(c, chain);
+    if (s != VNS_OK) return s;
+    ChainState cs;
+    VNS_HIP(c, hipMemcpyAsync(&cs, c->d_cs + chain, sizeof(cs), hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    if (cs.F == kInf) {
+        VNS_HIP(c, hipMemcpyAsync(c->d_cur + ci.cp0, old.data(), sizeof(Bits) * (size_t)ci.K, hipMemcpyHostToDevice, c->stream));
+        s = reinit_chain(c, chain);
+        if (s != VNS_OK) return s;
+        VNS_HIP(c, hipStreamSynchronize(c->stream));
+        return fail(c, VNS_ERANGE, "the solution leaves a product infeasible");
+    }
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_get_trajectory(vns_ctx *c, int32_t chain, vns_record *rec, int64_t cap, int64_t *n) {
+    VNS_LIVE(c);
+    vns_status s = check_chain(c, chain);
+    if (s != VNS_OK) return s;
+    const int64_t avail = c->trace_iters;
+    if (n) *n = avail;
+    const int64_t m = std::min<int64_t>(avail, cap < 0 ? 0 : cap);
+    if (rec && m > 0) {
+        VNS_HIP(c, hipMemcpyAsync(rec, c->d_trace + (int64_t)chain * c->trace_iters, sizeof(vns_record) * (size_t)m,
+                                  hipMemcpyDeviceToHost, c->stream));
+        VNS_HIP(c, hipStreamSynchronize(c->stream));
+    }
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_get_stats(const vns_ctx *c, vns_stats *out) {
+    if (!c || !out) return fail(nullptr, VNS_EINVAL, "null argument");
+    *out = c->stats;
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_instance_size(const vns_ctx *c, int32_t inst, int32_t *K, int32_t *T) {
+    if (!c) return fail(nullptr, VNS_EINVAL, "null context");
+    if (inst < 0 || inst >= c->n_inst) return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "instance out of range");
+    if (K) *K = c->K[(size_t)inst];
+    if (T) *T = c->T[(size_t)inst];
+    return VNS_OK;
+}
+
+extern "C" int64_t vns_num_chains(const vns_ctx *c) { return c ? (int64_t)c->chains.size() : 0; }
+
+extern "C" const char *vns_last_error(const vns_ctx *c) {
+    return c ? c->err.c_str() : g_create_error.c_str();
+}

@@ -1,0 +1,96 @@
+// Data layout shared by the host runtime and the kernels of the lot-sizing VNS.
+//
+// Everything lives in HBM for the whole life of a context (the paper's Section 3 notes that keeping the
+// data on the device, instead of copying it per VND call, is what made the GPU version pay off).
+//
+//   rows      int2 [sum over products of T]   (D(t), PR(t)) per period, PR = returns up to and including t
+//   prod      ProdParams [P]                  per product of every instance (costs, row offset, sums)
+//   chains    ChainInfo [G]                   per chain: its instance and where its products start
+//   cur/work  Bits [sum over chains of K]     32-byte setup record per (chain, product): the current
+//                                             solution x and the working copy x' / x'' of the search
+//   cur_cost/work_cost int64 [same]           exact cost of each (chain, product)
+//   cstate    ChainState [G]                  objective, best, shake size, counters
+#pragma once
+#include <stdint.h>
+
+namespace vns {
+
+constexpr int kWords = 4;          // 32-bit words per setup row: T <= 128
+constexpr int kTMax = 32 * kWords;
+constexpr int kShakeMax = 64;
+constexpr int kMaxWaves = 16;
+constexpr int kMaxPasses = 1 << 16;  // VND passes per product and iteration: a guard, not a limit of the method
+constexpr int64_t kInf = INT64_MAX;
+constexpr uint64_t kInfKey = ~0ull;
+constexpr int kSlotBits = 16;      // argmin key = cost << 16 | local slot; cost < 2^47 is checked at create
+
+struct Bits {
+    uint32_t m[kWords];   // zM, bit t of word t/32
+    uint32_t r[kWords];   // zR
+};
+
+struct ProdParams {
+    int32_t kM, kR, hM, hR;
+    int64_t S_tD;   // sum_t t * D(t)
+    int64_t S_PR;   // sum_t PR(t)
+    int32_t T;
+    int32_t row;    // offset of the product's first period in rows
+};
+
+struct ChainInfo {
+    int32_t inst;
+    int32_t K;
+    int32_t T;
+    int32_t prod0;  // global index of product 0 of the chain's instance
+    int64_t cp0;    // index of the chain's product 0 in the cur/work arrays
+};
+
+struct ChainState {
+    int64_t F;
+    int64_t F_best;
+    int64_t evals;  // move-evaluations of this chain during the last run
+    int32_t k;      // shake size for the next iteration
+    int32_t lopt;   // 1 when every product of x is known to be a VND local optimum
+    int32_t err;    // nonzero if a VND exceeded kMaxPasses (cannot happen with a consistent decode)
+    int32_t pad;
+};
+
+struct Record {    // identical layout to vns_record
+    int32_t iter, k, accepted, pad;
+    int64_t F_shaken, F_local, F_best;
+};
+
+struct RunArgs {
+    const ChainInfo *chains;
+    const ProdParams *prod;
+    const int2 *rows;
+    Bits *cur;
+    int64_t *cur_cost;
+    Bits *work;
+    int64_t *work_cost;
+    ChainState *cstate;
+    Record *trace;          // [G][iters] or nullptr
+    uint64_t seed;
+    int64_t it0;
+    int32_t iters;
+    int32_t kmax;
+    uint32_t nb_list;       // one neighbourhood id per nibble
+    int32_t n_nb;
+};
+
+struct EvalArgs {
+    const ChainInfo *chains;
+    const ProdParams *prod;
+    const int2 *rows;
+    const Bits *cur;
+    const int64_t *cur_cost;
+    const ChainState *cstate;
+    int64_t *slot_price;         // optional [sum over chains of 4*K*T]
+    const int64_t *price_off;    // [G] offset of each chain's slot block in slot_price
+    uint64_t *prod_key;          // [sum over chains of K]: cost << 16 | slot of each product's best move
+    unsigned long long *evals;   // device counter of move-evaluations
+    uint32_t nb_mask;
+    int32_t chain0;              // first chain of the launch
+};
+
+}  // namespace vns
