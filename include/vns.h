@@ -63,7 +63,9 @@ enum vns_option {
     VNS_OPT_NB_LIST = 3,  /* VND neighbourhood order, one id per 4-bit nibble, lowest nibble first,
                              up to 4 entries (default 0x421 = flip zM, flip zR, shift)                   */
     VNS_OPT_TRACE = 4,    /* 1 = vns_run keeps one record per chain and iteration (default 1)           */
-    VNS_OPT_RUN_WAVES = 5 /* wavefronts per workgroup of the search kernel, 1..16 (default 8)           */
+    VNS_OPT_RUN_WAVES = 5, /* wavefronts per workgroup of the search kernel, 1..8 (default 8)           */
+    VNS_OPT_EVAL_GROUP = 6 /* chains of one instance priced together by one pricing workgroup, 1..16
+                              (default 4); a tuning knob, results do not depend on it                   */
 };
 
 /* One GVNS iteration of one chain. */

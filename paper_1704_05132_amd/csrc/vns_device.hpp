@@ -56,45 +56,63 @@ __device__ __forceinline__ bool apply_move(Bits &b, int l, int T) {
     return true;
 }
 
-// Exact cost of one product's pattern (kInf when infeasible).  row points at the product's (D, PR) pairs;
-// it may be an LDS or a global pointer (after inlining the address space is known).
-template <class RowPtr>
-__device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T, const ProdParams &pp) {
+// State of the forward decode of one pattern (one lane).
+struct DecodeState {
     int32_t lim = 0, XR = 0, lsR = 0, lastM = 0, A1 = 0, A2 = 0;
     int32_t nolast = -1, bad = 0;
-#pragma unroll
-    for (int j = 0; j < kWords; ++j) {
-        if (32 * j >= T) break;
-        const uint32_t m = b.m[j], r = b.r[j];
-        const int nb = min(32, T - 32 * j);
-        for (int q = 0; q < nb; ++q) {
-            const int tau = 32 * j + q;
-            const int2 dp = row[tau];
-            const int32_t sm = __builtin_amdgcn_sbfe((int32_t)m, q, 1);   // 0 or -1
-            const int32_t sr = __builtin_amdgcn_sbfe((int32_t)r, q, 1);
-            lim = sel(sm, XR, lim);        // a manufacturing setup closes the remanufacturing capacity
-            lastM = sel(sm, tau, lastM);
-            nolast &= ~sm;
-            lim = sel(sr, dp.y, lim);      // a remanufacturing setup may use every return so far
-            lsR = sel(sr, tau, lsR);
-            const int32_t xn = min(XR + dp.x, lim);
-            const int32_t u = xn - XR;     // units remanufactured at lsR for period tau
-            XR = xn;
-            A1 += (int32_t)__umul24((uint32_t)u, (uint32_t)lsR);
-            const int32_t rr = dp.x - u;   // units manufactured at lastM for period tau
-            A2 += (int32_t)__umul24((uint32_t)rr, (uint32_t)lastM);
-            bad |= rr & nolast;            // demand with no manufacturing setup at or before it
-        }
-    }
-    if (bad) return kInf;
+};
+
+// One period-step: sm, sr are the setup bits of period tau as 0 / -1 masks, dp = (D(tau), PR(tau)).
+__device__ __forceinline__ void decode_step(DecodeState &s, int32_t sm, int32_t sr, int32_t tau, int2 dp) {
+    s.lim = sel(sm, s.XR, s.lim);         // a manufacturing setup closes the remanufacturing capacity
+    s.lastM = sel(sm, tau, s.lastM);
+    s.nolast &= ~sm;
+    s.lim = sel(sr, dp.y, s.lim);         // a remanufacturing setup may use every return so far
+    s.lsR = sel(sr, tau, s.lsR);
+    const int32_t xn = min(s.XR + dp.x, s.lim);
+    const int32_t u = xn - s.XR;          // units remanufactured at lsR for period tau
+    s.XR = xn;
+    s.A1 += (int32_t)__umul24((uint32_t)u, (uint32_t)s.lsR);
+    const int32_t rr = dp.x - u;          // units manufactured at lastM for period tau
+    s.A2 += (int32_t)__umul24((uint32_t)rr, (uint32_t)s.lastM);
+    s.bad |= rr & s.nolast;               // demand with no manufacturing setup at or before it
+}
+
+__device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bits &b, int T, const ProdParams &pp) {
+    if (s.bad) return kInf;
     int32_t nM = 0, nR = 0;
 #pragma unroll
     for (int j = 0; j < kWords; ++j) {
         nM += __popc(b.m[j]);
         nR += __popc(b.r[j]);
     }
-    return (int64_t)pp.kM * nM + (int64_t)pp.kR * nR + (int64_t)pp.hM * (pp.S_tD - (int64_t)A1 - (int64_t)A2) +
-           (int64_t)pp.hR * (pp.S_PR - (int64_t)T * XR + (int64_t)A1);
+    return (int64_t)pp.kM * nM + (int64_t)pp.kR * nR + (int64_t)pp.hM * (pp.S_tD - (int64_t)s.A1 - (int64_t)s.A2) +
+           (int64_t)pp.hR * (pp.S_PR - (int64_t)T * s.XR + (int64_t)s.A1);
+}
+
+// Exact cost of one product's pattern (kInf when infeasible), any T <= kTMax.  row points at the product's
+// (D, PR) pairs; it may be an LDS or a global pointer (after inlining the address space is known).  The row
+// is read two periods ahead of its use so that a lone wavefront does not wait on each load.
+template <class RowPtr>
+__device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T, const ProdParams &pp) {
+    DecodeState s;
+    int2 ahead1 = row[0];
+    int2 ahead2 = row[T > 1 ? 1 : 0];
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) {
+        if (32 * j >= T) break;
+        const uint32_t m = b.m[j], r = b.r[j];
+        const int nb = min(32, T - 32 * j);
+#pragma unroll 2
+        for (int q = 0; q < nb; ++q) {
+            const int tau = 32 * j + q;
+            const int2 dp = ahead1;
+            ahead1 = ahead2;
+            ahead2 = row[tau + 2 < T ? tau + 2 : T - 1];
+            decode_step(s, __builtin_amdgcn_sbfe((int32_t)m, q, 1), __builtin_amdgcn_sbfe((int32_t)r, q, 1), tau, dp);
+        }
+    }
+    return decode_finish(s, b, T, pp);
 }
 
 // Feasibility of a pattern: only the periods before the first manufacturing setup can fail (afterwards

@@ -32,8 +32,8 @@ struct ChainBestArgs {
 };
 
 hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s);
-hipError_t launch_eval(const EvalArgs &a, int64_t cp_begin, int64_t n_cp, const int32_t *cp_chain, hipStream_t s);
+hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s);
 hipError_t launch_chain_best(const ChainBestArgs &a, int n_chains, hipStream_t s);
-hipError_t launch_run(const RunArgs &a, int n_chains, int waves, hipStream_t s);
+hipError_t launch_run(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, hipStream_t s);
 
 }  // namespace vns

@@ -48,6 +48,8 @@ struct vns_ctx {
     int32_t n_nb = 3;
     int32_t trace = 1;
     int32_t run_waves = 8;
+    int32_t eval_group = 4;
+    int64_t run_lds_budget = 64 * 1024;   // bytes of LDS the search kernel may use for an instance's rows
 
     // chains (host mirror)
     std::vector<ChainInfo> chains;
@@ -75,6 +77,9 @@ struct vns_ctx {
     Record *d_trace = nullptr;
     size_t trace_cap = 0;
     int32_t trace_iters = 0;
+    EvalWg *d_eval_wg = nullptr;          // k_eval workgroup table of the last chain range priced
+    int64_t eval_wg_n = 0;
+    int64_t eval_wg_key[3] = {-1, -1, -1};  // (first chain, number of chains, group size) of that table
 
     hipStream_t own_stream = nullptr, stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -151,6 +156,9 @@ static void free_chains(vns_ctx *c) {
     dfree(c->d_trace);
     c->trace_cap = 0;
     c->trace_iters = 0;
+    dfree(c->d_eval_wg);
+    c->eval_wg_n = 0;
+    c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = -1;
 }
 
 static void free_all(vns_ctx *c) {
@@ -388,6 +396,10 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v < 1 || v > kMaxWaves) return fail(c, VNS_EINVAL, "run waves out of range");
             c->run_waves = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_EVAL_GROUP:
+            if (v < 1 || v > kEvalGroup) return fail(c, VNS_EINVAL, "eval group out of range");
+            c->eval_group = (int32_t)v;
+            return VNS_OK;
         default:
             return fail(c, VNS_EINVAL, "unknown option");
     }
@@ -401,6 +413,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_NB_LIST: *v = c->nb_list; return VNS_OK;
         case VNS_OPT_TRACE: *v = c->trace; return VNS_OK;
         case VNS_OPT_RUN_WAVES: *v = c->run_waves; return VNS_OK;
+        case VNS_OPT_EVAL_GROUP: *v = c->eval_group; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
 }
@@ -441,7 +454,29 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
         VNS_HIP(c, dmalloc(&c->d_slot_price, (size_t)n_slots));
         c->slot_price_cap = (size_t)n_slots;
     }
+    // workgroup table: for each run of up to eval_group consecutive chains of one instance, one workgroup
+    // per product
+    const int64_t key[3] = {g0, ng, c->eval_group};
+    if (!(key[0] == c->eval_wg_key[0] && key[1] == c->eval_wg_key[1] && key[2] == c->eval_wg_key[2])) {
+        std::vector<EvalWg> tab;
+        int32_t g = g0;
+        while (g < g0 + ng) {
+            const ChainInfo &ci = c->chains[(size_t)g];
+            int32_t n = 1;
+            while (n < c->eval_group && g + n < g0 + ng && c->chains[(size_t)(g + n)].inst == ci.inst) ++n;
+            for (int32_t p = 0; p < ci.K; ++p) tab.push_back(EvalWg{ci.cp0 + p, n, 0});
+            g += n;
+        }
+        dfree(c->d_eval_wg);
+        c->eval_wg_n = 0;
+        c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = -1;
+        VNS_HIP(c, dmalloc(&c->d_eval_wg, tab.size()));
+        VNS_HIP(c, hipMemcpyAsync(c->d_eval_wg, tab.data(), sizeof(EvalWg) * tab.size(), hipMemcpyHostToDevice, c->stream));
+        c->eval_wg_n = (int64_t)tab.size();
+        for (int i = 0; i < 3; ++i) c->eval_wg_key[i] = key[i];
+    }
     EvalArgs ea{};
+    ea.cp_chain = c->d_cp_chain;
     ea.chains = c->d_chains;
     ea.prod = c->d_prod;
     ea.rows = c->d_rows;
@@ -453,10 +488,9 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     ea.prod_key = c->d_prod_key;
     ea.evals = c->d_evals;
     ea.nb_mask = nb_mask;
-    ea.chain0 = g0;
     VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long), c->stream));
     VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-    VNS_HIP(c, launch_eval(ea, cp_begin, n_cp, c->d_cp_chain, c->stream));
+    VNS_HIP(c, launch_eval(ea, c->d_eval_wg, c->eval_wg_n, c->stream));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     ChainBestArgs cb{c->d_chains, c->d_cs, c->d_cur_cost, c->d_prod_key, c->d_prod_price, c->d_prod_slot,
                      c->d_best, c->d_best_slot, g0};
@@ -517,8 +551,12 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     ra.kmax = c->kmax;
     ra.nb_list = c->nb_list;
     ra.n_nb = c->n_nb;
+    int64_t max_rows = 0;
+    for (int32_t i = 0; i < c->n_inst; ++i) max_rows = std::max<int64_t>(max_rows, (int64_t)c->K[(size_t)i] * c->T[(size_t)i]);
+    ra.rows_in_lds = max_rows * (int64_t)sizeof(int2) <= c->run_lds_budget ? 1 : 0;
+    const size_t lds = ra.rows_in_lds ? (size_t)max_rows * sizeof(int2) : (size_t)c->run_waves * kTMax * sizeof(int2);
     VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-    VNS_HIP(c, launch_run(ra, (int)G, c->run_waves, c->stream));
+    VNS_HIP(c, launch_run(ra, (int)G, c->run_waves, lds, c->stream));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     std::vector<ChainState> cs((size_t)G);
     VNS_HIP(c, hipMemcpyAsync(cs.data(), c->d_cs, sizeof(ChainState) * (size_t)G, hipMemcpyDeviceToHost, c->stream));

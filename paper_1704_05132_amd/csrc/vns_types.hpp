@@ -18,7 +18,8 @@ namespace vns {
 constexpr int kWords = 4;          // 32-bit words per setup row: T <= 128
 constexpr int kTMax = 32 * kWords;
 constexpr int kShakeMax = 64;
-constexpr int kMaxWaves = 16;
+constexpr int kMaxWaves = 8;
+constexpr int kEvalGroup = 16;     // chains of one instance priced by one k_eval workgroup
 constexpr int kMaxPasses = 1 << 16;  // VND passes per product and iteration: a guard, not a limit of the method
 constexpr int64_t kInf = INT64_MAX;
 constexpr uint64_t kInfKey = ~0ull;
@@ -76,9 +77,19 @@ struct RunArgs {
     int32_t kmax;
     uint32_t nb_list;       // one neighbourhood id per nibble
     int32_t n_nb;
+    int32_t rows_in_lds;    // 1: the whole instance's rows are staged in LDS at kernel start
+};
+
+// One k_eval workgroup: product cp - chains[cp_chain[cp]].cp0 of the n consecutive chains starting with the
+// chain of cp (chains of one instance are consecutive, their products K apart).
+struct EvalWg {
+    int64_t cp;
+    int32_t n;
+    int32_t pad;
 };
 
 struct EvalArgs {
+    const int32_t *cp_chain;     // [sum over chains of K] chain of each (chain, product)
     const ChainInfo *chains;
     const ProdParams *prod;
     const int2 *rows;
@@ -90,7 +101,6 @@ struct EvalArgs {
     uint64_t *prod_key;          // [sum over chains of K]: cost << 16 | slot of each product's best move
     unsigned long long *evals;   // device counter of move-evaluations
     uint32_t nb_mask;
-    int32_t chain0;              // first chain of the launch
 };
 
 }  // namespace vns

@@ -19,7 +19,7 @@ LIB_PATH = _PKG / "libvns.so"
 
 VNS_OK, VNS_EINVAL, VNS_ENOMEM, VNS_EDEVICE, VNS_ERANGE, VNS_ESTATE = 0, -1, -2, -3, -4, -5
 NB_FLIP_M, NB_FLIP_R, NB_SHIFT = 1, 2, 4
-OPT_CHAINS, OPT_KMAX, OPT_NB_LIST, OPT_TRACE, OPT_RUN_WAVES = 1, 2, 3, 4, 5
+OPT_CHAINS, OPT_KMAX, OPT_NB_LIST, OPT_TRACE, OPT_RUN_WAVES, OPT_EVAL_GROUP = 1, 2, 3, 4, 5, 6
 ALL_CHAINS = -1
 PRICE_INF = np.iinfo(np.int64).max
 T_MAX = 128
