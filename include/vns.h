@@ -55,6 +55,8 @@ enum { VNS_NB_FLIP_M = 1, VNS_NB_FLIP_R = 2, VNS_NB_SHIFT = 4 };
 #define VNS_KSHAKE_MAX 64      /* largest shake size k_max                              */
 #define VNS_ALL_CHAINS (-1)    /* chain argument of vns_eval_neighbourhood: every chain  */
 #define VNS_PRICE_INF INT64_MAX
+#define VNS_MLP_PARAMS 5313    /* float32 parameters of the learned move scorer                  */
+#define VNS_MLP_FEATURES 16    /* features per move                                             */
 
 /* Options (vns_set_option / vns_get_option). */
 enum vns_option {
@@ -64,8 +66,20 @@ enum vns_option {
                              up to 4 entries (default 0x421 = flip zM, flip zR, shift)                   */
     VNS_OPT_TRACE = 4,    /* 1 = vns_run keeps one record per chain and iteration (default 1)           */
     VNS_OPT_RUN_WAVES = 5, /* wavefronts per workgroup of the search kernel, 1..8 (default 8)           */
-    VNS_OPT_EVAL_GROUP = 6 /* chains of one instance priced together by one pricing workgroup, 1..16
+    VNS_OPT_EVAL_GROUP = 6, /* chains of one instance priced together by one pricing workgroup, 1..16
                               (default 4); a tuning knob, results do not depend on it                   */
+    VNS_OPT_RUN_LDS = 7,   /* bytes of LDS the search kernel may use to keep an instance's rows resident,
+                              0..131072 (default 65536); a tuning knob, results do not depend on it     */
+    VNS_OPT_GRAPH = 8,     /* 1 = vns_run captures its launch (search kernel + iteration-counter advance)
+                              in a HIP graph once per (iters, layout) and replays it (default 0); needs a
+                              stream other than the legacy default stream                               */
+    VNS_OPT_LEARNED = 9,   /* 0 = plain VND; p in 1..1000 = learned VND: in every neighbourhood evaluation
+                              the scorer ranks the moves, the best-ranked ceil(p*n/1000) are priced
+                              exactly and the best of them is applied if it improves, otherwise the whole
+                              neighbourhood is priced exactly and its best move applied if it improves   */
+    VNS_OPT_LOG = 10       /* move-log capacity in records (0 = off, default); a plain vns_run appends, for
+                              every applied move, its features and cost change and those of one other
+                              priced move of the same evaluation                                       */
 };
 
 /* One GVNS iteration of one chain. */
@@ -86,6 +100,10 @@ typedef struct vns_stats {
     double last_run_ms;      /* device time of the last vns_run call (HIP events on the context stream)  */
     int64_t last_eval_evals; /* move-evaluations of the last vns_eval_neighbourhood call                  */
     double last_eval_ms;     /* device time of the pricing kernel of that call                           */
+    int64_t last_run_period_steps;   /* sum over the last run's move-evaluations of their instance's T   */
+    int64_t last_eval_period_steps;  /* the same for the last vns_eval_neighbourhood call                */
+    int64_t last_run_learned_evals;  /* learned VND: neighbourhood evaluations of the last run           */
+    int64_t last_run_fallbacks;      /*   and how many of them priced the whole neighbourhood            */
 } vns_stats;
 
 /*
@@ -166,6 +184,41 @@ vns_status vns_get_trajectory(vns_ctx *ctx, int32_t chain, vns_record *rec, int6
 
 /* vns_get_stats — counters and device times, see vns_stats. */
 vns_status vns_get_stats(const vns_ctx *ctx, vns_stats *out);
+
+/*
+ * Learned move scorer (an MLP 16 -> 64 -> 64 -> 1 with ReLU, bfloat16 weights and layer inputs on the
+ * matrix cores, float32 accumulation) that ranks moves so that only the best-ranked are priced exactly.
+ * Features of a move at period t (float32): one-hot type (flip zM, flip zR, swap zM, swap zR); zM(t), zR(t);
+ * D(t)/200, R(t)/200, D(t-1)/200, D(t+1)/200 (0 outside the horizon); kM/2000, kR/2000, hM/8, hR/8;
+ * (t - last setup <= t)/T (1 if none); (next setup > t - t)/T (T if none).
+ * Parameters: VNS_MLP_PARAMS float32 = W1 [16][64] row-major, b1 [64], W2 [64][64], b2 [64], W3 [64], b3.
+ * A new context's parameters are all zero.
+ */
+vns_status vns_mlp_set_params(vns_ctx *ctx, const float *params);   /* also resets the Adam state       */
+vns_status vns_mlp_get_params(vns_ctx *ctx, float *params);
+/* Scores of n feature rows ([n][16] float32) into scores [n]. */
+vns_status vns_mlp_score(vns_ctx *ctx, const float *feats, int64_t n, float *scores);
+/* Gradient (VNS_MLP_PARAMS float32, may be NULL) and value (may be NULL) of the mean squared error of the
+ * scores of n rows against targets [n]. */
+vns_status vns_mlp_grad(vns_ctx *ctx, const float *feats, const float *targets, int64_t n, float *grads, float *loss);
+/* Adam (lr, betas 0.9 / 0.999, eps 1e-8) over `epochs` passes of minibatches of `batch` rows, each epoch in
+ * the order (m*i + a_e) mod n with m coprime to n and a_e drawn from seed; *last_loss (may be NULL) receives
+ * the last minibatch's loss.  The data are copied to the device for the call. */
+vns_status vns_mlp_train(vns_ctx *ctx, const float *feats, const float *targets, int64_t n, int32_t epochs,
+                         int32_t batch, float lr, uint64_t seed, float *last_loss);
+/* Move log of plain runs (VNS_OPT_LOG): up to cap records into feats [cap][16] and targets [cap] (cost
+ * change / 1000); *n receives the number stored.  Record order depends on chain scheduling. */
+vns_status vns_get_move_log(vns_ctx *ctx, float *feats, float *targets, int64_t cap, int64_t *n);
+/*
+ * vns_eval_learned — the learned choice of one neighbourhood's move (nb: one VNS_NB_* id) for every product
+ * of one chain's current solution, as the learned VND makes it: scores of every move, the best-ranked
+ * ceil(top_permille*n/1000) priced exactly, the whole neighbourhood when none of those improves.
+ * Outputs (each may be NULL): scores [4KT] (NaN where not a move), selected [4KT] (1 = priced before any
+ * fallback), prod_best [K] price of the chosen move (VNS_PRICE_INF if none), prod_best_slot [K] its local
+ * slot (-1), fallback [K] (1 = the whole neighbourhood was priced).
+ */
+vns_status vns_eval_learned(vns_ctx *ctx, uint32_t nb, int32_t chain, int32_t top_permille, float *scores,
+                            uint8_t *selected, int64_t *prod_best, int32_t *prod_best_slot, uint8_t *fallback);
 
 /* vns_instance_size — K and T of instance `inst`; vns_num_chains — total number of chains. */
 vns_status vns_instance_size(const vns_ctx *ctx, int32_t inst, int32_t *K, int32_t *T);

@@ -1,0 +1,99 @@
+"""Autotuner for the launch shape of the search and pricing kernels.
+
+The search kernel runs one workgroup per chain; how many wavefronts a workgroup has (so how many of a
+chain's products run their VND side by side) and how much LDS it may use to keep an instance's rows
+resident trade occupancy against parallelism, and the best choice depends on K, T and the number of
+chains.  The pricing kernel's tuning knob is how many chains of an instance share one workgroup.  Results
+never depend on these choices (the kernels compute the same exact costs and trajectories); only time does.
+
+`tune_search` and `tune_eval` time each candidate on the actual workload with the library's own device
+timers and return the fastest; `TuneTable` persists choices per workload signature in JSON.
+"""
+from __future__ import annotations
+
+import json
+from pathlib import Path
+from typing import Callable, Iterable, Sequence
+
+SEARCH_CANDIDATES = [dict(waves=w, lds=l) for w in (2, 4, 8) for l in (0, 65536)]
+EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 4, 8, 16)]
+
+
+def signature(instances, chains: int) -> str:
+    """Workload key: instance count, K range, the set of horizons, chains per instance."""
+    Ks = [i.K for i in instances]
+    Ts = sorted({i.T for i in instances})
+    return f"n{len(instances)}_K{min(Ks)}-{max(Ks)}_T{'-'.join(map(str, Ts))}_c{chains}"
+
+
+def pick(candidates: Iterable[dict], measure: Callable[[dict], float]):
+    """Measure every candidate; return (fastest, [(candidate, ms), ...]).  Ties keep the earlier one."""
+    timings = []
+    best, best_ms = None, None
+    for cand in candidates:
+        ms = float(measure(cand))
+        timings.append((dict(cand), ms))
+        if best_ms is None or ms < best_ms:
+            best, best_ms = dict(cand), ms
+    return best, timings
+
+
+def tune_search(instances, seed: int, chains: int, nb_list: Sequence[int] = (1, 2, 4), iters: int = 20,
+                candidates: Sequence[dict] = tuple(SEARCH_CANDIDATES)):
+    """Time the first `iters` GVNS iterations (one launch, fresh context) for each (waves, lds) candidate."""
+    from . import vns
+
+    def measure(c):
+        with vns.Context(instances, seed=seed, chains=chains, nb_list=nb_list, trace=False,
+                         options={vns.OPT_RUN_WAVES: c["waves"], vns.OPT_RUN_LDS: c["lds"]}) as ctx:
+            ctx.run(iters)
+            return ctx.stats()["last_run_ms"]
+
+    return pick(candidates, measure)
+
+
+def tune_eval(ctx, nb_mask: int = 7, reps: int = 5, candidates: Sequence[dict] = tuple(EVAL_CANDIDATES)):
+    """Median device time of a full pricing sweep of every chain of ctx for each chains-per-workgroup value."""
+    from . import vns
+
+    def measure(c):
+        ctx.set_option(vns.OPT_EVAL_GROUP, c["group"])
+        ms = []
+        for _ in range(reps):
+            ctx.eval_neighbourhood(nb_mask, vns.ALL_CHAINS, slot_prices=False)
+            ms.append(ctx.stats()["last_eval_ms"])
+        return sorted(ms)[len(ms) // 2]
+
+    best, timings = pick(candidates, measure)
+    ctx.set_option(vns.OPT_EVAL_GROUP, best["group"])
+    return best, timings
+
+
+class TuneTable:
+    """Choices per workload signature, stored as JSON."""
+
+    def __init__(self, path):
+        self.path = Path(path)
+        self.data = json.loads(self.path.read_text()) if self.path.exists() else {}
+
+    def get(self, key: str):
+        return self.data.get(key)
+
+    def put(self, key: str, choice: dict, timings=None):
+        self.data[key] = {"choice": choice, "timings_ms": [[c, ms] for c, ms in (timings or [])]}
+        self.path.write_text(json.dumps(self.data, indent=1, sort_keys=True))
+
+    def apply(self, ctx, key: str) -> bool:
+        """Set the stored search/eval options on ctx; False if the table has no entry for key."""
+        from . import vns
+        e = self.get(key)
+        if not e:
+            return False
+        ch = e["choice"]
+        if "waves" in ch:
+            ctx.set_option(vns.OPT_RUN_WAVES, ch["waves"])
+        if "lds" in ch:
+            ctx.set_option(vns.OPT_RUN_LDS, ch["lds"])
+        if "group" in ch:
+            ctx.set_option(vns.OPT_EVAL_GROUP, ch["group"])
+        return True

@@ -9,7 +9,7 @@ from pathlib import Path
 PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
-SOURCES = ["vns_kernels.hip", "vns_runtime.hip"]
+SOURCES = ["vns_kernels.hip", "vns_mlp.hip", "vns_runtime.hip"]
 ARCH = os.environ.get("VNS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

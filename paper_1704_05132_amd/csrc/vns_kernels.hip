@@ -13,68 +13,10 @@
 
 #include "vns_device.hpp"
 #include "vns_launch.hpp"
+#include "vns_search.hpp"
 
 namespace vns {
 
-namespace {
-
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Bit t of v set iff swapping bits t and t+1 of z is a move (t < T-1 and the bits differ).
-__device__ __forceinline__ void swap_valid(const uint32_t (&z)[kWords], int T, uint32_t (&v)[kWords]) {
-#pragma unroll
-    for (int j = 0; j < kWords; ++j) {
-        const uint32_t next = (j + 1 < kWords) ? z[j + 1] : 0u;
-        const uint32_t d = z[j] ^ ((z[j] >> 1) | (next << 31));
-        const int lim = T - 1 - 32 * j;  // valid positions q < lim in this word
-        const uint32_t keep = lim >= 32 ? ~0u : (lim <= 0 ? 0u : ((1u << lim) - 1u));
-        v[j] = d & keep;
-    }
-}
-
-__device__ __forceinline__ int popc_words(const uint32_t (&v)[kWords]) {
-    int n = 0;
-#pragma unroll
-    for (int j = 0; j < kWords; ++j) n += __popc(v[j]);
-    return n;
-}
-
-// Rank of bit t among the set bits of v, and whether it is set.
-__device__ __forceinline__ int rank_bit(const uint32_t (&v)[kWords], int t, bool &set) {
-    const int jt = t >> 5;
-    const uint32_t below = (1u << (t & 31)) - 1u;
-    int r = 0;
-    set = false;
-#pragma unroll
-    for (int j = 0; j < kWords; ++j) {
-        r += (j < jt) ? __popc(v[j]) : (j == jt ? __popc(v[j] & below) : 0);
-        set |= (j == jt) && ((v[j] >> (t & 31)) & 1u);
-    }
-    return r;
-}
-
-// One wavefront writes the local slots of the valid swaps of b (zM swaps, then zR swaps) to list and
-// returns how many there are.  The caller synchronises the wavefront before reading the list.
-__device__ __forceinline__ int build_swap_list(const Bits &b, int T, uint16_t *list, int lane) {
-    uint32_t vm[kWords], vr[kWords];
-    swap_valid(b.m, T, vm);
-    swap_valid(b.r, T, vr);
-    const int nm = popc_words(vm);
-    for (int t = lane; t < T - 1; t += 64) {
-        bool sm, sr;
-        const int pm = rank_bit(vm, t, sm);
-        const int pr = rank_bit(vr, t, sr);
-        if (sm) list[pm] = (uint16_t)(2 * T + t);
-        if (sr) list[nm + pr] = (uint16_t)(3 * T + t);
-    }
-    return nm + popc_words(vr);
-}
-
-}  // namespace
 
 // ---------------------------------------------------------------------------------------------------
 // k_init_costs: one workgroup per chain.  Costs of the current solution, copy to the working solution,
@@ -114,6 +56,8 @@ __global__ __launch_bounds__(256) void k_init_costs(InitArgs a) {
         cs.lopt = 0;
         cs.err = 0;
         cs.pad = 0;
+        cs.nb_evals = 0;
+        cs.fallbacks = 0;
         a.cstate[g] = cs;
     }
 }
@@ -205,7 +149,10 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restri
     eval_items(a, sh, n, nflip, fm, T, pp);
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x) a.prod_key[d.cp + (int64_t)j * K] = sh.key[j];
-    if (threadIdx.x == 0) atomicAdd(a.evals, (unsigned long long)sh.off[n]);
+    if (threadIdx.x == 0) {
+        atomicAdd(a.evals, (unsigned long long)sh.off[n]);
+        atomicAdd(a.evals + 1, (unsigned long long)sh.off[n] * (unsigned long long)T);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------------
@@ -253,7 +200,8 @@ __global__ __launch_bounds__(256) void k_chain_best(ChainBestArgs a) {
 // ---------------------------------------------------------------------------------------------------
 // k_run: persistent GVNS.  One workgroup per chain, W wavefronts.  Invariant at every iteration start:
 // work == cur for every product of the chain.  The instance's rows sit in LDS when they fit
-// (a.rows_in_lds), otherwise each wavefront stages the row of the product it works on.
+// (K*T <= a.lds_rows), otherwise each wavefront stages the row of the product it works on.  The first
+// iteration index comes from device memory so that a captured launch can be replayed unchanged.
 // ---------------------------------------------------------------------------------------------------
 namespace {
 
@@ -264,41 +212,9 @@ struct RunShared {
     int64_t part[kMaxWaves];
     int64_t shk[kMaxWaves];
     int64_t ev[kMaxWaves];
+    int64_t fb[kMaxWaves];
     int32_t nd;
 };
-
-// Best move of one neighbourhood for a product, computed by one wavefront: key = cost << 16 | slot.
-// With `ident`, one more item prices the unchanged pattern and its cost is returned in *ident_cost.
-__device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *row, int T, const ProdParams &pp,
-                                                   uint32_t nb, uint16_t *list, bool ident, int64_t *ident_cost,
-                                                   int64_t &evals) {
-    const int lane = threadIdx.x & 63;
-    const bool fm = nb & 1u;
-    const int nflip = (nb & 3u) ? T : 0;   // the list holds one neighbourhood: flip zM, flip zR or shift
-    int nswap = 0;
-    if (nb & 4u) {
-        nswap = build_swap_list(b, T, list, lane);
-        wave_sync_lds();
-    }
-    const int nitems = nflip + nswap;
-    const int total = nitems + (ident ? 1 : 0);
-    evals += nitems;
-    uint64_t best = kInfKey;
-    int64_t idc = 0;
-    for (int basei = 0; basei < total; basei += 64) {
-        const int idx = basei + lane;
-        int slot = -1;
-        if (idx < nitems) slot = idx < nflip ? (fm ? idx : T + idx) : (int)list[idx - nflip];
-        Bits mb = b;
-        if (slot >= 0) apply_move(mb, slot, T);
-        const int64_t c = decode_cost(mb, row, T, pp);
-        if (idx == nitems) idc = c;
-        const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
-        best = key < best ? key : best;
-    }
-    if (ident) *ident_cost = __shfl(idc, nitems & 63, 64);
-    return wave_min_u64(best);
-}
 
 __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 *s_rows) {
     const int g = blockIdx.x;
@@ -308,8 +224,10 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int W = blockDim.x >> 6;
     const int2 *inst_rows = a.rows + a.prod[ci.prod0].row;   // an instance's rows are contiguous
+    const bool rows_in_lds = K * T <= a.lds_rows;
+    const int64_t it_first = *a.it0;
 
-    if (a.rows_in_lds) {
+    if (rows_in_lds) {
         for (int i = threadIdx.x; i < K * T; i += blockDim.x) s_rows[i] = inst_rows[i];
         __syncthreads();
     }
@@ -317,10 +235,19 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
     ChainState cs = a.cstate[g];
     int64_t evals = 0;   // per wavefront (uniform)
     int vnd_err = 0;     // per wavefront (uniform)
+    int64_t nb_evals = 0, fallbacks = 0;   // learned mode, per wavefront
+    // learned search: this wavefront's tiles after the rows region (kept 16-byte aligned), and the scorer's
+    // weight fragments
+    const int rows_entries = run_rows_entries(a.lds_rows, W);
+    char *lbase = reinterpret_cast<char *>(s_rows + rows_entries) + wave * kLearnedWaveBytes;
+    LearnedLds L{reinterpret_cast<__bf16 *>(lbase), reinterpret_cast<__bf16 *>(lbase + 64 * 16 * 2),
+                 reinterpret_cast<uint16_t *>(lbase + 64 * 16 * 2 + 64 * 64 * 2)};
+    mlp::Frags fr;
+    if (a.permille > 0) mlp::load_frags(a.mlp, fr);
     const uint64_t nflip_all = 2ull * (uint64_t)K * (uint64_t)T;
 
     for (int i = 0; i < a.iters; ++i) {
-        const int64_t it = a.it0 + i;
+        const int64_t it = it_first + i;
         const int kshake = cs.k;
 
         // ---- Shake(x, k): wavefront 0 draws k flips and keeps the feasible ones in the dirty list ----
@@ -337,7 +264,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
                 apply_move(b, l, T);
                 // a manufacturing setup in period 0 makes any pattern feasible; otherwise check the prefix
                 bool ok = (b.m[0] & 1u) != 0u;
-                if (!ok) ok = a.rows_in_lds ? feasible(b, s_rows + p * T, T) : feasible(b, inst_rows + p * T, T);
+                if (!ok) ok = rows_in_lds ? feasible(b, s_rows + p * T, T) : feasible(b, inst_rows + p * T, T);
                 if (ok) {
                     if (e < 0) {
                         e = nd++;
@@ -368,7 +295,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
             const int64_t cp = cp0 + p;
             const ProdParams pp = a.prod[ci.prod0 + p];
             const int2 *row;
-            if (a.rows_in_lds) {
+            if (rows_in_lds) {
                 row = s_rows + p * T;
             } else {
                 int2 *slice = s_rows + wave * kTMax;
@@ -390,17 +317,43 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
                 improved = false;
                 for (int q = 0; q < a.n_nb; ++q) {
                     const uint32_t nb = (a.nb_list >> (4 * q)) & 0xFu;
-                    int64_t idc = 0;
-                    const uint64_t key = wave_best_move(b, row, T, pp, nb, sh.list[wave], need_ident, &idc, evals);
-                    if (need_ident) {
-                        cost = idc;
-                        shk += idc - c_cur;
-                        need_ident = false;
+                    uint64_t key, ckey = kInfKey;
+                    int nitems = 0;
+                    // contrast move for the log: a fixed pseudo-random item of this evaluation
+                    const int chash = a.log_x ? (int)(((uint32_t)it * 2654435761u + (uint32_t)p * 40503u +
+                                                       (uint32_t)(q + 4 * passes) * 97u) & 0x7FFFFFFFu) : -1;
+                    if (a.permille > 0) {
+                        int fb = 0;
+                        const bool id = need_ident;
+                        key = learned_best_move(b, row, T, pp, nb, sh.list[wave], L, fr, a.mlp, a.permille, id, cost,
+                                                evals, fb);
+                        ++nb_evals;
+                        fallbacks += fb;
+                        if (id) {
+                            shk += cost - c_cur;
+                            need_ident = false;
+                        }
+                    } else {
+                        int64_t idc = 0;
+                        key = wave_best_move(b, row, T, pp, nb, sh.list[wave], need_ident, &idc, evals, chash, &ckey,
+                                             &nitems);
+                        if (need_ident) {
+                            cost = idc;
+                            shk += idc - c_cur;
+                            need_ident = false;
+                        }
                     }
                     if (key != kInfKey) {
                         const int64_t c = (int64_t)(key >> kSlotBits);
                         if (c < cost) {
-                            apply_move(b, (int)(key & ((1u << kSlotBits) - 1)), T);
+                            const int slot = (int)(key & ((1u << kSlotBits) - 1));
+                            if (a.log_x && a.permille == 0) {
+                                const bool has_c = ckey != kInfKey && ckey != key;
+                                log_moves(b, row, T, pp, slot, c - cost, has_c ? (int)(ckey & 0xFFFFu) : -1,
+                                          has_c ? (int64_t)(ckey >> kSlotBits) - cost : 0, a.log_x, a.log_y, a.log_n,
+                                          a.log_cap);
+                            }
+                            apply_move(b, slot, T);
                             cost = c;
                             improved = true;
                         }
@@ -465,17 +418,23 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
     if (lane == 0) {
         sh.ev[wave] = evals;
         sh.part[wave] = vnd_err;
+        sh.shk[wave] = nb_evals;
+        sh.fb[wave] = fallbacks;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int64_t e = 0;
+        int64_t e = 0, ne = 0, nf = 0;
         int32_t err = 0;
         for (int w = 0; w < W; ++w) {
             e += sh.ev[w];
             err |= (int32_t)sh.part[w];
+            ne += sh.shk[w];
+            nf += sh.fb[w];
         }
         cs.evals = e;
         cs.err |= err;
+        cs.nb_evals = ne;
+        cs.fallbacks = nf;
         a.cstate[g] = cs;
     }
 }
@@ -484,9 +443,48 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
 
 __global__ __launch_bounds__(512) void k_run(RunArgs a) {
     __shared__ RunShared sh;
-    extern __shared__ int2 s_rows[];
+    extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
     run_chain(a, sh, s_rows);
 }
+
+// ---------------------------------------------------------------------------------------------------
+// k_eval_learned: one wavefront per (chain, product) of a chain range: the learned choice of one
+// neighbourhood's move for the current solution, with the scores and the selection of every move.
+// ---------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_eval_learned(EvalLearnedArgs a, int64_t cp_begin) {
+    __shared__ int2 s_row[kTMax];
+    __shared__ uint16_t s_list[2 * kTMax];
+    __shared__ uint16_t s_sel[2 * kTMax];
+    __shared__ __attribute__((aligned(16))) __bf16 s_x[64 * 16];   // read as 16-byte vectors
+    __shared__ __attribute__((aligned(16))) __bf16 s_h[64 * 64];
+    const int64_t cp = cp_begin + blockIdx.x;
+    const int g = a.cp_chain[cp];
+    const ChainInfo ci = a.chains[g];
+    const int T = ci.T;
+    const int p = (int)(cp - ci.cp0);
+    const ProdParams pp = a.prod[ci.prod0 + p];
+    for (int t = threadIdx.x; t < T; t += 64) s_row[t] = a.rows[pp.row + t];
+    wave_sync_lds();
+    mlp::Frags fr;
+    mlp::load_frags(a.mlp, fr);
+    const Bits b = a.cur[cp];
+    int64_t cost = a.cur_cost[cp], evals = 0;
+    int fb = 0;
+    const int64_t off = a.slot_off[g] + (int64_t)p * 4 * T;
+    LearnedLds L{s_x, s_h, s_sel};
+    const uint64_t key = learned_best_move(b, s_row, T, pp, a.nb, s_list, L, fr, a.mlp, a.permille, false, cost, evals,
+                                           fb, a.scores ? a.scores + off : nullptr, a.selected ? a.selected + off : nullptr);
+    if (threadIdx.x == 0) {
+        const int64_t F = a.cstate[g].F;
+        a.prod_price[cp] = key == kInfKey ? kInf : F - cost + (int64_t)(key >> kSlotBits);
+        a.prod_slot[cp] = key == kInfKey ? -1 : (int32_t)(key & 0xFFFFu);
+        a.fallback[cp] = (uint8_t)fb;
+        atomicAdd(a.evals, (unsigned long long)evals);
+    }
+}
+
+// k_advance: the iteration counter moves on once every chain of the launch has read it.
+__global__ void k_advance(int64_t *it, int32_t iters) { *it += iters; }
 
 // ---------------------------------------------------------------------------------------------------
 // Host-side launchers (called by the runtime).
@@ -509,9 +507,27 @@ hipError_t launch_chain_best(const ChainBestArgs &a, int n_chains, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_run(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64_t n_cp, hipStream_t s) {
+    if (n_cp <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eval_learned, dim3((unsigned)n_cp), dim3(64), 0, s, a, cp_begin);
+    return hipGetLastError();
+}
+
+hipError_t run_kernel_lds(size_t *static_bytes, size_t dynamic_bytes) {
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_run));
+    if (e != hipSuccess) return e;
+    *static_bytes = fa.sharedSizeBytes;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)dynamic_bytes);
+}
+
+hipError_t launch_run(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter, hipStream_t s) {
     if (n_chains <= 0 || a.iters <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_run, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, it_counter, a.iters);
     return hipGetLastError();
 }
 

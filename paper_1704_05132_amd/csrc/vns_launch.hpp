@@ -31,9 +31,43 @@ struct ChainBestArgs {
     int32_t chain0;
 };
 
+// Static LDS bytes of the search kernel, and permission for it to request dynamic_bytes more.
+hipError_t run_kernel_lds(size_t *static_bytes, size_t dynamic_bytes);
+// Learned scorer (vns_mlp.hip).  P: 5313 float32 parameters.  Scores of n feature rows [n][16].
+hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *out, hipStream_t s);
+// Gradient (and loss in grad_out[5313]) of the mean squared error over rows idx[0..n) (all rows when idx is
+// null).  Scratch, sized for ceil(n/64) blocks of 64 rows: Xb [*][16], sc [*], z1 and z2 [*][64],
+// part [blocks][5314].
+hipError_t launch_mlp_grad(const float *P, const float *X, const float *y, const int64_t *idx, int64_t n, float *Xb,
+                           float *sc, float *z1, float *z2, float *part, float *grad_out, hipStream_t s);
+// One Adam step (step counts from 1) on P with moments m, v.
+hipError_t launch_adam(float *P, const float *grad, float *m, float *v, float lr, int64_t step, hipStream_t s);
+struct EvalLearnedArgs {
+    const int32_t *cp_chain;
+    const ChainInfo *chains;
+    const ProdParams *prod;
+    const int2 *rows;
+    const Bits *cur;
+    const int64_t *cur_cost;
+    const ChainState *cstate;
+    const float *mlp;
+    const int64_t *slot_off;   // [G] first slot of each chain in scores / selected
+    float *scores;             // optional: score of every move, by slot
+    uint8_t *selected;         // optional: 1 for the moves priced exactly before any fallback
+    int64_t *prod_price;       // [cp]
+    int32_t *prod_slot;        // [cp]
+    uint8_t *fallback;         // [cp]
+    unsigned long long *evals;
+    uint32_t nb;
+    int32_t permille;
+};
+
 hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s);
+hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64_t n_cp, hipStream_t s);
 hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s);
 hipError_t launch_chain_best(const ChainBestArgs &a, int n_chains, hipStream_t s);
-hipError_t launch_run(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, hipStream_t s);
+// k_run over n_chains workgroups, then the device iteration counter advances by a.iters (two kernels on s;
+// both can be captured in a graph).
+hipError_t launch_run(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter, hipStream_t s);
 
 }  // namespace vns

@@ -1,0 +1,181 @@
+// Learned move scorer: per-move features and an MLP 16 -> 64 -> 64 -> 1 (ReLU) evaluated by one wavefront
+// for 64 moves at a time on the matrix cores (bfloat16 inputs, float32 accumulation).
+//
+// Features of a move at period t of a product (float32, in this order):
+//   0-3 one-hot type (flip zM, flip zR, swap zM, swap zR); 4,5 zM(t), zR(t) of the current pattern;
+//   6,7 D(t)/200, R(t)/200; 8,9 D(t-1)/200, D(t+1)/200 (0 outside the horizon); 10-13 kM/2000, kR/2000,
+//   hM/8, hR/8; 14 (t - p)/T with p the last setup period <= t (1 if none); 15 (n - t)/T with n the first
+//   setup period > t (T if none).
+// Parameters (float32 master copy, 5313 values): W1 [16][64] row-major, b1 [64], W2 [64][64], b2 [64],
+// W3 [64], b3.  The forward pass rounds weights and every layer's input to bfloat16 (nearest even); the
+// products are accumulated in float32 by v_mfma_f32_16x16x32_bf16 (layers 1 and 2) and by a float32 dot
+// product (layer 3).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vns_device.hpp"
+
+namespace vns {
+namespace mlp {
+
+constexpr int kF = 16;
+constexpr int kH = 64;
+constexpr int kParams = 5313;
+constexpr int oW1 = 0, oB1 = 1024, oW2 = 1088, oB2 = 5184, oW3 = 5248, oB3 = 5312;
+constexpr int kWaveLdsBytes = 64 * kF * 2 + 64 * kH * 2;   // feature tile + hidden tile, bfloat16
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Per-lane B-operand fragments of W1 and W2 (lane l: column l % 16, rows 8*(l/16) .. +7 of a 32-row slice).
+struct Frags {
+    bf8 w1[4];      // [n-tile], rows 16..31 of the zero-padded W1 are 0
+    bf8 w2[2][4];   // [k-slice][n-tile]
+};
+
+__device__ __forceinline__ void load_frags(const float *__restrict__ P, Frags &fr) {
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = 8 * g + e;
+            fr.w1[nt][e] = k < kF ? (__bf16)P[oW1 + k * kH + 16 * nt + c] : (__bf16)0.f;
+        }
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) fr.w2[kt][nt][e] = (__bf16)P[oW2 + (32 * kt + 8 * g + e) * kH + 16 * nt + c];
+}
+
+// Scores of 64 rows whose features sit in sx ([64][16] bfloat16); sh is a [64][64] bfloat16 scratch tile.
+// Every lane of the wavefront must call it; lane l receives the score of row l.  When z1 / z2 are given, the
+// pre-activations of the two hidden layers (float32, [64][64] row-major) are stored there as well.
+__device__ __forceinline__ float forward64(const __bf16 *sx, __bf16 *sh, const Frags &fr,
+                                           const float *__restrict__ P, float *z1 = nullptr, float *z2 = nullptr) {
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
+    const bf8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+    // layer 1: [64 x 32(16 used)] x [32 x 64]
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const bf8 a = g < 2 ? *reinterpret_cast<const bf8 *>(sx + (16 * mt + c) * kF + 8 * g) : zero8;
+        f4 acc[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f4 z = {0.f, 0.f, 0.f, 0.f};
+            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, fr.w1[nt], z, 0, 0, 0);
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float z = acc[nt][e] + P[oB1 + 16 * nt + c];
+                if (z1) z1[(16 * mt + 4 * g + e) * kH + 16 * nt + c] = z;
+                sh[(16 * mt + 4 * g + e) * kH + 16 * nt + c] = (__bf16)fmaxf(z, 0.f);
+            }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // layer 2: [64 x 64] x [64 x 64]; all outputs are kept in registers before the tile is overwritten
+    f4 h2[4][4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const bf8 a0 = *reinterpret_cast<const bf8 *>(sh + (16 * mt + c) * kH + 8 * g);
+        const bf8 a1 = *reinterpret_cast<const bf8 *>(sh + (16 * mt + c) * kH + 32 + 8 * g);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f4 z = {0.f, 0.f, 0.f, 0.f};
+            f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, fr.w2[0][nt], z, 0, 0, 0);
+            h2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, fr.w2[1][nt], acc, 0, 0, 0);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float z = h2[mt][nt][e] + P[oB2 + 16 * nt + c];
+                if (z2) z2[(16 * mt + 4 * g + e) * kH + 16 * nt + c] = z;
+                sh[(16 * mt + 4 * g + e) * kH + 16 * nt + c] = (__bf16)fmaxf(z, 0.f);
+            }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // layer 3: dot product of row `lane` with W3
+    float s = P[oB3];
+#pragma unroll 8
+    for (int j = 0; j < kH; ++j) s += (float)sh[lane * kH + j] * (float)(__bf16)P[oW3 + j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return s;
+}
+
+// Last setup period <= t and first setup period > t of the pattern s (either type); -1 / T when none.
+__device__ __forceinline__ void setup_neighbours(const uint32_t (&s)[kWords], int t, int T, int &prev, int &next) {
+    prev = -1;
+    next = T;
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) {
+        const int lo = 32 * j;
+        // bits of word j at positions <= t
+        const uint32_t le = t >= lo + 31 ? ~0u : (t < lo ? 0u : (0xFFFFFFFFu >> (31 - (t - lo))));
+        const uint32_t wle = s[j] & le;
+        if (wle) prev = lo + 31 - __clz(wle);
+        // bits of word j at positions > t (scan from the highest word down so the lowest one wins)
+    }
+#pragma unroll
+    for (int j = kWords - 1; j >= 0; --j) {
+        const int lo = 32 * j;
+        const uint32_t gt = t >= lo + 31 ? 0u : (t < lo ? ~0u : (0xFFFFFFFFu << (t - lo + 1)));
+        const uint32_t wgt = s[j] & gt;
+        if (wgt) next = lo + __ffs(wgt) - 1;
+    }
+    if (next > T) next = T;
+}
+
+// Features of local slot l of a product with current pattern b, rows (D, PR), horizon T.
+template <class RowPtr>
+__device__ __forceinline__ void move_features(const Bits &b, RowPtr row, int T, const ProdParams &pp, int l,
+                                              float (&f)[kF]) {
+    const int ty = (l >= T) + (l >= 2 * T) + (l >= 3 * T);
+    const int t = l - ty * T;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) f[i] = ty == i ? 1.f : 0.f;
+    f[4] = test_bit(b.m, t) ? 1.f : 0.f;
+    f[5] = test_bit(b.r, t) ? 1.f : 0.f;
+    const int2 cur = row[t];
+    const int Rt = cur.y - (t > 0 ? row[t - 1].y : 0);
+    f[6] = (float)cur.x / 200.f;
+    f[7] = (float)Rt / 200.f;
+    f[8] = t > 0 ? (float)row[t - 1].x / 200.f : 0.f;
+    f[9] = t + 1 < T ? (float)row[t + 1].x / 200.f : 0.f;
+    f[10] = (float)pp.kM / 2000.f;
+    f[11] = (float)pp.kR / 2000.f;
+    f[12] = (float)pp.hM / 8.f;
+    f[13] = (float)pp.hR / 8.f;
+    uint32_t s[kWords];
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) s[j] = b.m[j] | b.r[j];
+    int prev, next;
+    setup_neighbours(s, t, T, prev, next);
+    f[14] = prev >= 0 ? (float)(t - prev) / (float)T : 1.f;
+    f[15] = (float)(next - t) / (float)T;
+}
+
+// Order-preserving map of a float score to an unsigned key (lower score -> lower key).
+__device__ __forceinline__ uint32_t sortable(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+}  // namespace mlp
+}  // namespace vns

@@ -14,12 +14,14 @@
 
 #include "vns.h"
 #include "vns_launch.hpp"
+#include "vns_mlp.hpp"
 #include "vns_types.hpp"
 
 using namespace vns;
 
 static_assert(sizeof(Record) == sizeof(vns_record), "record layout");
 static_assert(sizeof(Bits) == 32, "bits layout");
+static_assert(VNS_MLP_PARAMS == mlp::kParams, "scorer parameter count");
 
 namespace {
 
@@ -50,6 +52,10 @@ struct vns_ctx {
     int32_t run_waves = 8;
     int32_t eval_group = 4;
     int64_t run_lds_budget = 64 * 1024;   // bytes of LDS the search kernel may use for an instance's rows
+    int32_t use_graph = 0;
+    int64_t max_lds_per_wg = 65536;       // device limit on LDS per workgroup (queried at create)
+    int32_t permille = 0;                 // learned scorer: top permille priced exactly (0 = plain search)
+    int64_t log_cap = 0;                  // move-log capacity in records (0 = no log)
 
     // chains (host mirror)
     std::vector<ChainInfo> chains;
@@ -77,6 +83,15 @@ struct vns_ctx {
     Record *d_trace = nullptr;
     size_t trace_cap = 0;
     int32_t trace_iters = 0;
+    int64_t *d_iter = nullptr;            // device iteration counter (first iteration of the next run)
+    float *d_mlp = nullptr;               // scorer parameters, Adam moments
+    float *d_adam_m = nullptr, *d_adam_v = nullptr;
+    int64_t adam_step = 0;
+    float *d_log_x = nullptr, *d_log_y = nullptr;   // move log
+    unsigned long long *d_log_n = nullptr;
+    hipGraph_t graph = nullptr;           // captured search launch (VNS_OPT_GRAPH)
+    hipGraphExec_t graph_exec = nullptr;
+    int64_t graph_key[5] = {-1, -1, -1, -1, -1};  // (iters, chains, waves, LDS bytes, trace buffer)
     EvalWg *d_eval_wg = nullptr;          // k_eval workgroup table of the last chain range priced
     int64_t eval_wg_n = 0;
     int64_t eval_wg_key[3] = {-1, -1, -1};  // (first chain, number of chains, group size) of that table
@@ -137,7 +152,17 @@ static void dfree(T *&p) {
     p = nullptr;
 }
 
+static void drop_graph(vns_ctx *c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    for (int i = 0; i < 5; ++i) c->graph_key[i] = -1;
+}
+
 static void free_chains(vns_ctx *c) {
+    drop_graph(c);
+    dfree(c->d_iter);
     dfree(c->d_chains);
     dfree(c->d_cp_chain);
     dfree(c->d_price_off);
@@ -161,8 +186,18 @@ static void free_chains(vns_ctx *c) {
     c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = -1;
 }
 
+static void free_log(vns_ctx *c) {
+    dfree(c->d_log_x);
+    dfree(c->d_log_y);
+    dfree(c->d_log_n);
+}
+
 static void free_all(vns_ctx *c) {
     free_chains(c);
+    free_log(c);
+    dfree(c->d_mlp);
+    dfree(c->d_adam_m);
+    dfree(c->d_adam_v);
     dfree(c->d_rows);
     dfree(c->d_prod);
     dfree(c->d_evals);
@@ -227,6 +262,9 @@ static vns_status setup_chains(vns_ctx *c) {
     VNS_HIP(c, dmalloc(&c->d_prod_slot, (size_t)cp));
     VNS_HIP(c, dmalloc(&c->d_best, (size_t)G));
     VNS_HIP(c, dmalloc(&c->d_best_slot, (size_t)G));
+    VNS_HIP(c, dmalloc(&c->d_iter, 1));
+    const int64_t zero = 0;
+    VNS_HIP(c, hipMemcpyAsync(c->d_iter, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
     VNS_HIP(c, hipMemcpyAsync(c->d_chains, c->chains.data(), sizeof(ChainInfo) * (size_t)G, hipMemcpyHostToDevice, c->stream));
     VNS_HIP(c, hipMemcpyAsync(c->d_cp_chain, cp_chain.data(), sizeof(int32_t) * (size_t)cp, hipMemcpyHostToDevice, c->stream));
     VNS_HIP(c, hipMemcpyAsync(c->d_price_off, c->price_off.data(), sizeof(int64_t) * (size_t)G, hipMemcpyHostToDevice, c->stream));
@@ -330,13 +368,24 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
         if (e_ != hipSuccess) return bail(hip_fail(c, e_, #expr)); \
     } while (0)
     VNS_CREATE_HIP(hipGetDevice(&c->device));
+    {
+        int v = 0;
+        VNS_CREATE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+        c->max_lds_per_wg = v;
+    }
     VNS_CREATE_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
     c->stream = c->own_stream;
     VNS_CREATE_HIP(hipEventCreate(&c->ev0));
     VNS_CREATE_HIP(hipEventCreate(&c->ev1));
     VNS_CREATE_HIP(dmalloc(&c->d_rows, (size_t)n_rows));
     VNS_CREATE_HIP(dmalloc(&c->d_prod, (size_t)n_prod));
-    VNS_CREATE_HIP(dmalloc(&c->d_evals, 1));
+    VNS_CREATE_HIP(dmalloc(&c->d_evals, 2));
+    VNS_CREATE_HIP(dmalloc(&c->d_mlp, (size_t)mlp::kParams));
+    VNS_CREATE_HIP(dmalloc(&c->d_adam_m, (size_t)mlp::kParams));
+    VNS_CREATE_HIP(dmalloc(&c->d_adam_v, (size_t)mlp::kParams));
+    VNS_CREATE_HIP(hipMemsetAsync(c->d_mlp, 0, sizeof(float) * mlp::kParams, c->stream));
+    VNS_CREATE_HIP(hipMemsetAsync(c->d_adam_m, 0, sizeof(float) * mlp::kParams, c->stream));
+    VNS_CREATE_HIP(hipMemsetAsync(c->d_adam_v, 0, sizeof(float) * mlp::kParams, c->stream));
     VNS_CREATE_HIP(hipMemcpyAsync(c->d_rows, rows.data(), sizeof(int2) * (size_t)n_rows, hipMemcpyHostToDevice, c->stream));
     VNS_CREATE_HIP(hipMemcpyAsync(c->d_prod, prod.data(), sizeof(ProdParams) * (size_t)n_prod, hipMemcpyHostToDevice, c->stream));
 #undef VNS_CREATE_HIP
@@ -364,6 +413,7 @@ extern "C" void vns_destroy(vns_ctx *c) {
 // ---------------------------------------------------------------------------------------------------
 extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
     VNS_LIVE(c);
+    drop_graph(c);   // a captured launch holds the previous options in its arguments
     switch (key) {
         case VNS_OPT_CHAINS:
             if (v < 1 || v > 65536) return fail(c, VNS_EINVAL, "chains out of range");
@@ -400,6 +450,33 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v < 1 || v > kEvalGroup) return fail(c, VNS_EINVAL, "eval group out of range");
             c->eval_group = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_RUN_LDS:
+            if (v < 0 || v > kRunLdsMax) return fail(c, VNS_EINVAL, "search kernel LDS budget out of range");
+            c->run_lds_budget = v;
+            return VNS_OK;
+        case VNS_OPT_GRAPH:
+            if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "graph must be 0 or 1");
+            c->use_graph = (int32_t)v;
+            if (!v) drop_graph(c);
+            return VNS_OK;
+        case VNS_OPT_LEARNED:
+            if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
+            c->permille = (int32_t)v;
+            return VNS_OK;
+        case VNS_OPT_LOG: {
+            if (v < 0 || v > ((int64_t)1 << 31)) return fail(c, VNS_EINVAL, "move-log capacity out of range");
+            free_log(c);
+            c->log_cap = 0;
+            if (v > 0) {
+                VNS_HIP(c, dmalloc(&c->d_log_x, (size_t)v * mlp::kF));
+                VNS_HIP(c, dmalloc(&c->d_log_y, (size_t)v));
+                VNS_HIP(c, dmalloc(&c->d_log_n, 1));
+                VNS_HIP(c, hipMemsetAsync(c->d_log_n, 0, sizeof(unsigned long long), c->stream));
+                VNS_HIP(c, hipStreamSynchronize(c->stream));
+            }
+            c->log_cap = v;
+            return VNS_OK;
+        }
         default:
             return fail(c, VNS_EINVAL, "unknown option");
     }
@@ -414,6 +491,10 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_TRACE: *v = c->trace; return VNS_OK;
         case VNS_OPT_RUN_WAVES: *v = c->run_waves; return VNS_OK;
         case VNS_OPT_EVAL_GROUP: *v = c->eval_group; return VNS_OK;
+        case VNS_OPT_RUN_LDS: *v = c->run_lds_budget; return VNS_OK;
+        case VNS_OPT_GRAPH: *v = c->use_graph; return VNS_OK;
+        case VNS_OPT_LEARNED: *v = c->permille; return VNS_OK;
+        case VNS_OPT_LOG: *v = c->log_cap; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
 }
@@ -421,6 +502,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
 extern "C" vns_status vns_bind_stream(vns_ctx *c, void *s) {
     VNS_LIVE(c);
     VNS_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
     c->stream = s ? (hipStream_t)s : c->own_stream;
     return VNS_OK;
 }
@@ -488,7 +570,7 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     ea.prod_key = c->d_prod_key;
     ea.evals = c->d_evals;
     ea.nb_mask = nb_mask;
-    VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long), c->stream));
+    VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, 2 * sizeof(unsigned long long), c->stream));
     VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
     VNS_HIP(c, launch_eval(ea, c->d_eval_wg, c->eval_wg_n, c->stream));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
@@ -504,12 +586,13 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     if (best) VNS_HIP(c, hipMemcpyAsync(best, c->d_best, sizeof(int64_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
     if (best_slot)
         VNS_HIP(c, hipMemcpyAsync(best_slot, c->d_best_slot, sizeof(int32_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
-    unsigned long long ev = 0;
-    VNS_HIP(c, hipMemcpyAsync(&ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost, c->stream));
+    unsigned long long ev[2] = {0, 0};
+    VNS_HIP(c, hipMemcpyAsync(ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost, c->stream));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     float ms = 0.f;
     VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    c->stats.last_eval_evals = (int64_t)ev;
+    c->stats.last_eval_evals = (int64_t)ev[0];
+    c->stats.last_eval_period_steps = (int64_t)ev[1];
     c->stats.last_eval_ms = ms;
     return VNS_OK;
 }
@@ -545,34 +628,79 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     ra.work_cost = c->d_work_cost;
     ra.cstate = c->d_cs;
     ra.trace = c->trace ? c->d_trace : nullptr;
+    ra.it0 = c->d_iter;
     ra.seed = c->seed;
-    ra.it0 = c->iteration;
     ra.iters = iters;
     ra.kmax = c->kmax;
     ra.nb_list = c->nb_list;
     ra.n_nb = c->n_nb;
+    ra.permille = c->permille;
+    ra.mlp = c->d_mlp;
+    ra.log_x = c->log_cap > 0 ? c->d_log_x : nullptr;
+    ra.log_y = c->d_log_y;
+    ra.log_n = c->d_log_n;
+    ra.log_cap = c->log_cap;
     int64_t max_rows = 0;
     for (int32_t i = 0; i < c->n_inst; ++i) max_rows = std::max<int64_t>(max_rows, (int64_t)c->K[(size_t)i] * c->T[(size_t)i]);
-    ra.rows_in_lds = max_rows * (int64_t)sizeof(int2) <= c->run_lds_budget ? 1 : 0;
-    const size_t lds = ra.rows_in_lds ? (size_t)max_rows * sizeof(int2) : (size_t)c->run_waves * kTMax * sizeof(int2);
-    VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-    VNS_HIP(c, launch_run(ra, (int)G, c->run_waves, lds, c->stream));
-    VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
+    // instance rows in LDS for every chain whose instance fits the budget; the others stage one row per wave
+    size_t static_lds = 0;
+    VNS_HIP(c, run_kernel_lds(&static_lds, 0));
+    const int64_t learned = c->permille > 0 ? (int64_t)c->run_waves * kLearnedWaveBytes : 0;
+    const int64_t room = c->max_lds_per_wg - (int64_t)static_lds - learned;   // dynamic LDS left for rows
+    const int64_t slices = (int64_t)c->run_waves * kTMax;            // per-wave rows when the instance does not fit
+    if (room < slices * (int64_t)sizeof(int2)) return fail(c, VNS_EINVAL, "not enough LDS for the search kernel");
+    const int64_t budget = std::min<int64_t>(c->run_lds_budget, room) / (int64_t)sizeof(int2);
+    ra.lds_rows = (int32_t)std::min<int64_t>(max_rows, budget);
+    const size_t lds = (size_t)run_rows_entries(ra.lds_rows, c->run_waves) * sizeof(int2) + (size_t)learned;
+    VNS_HIP(c, run_kernel_lds(&static_lds, lds));
+    if (c->use_graph) {
+        const int64_t key[5] = {iters, G, c->run_waves, (int64_t)lds, (int64_t)(intptr_t)ra.trace};
+        bool same = true;
+        for (int i = 0; i < 5; ++i) same = same && key[i] == c->graph_key[i];
+        if (!same || !c->graph_exec) {
+            drop_graph(c);
+            VNS_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t le = launch_run(ra, (int)G, c->run_waves, lds, c->d_iter, c->stream);
+            hipGraph_t gr = nullptr;
+            hipError_t ce = hipStreamEndCapture(c->stream, &gr);
+            if (le != hipSuccess) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return hip_fail(c, le, "launch_run (capture)");
+            }
+            VNS_HIP(c, ce);
+            c->graph = gr;
+            VNS_HIP(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+            for (int i = 0; i < 5; ++i) c->graph_key[i] = key[i];
+        }
+        VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
+        VNS_HIP(c, hipGraphLaunch(c->graph_exec, c->stream));
+        VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
+    } else {
+        VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
+        VNS_HIP(c, launch_run(ra, (int)G, c->run_waves, lds, c->d_iter, c->stream));
+        VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
+    }
     std::vector<ChainState> cs((size_t)G);
     VNS_HIP(c, hipMemcpyAsync(cs.data(), c->d_cs, sizeof(ChainState) * (size_t)G, hipMemcpyDeviceToHost, c->stream));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     float ms = 0.f;
     VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    int64_t ev = 0;
+    int64_t ev = 0, steps = 0, nbe = 0, fbs = 0;
     int32_t err = 0;
-    for (const ChainState &s : cs) {
-        ev += s.evals;
-        err |= s.err;
+    for (size_t g = 0; g < cs.size(); ++g) {
+        ev += cs[g].evals;
+        steps += cs[g].evals * c->chains[g].T;
+        nbe += cs[g].nb_evals;
+        fbs += cs[g].fallbacks;
+        err |= cs[g].err;
     }
+    c->stats.last_run_learned_evals = nbe;
+    c->stats.last_run_fallbacks = fbs;
     if (err) return fail(c, VNS_EDEVICE, "a VND exceeded its pass guard (inconsistent costs)");
     c->iteration += iters;
     c->stats.iterations = c->iteration;
     c->stats.last_run_evals = ev;
+    c->stats.last_run_period_steps = steps;
     c->stats.move_evals += ev;
     c->stats.last_run_ms = ms;
     return VNS_OK;
@@ -682,4 +810,212 @@ extern "C" int64_t vns_num_chains(const vns_ctx *c) { return c ? (int64_t)c->cha
 
 extern "C" const char *vns_last_error(const vns_ctx *c) {
     return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+// ---------------------------------------------------------------------------------------------------
+// learned scorer
+// ---------------------------------------------------------------------------------------------------
+extern "C" vns_status vns_mlp_set_params(vns_ctx *c, const float *params) {
+    VNS_LIVE(c);
+    if (!params) return fail(c, VNS_EINVAL, "NULL params");
+    for (int i = 0; i < mlp::kParams; ++i)
+        if (!(params[i] == params[i]) || params[i] > 1e30f || params[i] < -1e30f)
+            return fail(c, VNS_EINVAL, "non-finite scorer parameter");
+    VNS_HIP(c, hipMemcpyAsync(c->d_mlp, params, sizeof(float) * mlp::kParams, hipMemcpyHostToDevice, c->stream));
+    VNS_HIP(c, hipMemsetAsync(c->d_adam_m, 0, sizeof(float) * mlp::kParams, c->stream));
+    VNS_HIP(c, hipMemsetAsync(c->d_adam_v, 0, sizeof(float) * mlp::kParams, c->stream));
+    c->adam_step = 0;
+    drop_graph(c);
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_mlp_get_params(vns_ctx *c, float *params) {
+    VNS_LIVE(c);
+    if (!params) return fail(c, VNS_EINVAL, "NULL params");
+    VNS_HIP(c, hipMemcpyAsync(params, c->d_mlp, sizeof(float) * mlp::kParams, hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    return VNS_OK;
+}
+
+template <class T>
+struct Scoped {
+    T *p = nullptr;
+    ~Scoped() { dfree(p); }
+};
+
+extern "C" vns_status vns_mlp_score(vns_ctx *c, const float *feats, int64_t n, float *scores) {
+    VNS_LIVE(c);
+    if (n < 0 || (n > 0 && (!feats || !scores))) return fail(c, VNS_EINVAL, "bad arguments");
+    if (n == 0) return VNS_OK;
+    Scoped<float> X, S;
+    VNS_HIP(c, dmalloc(&X.p, (size_t)n * mlp::kF));
+    VNS_HIP(c, dmalloc(&S.p, (size_t)n));
+    VNS_HIP(c, hipMemcpyAsync(X.p, feats, sizeof(float) * mlp::kF * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    VNS_HIP(c, launch_mlp_score(c->d_mlp, X.p, n, S.p, c->stream));
+    VNS_HIP(c, hipMemcpyAsync(scores, S.p, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    return VNS_OK;
+}
+
+// Device scratch of one gradient evaluation over up to n rows.
+struct GradScratch {
+    Scoped<float> Xb, sc, z1, z2, part, grad;
+    vns_status alloc(vns_ctx *c, int64_t n) {
+        const int64_t nb = (n + 63) / 64;
+        VNS_HIP(c, dmalloc(&Xb.p, (size_t)(nb * 64 * mlp::kF)));
+        VNS_HIP(c, dmalloc(&sc.p, (size_t)(nb * 64)));
+        VNS_HIP(c, dmalloc(&z1.p, (size_t)(nb * 64 * mlp::kH)));
+        VNS_HIP(c, dmalloc(&z2.p, (size_t)(nb * 64 * mlp::kH)));
+        VNS_HIP(c, dmalloc(&part.p, (size_t)(nb * (mlp::kParams + 1))));
+        VNS_HIP(c, dmalloc(&grad.p, (size_t)(mlp::kParams + 1)));
+        return VNS_OK;
+    }
+};
+
+extern "C" vns_status vns_mlp_grad(vns_ctx *c, const float *feats, const float *targets, int64_t n, float *grads,
+                                   float *loss) {
+    VNS_LIVE(c);
+    if (n <= 0 || !feats || !targets) return fail(c, VNS_EINVAL, "bad arguments");
+    Scoped<float> X, Y;
+    VNS_HIP(c, dmalloc(&X.p, (size_t)n * mlp::kF));
+    VNS_HIP(c, dmalloc(&Y.p, (size_t)n));
+    VNS_HIP(c, hipMemcpyAsync(X.p, feats, sizeof(float) * mlp::kF * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    VNS_HIP(c, hipMemcpyAsync(Y.p, targets, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    GradScratch gs;
+    vns_status st = gs.alloc(c, n);
+    if (st != VNS_OK) return st;
+    VNS_HIP(c, launch_mlp_grad(c->d_mlp, X.p, Y.p, nullptr, n, gs.Xb.p, gs.sc.p, gs.z1.p, gs.z2.p, gs.part.p, gs.grad.p,
+                               c->stream));
+    std::vector<float> g((size_t)mlp::kParams + 1);
+    VNS_HIP(c, hipMemcpyAsync(g.data(), gs.grad.p, sizeof(float) * g.size(), hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    if (grads) std::memcpy(grads, g.data(), sizeof(float) * mlp::kParams);
+    if (loss) *loss = g[(size_t)mlp::kParams];
+    return VNS_OK;
+}
+
+__global__ void k_batch_index(int64_t *idx, int64_t start, int64_t count, int64_t n, uint64_t mul, uint64_t add) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < count) idx[r] = (int64_t)(((unsigned __int128)mul * (uint64_t)(start + r) + add) % (uint64_t)n);
+}
+
+extern "C" vns_status vns_mlp_train(vns_ctx *c, const float *feats, const float *targets, int64_t n, int32_t epochs,
+                                    int32_t batch, float lr, uint64_t seed, float *last_loss) {
+    VNS_LIVE(c);
+    if (n <= 0 || !feats || !targets || epochs < 0 || batch < 1 || !(lr > 0.f)) return fail(c, VNS_EINVAL, "bad arguments");
+    Scoped<float> X, Y;
+    Scoped<int64_t> idx;
+    VNS_HIP(c, dmalloc(&X.p, (size_t)n * mlp::kF));
+    VNS_HIP(c, dmalloc(&Y.p, (size_t)n));
+    VNS_HIP(c, dmalloc(&idx.p, (size_t)batch));
+    VNS_HIP(c, hipMemcpyAsync(X.p, feats, sizeof(float) * mlp::kF * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    VNS_HIP(c, hipMemcpyAsync(Y.p, targets, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    const int64_t bmax = std::min<int64_t>(batch, n);
+    GradScratch gs;
+    vns_status st = gs.alloc(c, bmax);
+    if (st != VNS_OK) return st;
+    // rows of each epoch in the order (mul * i + add) mod n, mul coprime to n, add drawn per epoch
+    uint64_t mul = 1000003ull;
+    auto gcd = [](uint64_t a, uint64_t b) { while (b) { uint64_t t = a % b; a = b; b = t; } return a; };
+    while (gcd(mul, (uint64_t)n) != 1) mul += 2;
+    uint64_t state = seed * 0x9E3779B97F4A7C15ull + 1;
+    float loss = 0.f;
+    for (int32_t e = 0; e < epochs; ++e) {
+        state ^= state >> 33; state *= 0xFF51AFD7ED558CCDull; state ^= state >> 33;
+        const uint64_t add = state % (uint64_t)n;
+        for (int64_t s0 = 0; s0 < n; s0 += bmax) {
+            const int64_t cnt = std::min<int64_t>(bmax, n - s0);
+            hipLaunchKernelGGL(k_batch_index, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c->stream, idx.p, s0, cnt, n,
+                               mul, add);
+            VNS_HIP(c, hipGetLastError());
+            VNS_HIP(c, launch_mlp_grad(c->d_mlp, X.p, Y.p, idx.p, cnt, gs.Xb.p, gs.sc.p, gs.z1.p, gs.z2.p, gs.part.p,
+                                       gs.grad.p, c->stream));
+            VNS_HIP(c, launch_adam(c->d_mlp, gs.grad.p, c->d_adam_m, c->d_adam_v, lr, ++c->adam_step, c->stream));
+        }
+    }
+    if (epochs > 0) {
+        VNS_HIP(c, hipMemcpyAsync(&loss, gs.grad.p + mlp::kParams, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    }
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    if (last_loss) *last_loss = loss;
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_get_move_log(vns_ctx *c, float *feats, float *targets, int64_t cap, int64_t *n) {
+    VNS_LIVE(c);
+    if (c->log_cap <= 0) {
+        if (n) *n = 0;
+        return VNS_OK;
+    }
+    unsigned long long cnt = 0;
+    VNS_HIP(c, hipMemcpyAsync(&cnt, c->d_log_n, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    const int64_t avail = std::min<int64_t>((int64_t)cnt, c->log_cap);
+    if (n) *n = avail;
+    const int64_t m = std::min<int64_t>(avail, cap < 0 ? 0 : cap);
+    if (m > 0 && feats)
+        VNS_HIP(c, hipMemcpyAsync(feats, c->d_log_x, sizeof(float) * mlp::kF * (size_t)m, hipMemcpyDeviceToHost, c->stream));
+    if (m > 0 && targets)
+        VNS_HIP(c, hipMemcpyAsync(targets, c->d_log_y, sizeof(float) * (size_t)m, hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    return VNS_OK;
+}
+
+__global__ void k_fill_nan(float *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = __int_as_float(0x7FC00000);
+}
+
+extern "C" vns_status vns_eval_learned(vns_ctx *c, uint32_t nb, int32_t chain, int32_t top_permille, float *scores,
+                                       uint8_t *selected, int64_t *prod_best, int32_t *prod_best_slot, uint8_t *fallback) {
+    VNS_LIVE(c);
+    if (nb != VNS_NB_FLIP_M && nb != VNS_NB_FLIP_R && nb != VNS_NB_SHIFT) return fail(c, VNS_EINVAL, "nb must be one neighbourhood");
+    if (top_permille < 1 || top_permille > 1000) return fail(c, VNS_EINVAL, "top_permille must be in 1..1000");
+    vns_status st = check_chain(c, chain);
+    if (st != VNS_OK) return st;
+    const ChainInfo &ci = c->chains[(size_t)chain];
+    const int64_t n_slots = 4LL * ci.K * ci.T, slot0 = c->price_off[(size_t)chain];
+    Scoped<float> S;
+    Scoped<uint8_t> Sel, Fb;
+    Scoped<int64_t> PP;
+    Scoped<int32_t> PS;
+    VNS_HIP(c, dmalloc(&S.p, (size_t)n_slots));
+    VNS_HIP(c, dmalloc(&Sel.p, (size_t)n_slots));
+    VNS_HIP(c, dmalloc(&Fb.p, (size_t)ci.K));
+    hipLaunchKernelGGL(k_fill_nan, dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, c->stream, S.p, n_slots);
+    VNS_HIP(c, hipGetLastError());
+    VNS_HIP(c, hipMemsetAsync(Sel.p, 0, (size_t)n_slots, c->stream));
+    VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, 2 * sizeof(unsigned long long), c->stream));
+    EvalLearnedArgs a{};
+    a.cp_chain = c->d_cp_chain;
+    a.chains = c->d_chains;
+    a.prod = c->d_prod;
+    a.rows = c->d_rows;
+    a.cur = c->d_cur;
+    a.cur_cost = c->d_cur_cost;
+    a.cstate = c->d_cs;
+    a.mlp = c->d_mlp;
+    a.slot_off = c->d_price_off;
+    a.scores = S.p - slot0;
+    a.selected = Sel.p - slot0;
+    a.prod_price = c->d_prod_price;
+    a.prod_slot = c->d_prod_slot;
+    a.fallback = Fb.p - ci.cp0;
+    a.evals = c->d_evals;
+    a.nb = nb;
+    a.permille = top_permille;
+    VNS_HIP(c, launch_eval_learned(a, ci.cp0, ci.K, c->stream));
+    if (scores) VNS_HIP(c, hipMemcpyAsync(scores, S.p, sizeof(float) * (size_t)n_slots, hipMemcpyDeviceToHost, c->stream));
+    if (selected) VNS_HIP(c, hipMemcpyAsync(selected, Sel.p, (size_t)n_slots, hipMemcpyDeviceToHost, c->stream));
+    if (prod_best) VNS_HIP(c, hipMemcpyAsync(prod_best, c->d_prod_price + ci.cp0, sizeof(int64_t) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
+    if (prod_best_slot) VNS_HIP(c, hipMemcpyAsync(prod_best_slot, c->d_prod_slot + ci.cp0, sizeof(int32_t) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
+    if (fallback) VNS_HIP(c, hipMemcpyAsync(fallback, Fb.p, (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
+    unsigned long long ev[2] = {0, 0};
+    VNS_HIP(c, hipMemcpyAsync(ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    c->stats.last_eval_evals = (int64_t)ev[0];
+    c->stats.last_eval_period_steps = (int64_t)ev[0] * ci.T;
+    return VNS_OK;
 }

@@ -1,0 +1,227 @@
+// Per-wavefront move search used by the search kernel and the learned pricing kernel: the move list of a
+// neighbourhood (all flips, or the compacted list of swaps of differing bits), the exact best move of a
+// neighbourhood (one lane per move), its learned variant (the scorer ranks the moves, the best-ranked are
+// priced exactly, the whole neighbourhood is priced if none of them improves) and the move log.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "vns_device.hpp"
+#include "vns_mlp.hpp"
+
+namespace vns {
+
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bit t of v set iff swapping bits t and t+1 of z is a move (t < T-1 and the bits differ).
+__device__ __forceinline__ void swap_valid(const uint32_t (&z)[kWords], int T, uint32_t (&v)[kWords]) {
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) {
+        const uint32_t next = (j + 1 < kWords) ? z[j + 1] : 0u;
+        const uint32_t d = z[j] ^ ((z[j] >> 1) | (next << 31));
+        const int lim = T - 1 - 32 * j;  // valid positions q < lim in this word
+        const uint32_t keep = lim >= 32 ? ~0u : (lim <= 0 ? 0u : ((1u << lim) - 1u));
+        v[j] = d & keep;
+    }
+}
+
+__device__ __forceinline__ int popc_words(const uint32_t (&v)[kWords]) {
+    int n = 0;
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) n += __popc(v[j]);
+    return n;
+}
+
+// Rank of bit t among the set bits of v, and whether it is set.
+__device__ __forceinline__ int rank_bit(const uint32_t (&v)[kWords], int t, bool &set) {
+    const int jt = t >> 5;
+    const uint32_t below = (1u << (t & 31)) - 1u;
+    int r = 0;
+    set = false;
+#pragma unroll
+    for (int j = 0; j < kWords; ++j) {
+        r += (j < jt) ? __popc(v[j]) : (j == jt ? __popc(v[j] & below) : 0);
+        set |= (j == jt) && ((v[j] >> (t & 31)) & 1u);
+    }
+    return r;
+}
+
+// One wavefront writes the local slots of the valid swaps of b (zM swaps, then zR swaps) to list and
+// returns how many there are.  The caller synchronises the wavefront before reading the list.
+__device__ __forceinline__ int build_swap_list(const Bits &b, int T, uint16_t *list, int lane) {
+    uint32_t vm[kWords], vr[kWords];
+    swap_valid(b.m, T, vm);
+    swap_valid(b.r, T, vr);
+    const int nm = popc_words(vm);
+    for (int t = lane; t < T - 1; t += 64) {
+        bool sm, sr;
+        const int pm = rank_bit(vm, t, sm);
+        const int pr = rank_bit(vr, t, sr);
+        if (sm) list[pm] = (uint16_t)(2 * T + t);
+        if (sr) list[nm + pr] = (uint16_t)(3 * T + t);
+    }
+    return nm + popc_words(vr);
+}
+
+
+// Slot of item idx of a neighbourhood's move list: flips first (zM or zR), then the compacted swaps.
+__device__ __forceinline__ int item_slot(int idx, int nflip, bool fm, int T, const uint16_t *list) {
+    return idx < nflip ? (fm ? idx : T + idx) : (int)list[idx - nflip];
+}
+
+// Builds the move list of one neighbourhood (nb: 1 flip zM, 2 flip zR, 4 shift) for the pattern b;
+// returns the number of moves, sets nflip / fm.  Synchronises the wavefront when it writes the list.
+__device__ __forceinline__ int move_list(const Bits &b, int T, uint32_t nb, uint16_t *list, int &nflip, bool &fm) {
+    const int lane = threadIdx.x & 63;
+    fm = nb & 1u;
+    nflip = (nb & 3u) ? T : 0;
+    int nswap = 0;
+    if (nb & 4u) {
+        nswap = build_swap_list(b, T, list, lane);
+        wave_sync_lds();
+    }
+    return nflip + nswap;
+}
+
+// Exact best move of one neighbourhood for one product, computed by one wavefront: key = cost << 16 | slot.
+// With `ident`, one more item prices the unchanged pattern and its cost is returned in *ident_cost.  With
+// contrast >= 0, *contrast_key receives the key of item contrast (kInfKey when infeasible).
+__device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *row, int T, const ProdParams &pp,
+                                                   uint32_t nb, uint16_t *list, bool ident, int64_t *ident_cost,
+                                                   int64_t &evals, int contrast = -1, uint64_t *contrast_key = nullptr,
+                                                   int *n_items = nullptr) {
+    const int lane = threadIdx.x & 63;
+    int nflip;
+    bool fm;
+    const int nitems = move_list(b, T, nb, list, nflip, fm);
+    if (n_items) *n_items = nitems;
+    const int total = nitems + (ident ? 1 : 0);
+    evals += nitems;
+    uint64_t best = kInfKey, ck = kInfKey;
+    int64_t idc = 0;
+    for (int basei = 0; basei < total; basei += 64) {
+        const int idx = basei + lane;
+        const int slot = idx < nitems ? item_slot(idx, nflip, fm, T, list) : -1;
+        Bits mb = b;
+        if (slot >= 0) apply_move(mb, slot, T);
+        const int64_t c = decode_cost(mb, row, T, pp);
+        if (idx == nitems) idc = c;
+        const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
+        if (idx == contrast) ck = key;
+        best = key < best ? key : best;
+    }
+    if (ident) *ident_cost = __shfl(idc, nitems & 63, 64);
+    if (contrast >= 0 && contrast_key) *contrast_key = __shfl(ck, contrast & 63, 64);
+    return wave_min_u64(best);
+}
+
+// Per-wavefront LDS of the learned search: the scorer's feature and hidden tiles and the selected moves.
+struct LearnedLds {
+    __bf16 *sx;        // [64][16]
+    __bf16 *sh;        // [64][64]
+    uint16_t *sel;     // [2 * kTMax]
+};
+
+// Learned best move of one neighbourhood (one wavefront).  The scorer ranks the moves (lowest score first,
+// ties to the lower slot), the best-ranked ceil(permille * n / 1000) (at least one) are priced exactly and
+// the best of them is returned if it is cheaper than `cost`; otherwise the whole neighbourhood is priced
+// exactly (fallback) and its best move is returned.  With `ident` the unchanged pattern is priced with the
+// selected moves and *cost is set to it first.  score_out / sel_out (indexed by slot, may be null) receive
+// the scores and the selection.
+__device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 *row, int T, const ProdParams &pp,
+                                                      uint32_t nb, uint16_t *list, const LearnedLds &L,
+                                                      const mlp::Frags &fr, const float *__restrict__ P, int permille,
+                                                      bool ident, int64_t &cost, int64_t &evals, int &fallback,
+                                                      float *score_out = nullptr, uint8_t *sel_out = nullptr) {
+    const int lane = threadIdx.x & 63;
+    int nflip;
+    bool fm;
+    const int nitems = move_list(b, T, nb, list, nflip, fm);
+    // 1. scores of every move, kept as (sortable score << 32 | slot) keys, up to four per lane
+    uint64_t sk[4] = {kInfKey, kInfKey, kInfKey, kInfKey};
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        if (ch * 64 >= nitems) break;
+        const int idx = ch * 64 + lane;
+        const int slot = idx < nitems ? item_slot(idx, nflip, fm, T, list) : 0;
+        float f[mlp::kF];
+        if (idx < nitems) {
+            mlp::move_features(b, row, T, pp, slot, f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < mlp::kF; ++i) f[i] = 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < mlp::kF; ++i) L.sx[lane * mlp::kF + i] = (__bf16)f[i];
+        wave_sync_lds();
+        const float s = mlp::forward64(L.sx, L.sh, fr, P);
+        if (idx < nitems) {
+            sk[ch] = ((uint64_t)mlp::sortable(s) << 32) | (uint64_t)slot;
+            if (score_out) score_out[slot] = s;
+        }
+    }
+    // 2. the best-ranked moves, by repeated wavefront minima
+    int n_sel = (permille * nitems + 999) / 1000;
+    n_sel = n_sel < 1 ? 1 : (n_sel > nitems ? nitems : n_sel);
+    for (int r = 0; r < n_sel; ++r) {
+        uint64_t my = sk[0];
+#pragma unroll
+        for (int ch = 1; ch < 4; ++ch) my = sk[ch] < my ? sk[ch] : my;
+        const uint64_t m = wave_min_u64(my);
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) sk[ch] = sk[ch] == m ? kInfKey : sk[ch];
+        if (lane == 0) L.sel[r] = (uint16_t)(m & 0xFFFFu);
+        if (sel_out && lane == 0) sel_out[m & 0xFFFFu] = 1;
+    }
+    wave_sync_lds();
+    // 3. exact prices of the selection (and of the unchanged pattern)
+    const int total = n_sel + (ident ? 1 : 0);
+    evals += n_sel;
+    uint64_t best = kInfKey;
+    int64_t idc = 0;
+    for (int basei = 0; basei < total; basei += 64) {
+        const int idx = basei + lane;
+        const int slot = idx < n_sel ? (int)L.sel[idx] : -1;
+        Bits mb = b;
+        if (slot >= 0) apply_move(mb, slot, T);
+        const int64_t c = decode_cost(mb, row, T, pp);
+        if (idx == n_sel) idc = c;
+        const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
+        best = key < best ? key : best;
+    }
+    if (ident) cost = __shfl(idc, n_sel & 63, 64);
+    best = wave_min_u64(best);
+    if (best != kInfKey && (int64_t)(best >> kSlotBits) < cost) {
+        fallback = 0;
+        return best;
+    }
+    // 4. fallback: the whole neighbourhood, exactly
+    fallback = 1;
+    return wave_best_move(b, row, T, pp, nb, list, false, nullptr, evals);
+}
+
+// Appends the records of an applied move and of a contrast move of the same neighbourhood to the move log:
+// 16 features each (w.r.t. the pattern b before the move) and the cost change / 1000.  One lane writes.
+template <class RowPtr>
+__device__ __forceinline__ void log_moves(const Bits &b, RowPtr row, int T, const ProdParams &pp, int slot_a, int64_t dc_a,
+                                          int slot_b, int64_t dc_b, float *log_x, float *log_y,
+                                          unsigned long long *log_n, int64_t cap) {
+    if ((threadIdx.x & 63) != 0 || cap <= 0) return;
+    const unsigned long long pos = atomicAdd(log_n, slot_b >= 0 ? 2ull : 1ull);
+    float f[mlp::kF];
+    if ((int64_t)pos < cap) {
+        mlp::move_features(b, row, T, pp, slot_a, f);
+        for (int i = 0; i < mlp::kF; ++i) log_x[pos * mlp::kF + i] = f[i];
+        log_y[pos] = (float)dc_a / 1000.f;
+    }
+    if (slot_b >= 0 && (int64_t)pos + 1 < cap) {
+        mlp::move_features(b, row, T, pp, slot_b, f);
+        for (int i = 0; i < mlp::kF; ++i) log_x[(pos + 1) * mlp::kF + i] = f[i];
+        log_y[pos + 1] = (float)dc_b / 1000.f;
+    }
+}
+
+}  // namespace vns

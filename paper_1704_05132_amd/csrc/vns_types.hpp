@@ -19,7 +19,8 @@ constexpr int kWords = 4;          // 32-bit words per setup row: T <= 128
 constexpr int kTMax = 32 * kWords;
 constexpr int kShakeMax = 64;
 constexpr int kMaxWaves = 8;
-constexpr int kEvalGroup = 16;     // chains of one instance priced by one k_eval workgroup
+constexpr int kEvalGroup = 16;
+constexpr int64_t kRunLdsMax = 128 * 1024;  // dynamic LDS the search kernel may request for instance rows     // chains of one instance priced by one k_eval workgroup
 constexpr int kMaxPasses = 1 << 16;  // VND passes per product and iteration: a guard, not a limit of the method
 constexpr int64_t kInf = INT64_MAX;
 constexpr uint64_t kInfKey = ~0ull;
@@ -54,6 +55,8 @@ struct ChainState {
     int32_t lopt;   // 1 when every product of x is known to be a VND local optimum
     int32_t err;    // nonzero if a VND exceeded kMaxPasses (cannot happen with a consistent decode)
     int32_t pad;
+    int64_t nb_evals;   // learned mode: neighbourhood evaluations during the last run
+    int64_t fallbacks;  //   and how many of them priced the whole neighbourhood
 };
 
 struct Record {    // identical layout to vns_record
@@ -71,14 +74,30 @@ struct RunArgs {
     int64_t *work_cost;
     ChainState *cstate;
     Record *trace;          // [G][iters] or nullptr
+    const int64_t *it0;     // device iteration counter: the first iteration of this launch
     uint64_t seed;
-    int64_t it0;
     int32_t iters;
     int32_t kmax;
     uint32_t nb_list;       // one neighbourhood id per nibble
     int32_t n_nb;
-    int32_t rows_in_lds;    // 1: the whole instance's rows are staged in LDS at kernel start
+    int32_t lds_rows;       // int2 entries of dynamic LDS for an instance's rows: a chain whose instance has
+                            // at most that many periods in total keeps them all in LDS for the whole launch
+    int32_t permille;       // learned scorer: price the best-ranked permille/1000 of each neighbourhood; 0 = off
+    const float *mlp;       // scorer parameters (5313 float32)
+    float *log_x;           // move log: [log_cap][16] features, [log_cap] targets, count (null = off)
+    float *log_y;
+    unsigned long long *log_n;
+    int64_t log_cap;
 };
+
+// Dynamic LDS of the search kernel: the rows region (int2 entries, an even number so that what follows is
+// 16-byte aligned), then per wavefront the learned-search tiles.
+constexpr int kLearnedWaveBytes = 64 * 16 * 2 + 64 * 64 * 2 + 2 * kTMax * 2;
+static_assert(kLearnedWaveBytes % 16 == 0, "learned tiles stay 16-byte aligned");
+__host__ __device__ inline int run_rows_entries(int lds_rows, int waves) {
+    const int e = lds_rows > waves * kTMax ? lds_rows : waves * kTMax;
+    return (e + 1) & ~1;
+}
 
 // One k_eval workgroup: product cp - chains[cp_chain[cp]].cp0 of the n consecutive chains starting with the
 // chain of cp (chains of one instance are consecutive, their products K apart).
@@ -99,7 +118,7 @@ struct EvalArgs {
     int64_t *slot_price;         // optional [sum over chains of 4*K*T]
     const int64_t *price_off;    // [G] offset of each chain's slot block in slot_price
     uint64_t *prod_key;          // [sum over chains of K]: cost << 16 | slot of each product's best move
-    unsigned long long *evals;   // device counter of move-evaluations
+    unsigned long long *evals;   // device counters: [0] move-evaluations, [1] their period-steps
     uint32_t nb_mask;
 };
 

@@ -19,7 +19,9 @@ LIB_PATH = _PKG / "libvns.so"
 
 VNS_OK, VNS_EINVAL, VNS_ENOMEM, VNS_EDEVICE, VNS_ERANGE, VNS_ESTATE = 0, -1, -2, -3, -4, -5
 NB_FLIP_M, NB_FLIP_R, NB_SHIFT = 1, 2, 4
-OPT_CHAINS, OPT_KMAX, OPT_NB_LIST, OPT_TRACE, OPT_RUN_WAVES, OPT_EVAL_GROUP = 1, 2, 3, 4, 5, 6
+OPT_CHAINS, OPT_KMAX, OPT_NB_LIST, OPT_TRACE, OPT_RUN_WAVES, OPT_EVAL_GROUP, OPT_RUN_LDS, OPT_GRAPH = 1, 2, 3, 4, 5, 6, 7, 8
+OPT_LEARNED, OPT_LOG = 9, 10
+MLP_PARAMS, MLP_FEATURES = 5313, 16
 ALL_CHAINS = -1
 PRICE_INF = np.iinfo(np.int64).max
 T_MAX = 128
@@ -45,6 +47,14 @@ SIGNATURES = {
     "vns_get_trajectory": (_c.c_int, [_P, _c.c_int32, _P, _c.c_int64, _c.POINTER(_c.c_int64)]),
     "vns_get_stats": (_c.c_int, [_P, _P]),
     "vns_instance_size": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    "vns_mlp_set_params": (_c.c_int, [_P, _P]),
+    "vns_mlp_get_params": (_c.c_int, [_P, _P]),
+    "vns_mlp_score": (_c.c_int, [_P, _P, _c.c_int64, _P]),
+    "vns_mlp_grad": (_c.c_int, [_P, _P, _P, _c.c_int64, _P, _c.POINTER(_c.c_float)]),
+    "vns_mlp_train": (_c.c_int, [_P, _P, _P, _c.c_int64, _c.c_int32, _c.c_int32, _c.c_float, _c.c_uint64,
+                                 _c.POINTER(_c.c_float)]),
+    "vns_get_move_log": (_c.c_int, [_P, _P, _P, _c.c_int64, _c.POINTER(_c.c_int64)]),
+    "vns_eval_learned": (_c.c_int, [_P, _c.c_uint32, _c.c_int32, _c.c_int32, _P, _P, _P, _P, _P]),
     "vns_num_chains": (_c.c_int64, [_P]),
     "vns_last_error": (_c.c_char_p, [_P]),
 }
@@ -53,7 +63,9 @@ SIGNATURES = {
 class VNSStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int64), ("move_evals", ctypes.c_int64), ("last_run_evals", ctypes.c_int64),
                 ("last_run_ms", ctypes.c_double), ("last_eval_evals", ctypes.c_int64),
-                ("last_eval_ms", ctypes.c_double)]
+                ("last_eval_ms", ctypes.c_double), ("last_run_period_steps", ctypes.c_int64),
+                ("last_eval_period_steps", ctypes.c_int64), ("last_run_learned_evals", ctypes.c_int64),
+                ("last_run_fallbacks", ctypes.c_int64)]
 
 
 class VNSError(RuntimeError):
@@ -92,7 +104,7 @@ class Context:
     """A search context: one or several instances, their chains, all state resident on the GPU."""
 
     def __init__(self, instances, seed: int, chains: int = 1, k_max: int = 5, nb_list: Sequence[int] = (1, 2, 4),
-                 trace: bool = True, run_waves: int | None = None):
+                 trace: bool = True, run_waves: int | None = None, options: dict | None = None):
         L = lib()
         insts = instances if isinstance(instances, (list, tuple)) else [instances]
         self.instances = list(insts)
@@ -126,6 +138,8 @@ class Context:
             self.set_option(OPT_TRACE, 0)
         if run_waves is not None:
             self.set_option(OPT_RUN_WAVES, run_waves)
+        for key, val in (options or {}).items():
+            self.set_option(key, val)
         self.chains_per_inst = int(chains)
 
     # -- plumbing ------------------------------------------------------------------------------------
@@ -215,6 +229,62 @@ class Context:
         if len(rec):
             self._check(lib().vns_get_trajectory(self.h, int(chain), _ptr(rec), len(rec), ctypes.byref(n)))
         return rec
+
+    # -- learned scorer ------------------------------------------------------------------------------
+    def mlp_set(self, params):
+        """params: flat float32[5313] or the list [W1, b1, W2, b2, W3, b3]."""
+        flat = np.ascontiguousarray(np.concatenate([np.ravel(p) for p in params]) if isinstance(params, (list, tuple))
+                                    else np.ravel(params), np.float32)
+        assert flat.size == MLP_PARAMS
+        self._check(lib().vns_mlp_set_params(self.h, _ptr(flat)))
+
+    def mlp_get(self):
+        out = np.empty(MLP_PARAMS, np.float32)
+        self._check(lib().vns_mlp_get_params(self.h, _ptr(out)))
+        return out
+
+    def mlp_score(self, feats):
+        X = np.ascontiguousarray(feats, np.float32).reshape(-1, MLP_FEATURES)
+        out = np.empty(len(X), np.float32)
+        self._check(lib().vns_mlp_score(self.h, _ptr(X), len(X), _ptr(out)))
+        return out
+
+    def mlp_grad(self, feats, targets):
+        X = np.ascontiguousarray(feats, np.float32).reshape(-1, MLP_FEATURES)
+        y = np.ascontiguousarray(targets, np.float32)
+        g = np.empty(MLP_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        self._check(lib().vns_mlp_grad(self.h, _ptr(X), _ptr(y), len(X), _ptr(g), ctypes.byref(loss)))
+        return float(loss.value), g
+
+    def mlp_train(self, feats, targets, epochs, batch=4096, lr=1e-3, seed=0):
+        X = np.ascontiguousarray(feats, np.float32).reshape(-1, MLP_FEATURES)
+        y = np.ascontiguousarray(targets, np.float32)
+        loss = ctypes.c_float()
+        self._check(lib().vns_mlp_train(self.h, _ptr(X), _ptr(y), len(X), int(epochs), int(batch), float(lr),
+                                        ctypes.c_uint64(seed), ctypes.byref(loss)))
+        return float(loss.value)
+
+    def move_log(self):
+        n = ctypes.c_int64()
+        self._check(lib().vns_get_move_log(self.h, None, None, 0, ctypes.byref(n)))
+        X = np.empty((int(n.value), MLP_FEATURES), np.float32)
+        y = np.empty(int(n.value), np.float32)
+        if len(y):
+            self._check(lib().vns_get_move_log(self.h, _ptr(X), _ptr(y), len(y), ctypes.byref(n)))
+        return X, y
+
+    def eval_learned(self, nb, chain, top_permille):
+        inst = self.chain_instance(chain)
+        n = 4 * inst.K * inst.T
+        sc = np.empty(n, np.float32)
+        sel = np.empty(n, np.uint8)
+        pb = np.empty(inst.K, np.int64)
+        ps = np.empty(inst.K, np.int32)
+        fb = np.empty(inst.K, np.uint8)
+        self._check(lib().vns_eval_learned(self.h, int(nb), int(chain), int(top_permille), _ptr(sc), _ptr(sel),
+                                           _ptr(pb), _ptr(ps), _ptr(fb)))
+        return dict(scores=sc, selected=sel, prod_best=pb, prod_best_slot=ps, fallback=fb)
 
     def stats(self) -> dict:
         s = VNSStats()

@@ -1,0 +1,30 @@
+"""Autotuner selection and persistence (CPU only: the measurement is injected)."""
+import numpy as np
+
+from paper_1704_05132_amd import autotune
+from paper_1704_05132_amd.instances import draw_instance
+
+
+def test_pick_returns_fastest_and_all_timings():
+    times = {2: 5.0, 4: 3.0, 8: 3.0}
+    best, timings = autotune.pick([dict(waves=w) for w in (2, 4, 8)], lambda c: times[c["waves"]])
+    assert best == {"waves": 4}               # ties keep the earlier candidate
+    assert [ms for _, ms in timings] == [5.0, 3.0, 3.0]
+
+
+def test_signature_distinguishes_workloads():
+    rng = np.random.default_rng(1)
+    a = [draw_instance(rng, 10, 12), draw_instance(rng, 30, 52)]
+    b = [draw_instance(rng, 10, 12), draw_instance(rng, 30, 24)]
+    assert autotune.signature(a, 8) == "n2_K10-30_T12-52_c8"
+    assert autotune.signature(a, 8) != autotune.signature(b, 8)
+    assert autotune.signature(a, 8) != autotune.signature(a, 16)
+
+
+def test_table_round_trip(tmp_path):
+    t = autotune.TuneTable(tmp_path / "tune.json")
+    assert t.get("k") is None
+    t.put("k", {"waves": 4, "lds": 0}, [({"waves": 4, "lds": 0}, 1.5)])
+    t2 = autotune.TuneTable(tmp_path / "tune.json")
+    assert t2.get("k")["choice"] == {"waves": 4, "lds": 0}
+    assert t2.get("k")["timings_ms"] == [[{"waves": 4, "lds": 0}, 1.5]]

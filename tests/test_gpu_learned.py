@@ -1,0 +1,201 @@
+"""GPU: the learned move scorer against its float64 oracle, and the learned search's rules.
+
+  * scores (bfloat16 MFMA forward, float32 accumulation) against the oracle's float64 forward with the same
+    bfloat16 rounding: relative error bound 1e-2 (one bfloat16 step of a hidden activation, 2^-8, can move a
+    score by about that much when a float32 sum and a float64 sum round to neighbouring bfloat16 values);
+  * gradients of the device backward against the oracle's float64 gradients (same rounding, straight-through);
+  * training on the device lowers the loss;
+  * learned pricing of a neighbourhood (vns_eval_learned): every score matches the oracle's score of the
+    oracle's features of that move; the selection is the best-ranked ceil(p n / 1000) by the device scores
+    (ties to the lower slot); the chosen move is the exact argmin of the selection when it improves, and the
+    exact argmin of the whole neighbourhood (fallback) otherwise; all prices exact;
+  * a learned search ends in a local optimum of every neighbourhood, with exact objective values;
+  * a trained scorer falls back less, and prices fewer moves exactly, than an untrained one.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as L
+from paper_1704_05132_amd.instances import draw_instance, workload
+
+pytestmark = pytest.mark.gpu
+INF = oracle.INF
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def vns():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1704_05132_amd import vns as v
+    return v
+
+
+def random_params(seed):
+    rng = np.random.default_rng(seed)
+    ps = L.init_params(seed)
+    ps[1] = rng.normal(0, 0.2, 64).astype(np.float32)
+    ps[3] = rng.normal(0, 0.2, 64).astype(np.float32)
+    ps[5] = np.float32([0.3])
+    return ps
+
+
+def test_scores_match_oracle(vns):
+    inst = workload("plain_10x12")
+    rng = np.random.default_rng(51)
+    X = rng.uniform(0, 1, (1000 + 37, 16)).astype(np.float32)    # several waves and a ragged tail
+    params = random_params(52)
+    with vns.Context(inst, seed=1) as ctx:
+        ctx.mlp_set(params)
+        assert (ctx.mlp_get() == np.concatenate([np.ravel(p) for p in params])).all()
+        got = ctx.mlp_score(X)
+    ref, _ = L.forward(X, params, quantize=True)
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    say(f"  score max rel err {err.max():.2e}, median {np.median(err):.2e}")
+    assert err.max() < 1e-2
+    assert np.median(err) < 1e-5
+
+
+def test_gradients_match_oracle(vns):
+    inst = workload("plain_10x12")
+    rng = np.random.default_rng(53)
+    X = rng.uniform(0, 1, (300, 16)).astype(np.float32)
+    y = rng.normal(0, 1, 300).astype(np.float32)
+    params = random_params(54)
+    with vns.Context(inst, seed=1) as ctx:
+        ctx.mlp_set(params)
+        loss, g = ctx.mlp_grad(X, y)
+    rl, rg = L.loss_and_grads(X, y, params, quantize=True)
+    assert abs(loss - rl) <= 1e-3 * max(1.0, abs(rl))
+    off = 0
+    for i, r in enumerate(rg):
+        r = np.ravel(r)
+        gi = g[off:off + r.size]
+        off += r.size
+        scale = max(np.abs(r).max(), 1e-6)
+        assert np.abs(gi - r).max() <= 2e-2 * scale, (i, np.abs(gi - r).max(), scale)
+
+
+def test_training_lowers_the_loss(vns):
+    inst = workload("plain_10x12")
+    rng = np.random.default_rng(55)
+    X = rng.uniform(0, 1, (5000, 16)).astype(np.float32)
+    y = (X[:, 6] - 2 * X[:, 14] + X[:, 0] * X[:, 10]).astype(np.float32)
+    with vns.Context(inst, seed=1) as ctx:
+        ctx.mlp_set(L.init_params(56))
+        l0, _ = ctx.mlp_grad(X, y)
+        ctx.mlp_train(X, y, epochs=20, batch=512, lr=3e-3, seed=1)
+        l1, _ = ctx.mlp_grad(X, y)
+    say(f"  loss {l0:.4f} -> {l1:.4f}")
+    assert l1 < 0.2 * l0
+
+
+def sortable(x):
+    """The device's order of scores: float order, with -0 before +0."""
+    u = int(np.float32(x).view(np.uint32))
+    return (~u) & 0xFFFFFFFF if u & 0x80000000 else u | 0x80000000
+
+
+def _check_learned_eval(vns, ctx, inst, chain, nb, permille):
+    out = ctx.eval_learned(nb, chain, permille)
+    zM, zR = ctx.solution(chain)
+    F, cost = oracle.objective(inst, zM, zR)
+    price, _ = oracle.price_all(inst, zM, zR, nb)
+    params = ctx.mlp_get()
+    ps = [params[0:1024].reshape(16, 64), params[1024:1088], params[1088:5184].reshape(64, 64), params[5184:5248],
+          params[5248:5312].reshape(64, 1), params[5312:5313]]
+    T = inst.T
+    n_fallback = 0
+    for k in range(inst.K):
+        base = 4 * T * k
+        slots = [l for l in range(4 * T) if oracle.apply_slot(T, zM[k], zR[k], l)[0] and
+                 (oracle.learned.move_type(T, l) in {1: (0,), 2: (1,), 4: (2, 3)}[nb])]
+        sc = out["scores"][base:base + 4 * T]
+        assert np.isnan(np.delete(sc, slots)).all()
+        if not slots:                     # no move in this neighbourhood (e.g. no differing adjacent bits)
+            assert not out["selected"][base:base + 4 * T].any()
+            assert (int(out["prod_best"][k]), int(out["prod_best_slot"][k])) == (INF, -1)
+            continue
+        feats = np.array([L.move_features(inst, k, zM[k], zR[k], l) for l in slots])
+        ref, _ = L.forward(feats, ps, quantize=True)
+        got = sc[slots]
+        assert (np.abs(got - ref) <= 1e-2 * np.maximum(1.0, np.abs(ref))).all(), k
+        # selection: best-ranked by the device scores, ties to the lower slot
+        n_sel = min(len(slots), max(1, -(-permille * len(slots) // 1000)))
+        order = sorted(slots, key=lambda l: (sortable(sc[l]), l))
+        sel = set(order[:n_sel])
+        assert set(np.flatnonzero(out["selected"][base:base + 4 * T])) == sel, k
+        prices = price[base:base + 4 * T]
+        best_sel = min(((prices[l], l) for l in sel), default=(INF, -1))
+        if best_sel[0] < F:
+            assert out["fallback"][k] == 0
+            expect = best_sel
+        else:
+            assert out["fallback"][k] == 1
+            n_fallback += 1
+            fin = [(prices[l], l) for l in slots if prices[l] != INF]
+            expect = min(fin) if fin else (INF, -1)
+        assert (int(out["prod_best"][k]), int(out["prod_best_slot"][k])) == expect, k
+    return n_fallback
+
+
+@pytest.mark.parametrize("nb,permille", [(1, 100), (2, 100), (4, 100), (4, 300), (1, 1000)])
+def test_learned_eval_rules(vns, nb, permille):
+    inst = draw_instance(np.random.default_rng([57, nb, permille]), 6, 37)
+    with vns.Context(inst, seed=5) as ctx:
+        ctx.mlp_set(random_params(58))
+        say(f"  learned eval nb={nb} permille={permille} (initial solution)")
+        _check_learned_eval(vns, ctx, inst, 0, nb, permille)
+        ctx.run(3)
+        say(f"  learned eval nb={nb} permille={permille} (after 3 iterations)")
+        _check_learned_eval(vns, ctx, inst, 0, nb, permille)
+
+
+def test_learned_search_ends_in_local_optima(vns):
+    inst = workload("plain_10x12")
+    with vns.Context(inst, seed=1, chains=4, options={vns.OPT_LEARNED: 100}) as ctx:
+        ctx.mlp_set(random_params(59))
+        ctx.run(30)
+        st = ctx.stats()
+        assert st["last_run_learned_evals"] > 0
+        for g in range(4):
+            zM, zR = ctx.solution(g)
+            F, Fb = ctx.cost(g)
+            assert F == oracle.objective(inst, zM, zR)[0] and F == Fb
+            price, _ = oracle.price_all(inst, zM, zR, 7)
+            assert price.min() >= F
+            rec = ctx.trajectory(g)
+            assert (rec["F_local"] <= rec["F_shaken"]).all()
+            # accepted iff the VND result beats the solution before the iteration (the best so far)
+            assert ((rec["accepted"][1:] == 1) == (rec["F_local"][1:] < rec["F_best"][:-1])).all()
+
+
+def test_move_log_and_trained_scorer_gain(vns):
+    train = [workload("learned_100x52", 100 + j) for j in range(2)]
+    target = workload("learned_100x52", 0)
+    with vns.Context(train, seed=4, chains=8, options={vns.OPT_LOG: 400000}) as ctx:
+        ctx.run(60)
+        X, y = ctx.move_log()
+    say(f"  logged {len(y)} moves, {np.mean(y < 0):.2f} improving")
+    assert len(y) > 1000 and (y < 0).mean() > 0.3
+    assert (X[:, :4].sum(1) == 1).all() and (X[:, 14:] >= 0).all() and (X[:, 14:] <= 1).all()
+    results = {}
+    for name in ("untrained", "trained"):
+        with vns.Context(target, seed=4, chains=16, options={vns.OPT_LEARNED: 100}) as ctx:
+            ctx.mlp_set(L.init_params(60))
+            if name == "trained":
+                loss = ctx.mlp_train(X, y, epochs=10, batch=2048, lr=2e-3, seed=3)
+                say(f"  trained loss {loss:.4f}")
+            ctx.run(40)
+            st = ctx.stats()
+            results[name] = (st["last_run_fallbacks"] / st["last_run_learned_evals"], st["last_run_evals"])
+            say(f"  {name}: fallback rate {results[name][0]:.3f}, exact evaluations {results[name][1]}")
+    assert results["trained"][0] < results["untrained"][0]
+    assert results["trained"][1] < results["untrained"][1]
