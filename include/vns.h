@@ -77,9 +77,16 @@ enum vns_option {
                               the scorer ranks the moves, the best-ranked ceil(p*n/1000) are priced
                               exactly and the best of them is applied if it improves, otherwise the whole
                               neighbourhood is priced exactly and its best move applied if it improves   */
-    VNS_OPT_LOG = 10       /* move-log capacity in records (0 = off, default); a plain vns_run appends, for
+    VNS_OPT_LOG = 10,      /* move-log capacity in records (0 = off, default); a plain vns_run appends, for
                               every applied move, its features and cost change and those of one other
                               priced move of the same evaluation                                       */
+    VNS_OPT_SPECULATE = 11, /* plain search only: 1 (default) = each product's VND runs on a group of
+                              wavefronts, one per neighbourhood of the list, pricing the neighbourhoods
+                              not yet settled in the current pass side by side and applying, in list
+                              order, the first improving one (the others are priced again); the moves
+                              applied are those of the sequential pass and only consumed evaluations
+                              are counted.  0 = one wavefront per product, neighbourhoods in turn      */
+    VNS_OPT_SPEC_WAVES = 12 /* wavefronts per workgroup of the speculative search, 1..16 (default 16)   */
 };
 
 /* One GVNS iteration of one chain. */

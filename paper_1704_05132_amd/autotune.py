@@ -1,9 +1,10 @@
 """Autotuner for the launch shape of the search and pricing kernels.
 
 The search kernel runs one workgroup per chain; how many wavefronts a workgroup has (so how many of a
-chain's products run their VND side by side) and how much LDS it may use to keep an instance's rows
-resident trade occupancy against parallelism, and the best choice depends on K, T and the number of
-chains.  The pricing kernel's tuning knob is how many chains of an instance share one workgroup.  Results
+chain's products run their VND side by side), whether the neighbourhoods of one product's VND are priced
+side by side by a group of wavefronts (speculative VND, `spec`) and how much LDS it may use to keep an
+instance's rows resident trade occupancy against parallelism, and the best choice depends on K, T and the
+number of chains.  The pricing kernel's tuning knob is how many chains of an instance share one workgroup.  Results
 never depend on these choices (the kernels compute the same exact costs and trajectories); only time does.
 
 `tune_search` and `tune_eval` time each candidate on the actual workload with the library's own device
@@ -15,7 +16,8 @@ import json
 from pathlib import Path
 from typing import Callable, Iterable, Sequence
 
-SEARCH_CANDIDATES = [dict(waves=w, lds=l) for w in (2, 4, 8) for l in (0, 65536)]
+SEARCH_CANDIDATES = ([dict(waves=w, lds=l, spec=0) for w in (2, 4, 8) for l in (0, 65536)] +
+                     [dict(spec=1, spec_waves=s, lds=l) for s in (6, 9, 15) for l in (0, 65536)])
 EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 4, 8, 16)]
 
 
@@ -40,16 +42,31 @@ def pick(candidates: Iterable[dict], measure: Callable[[dict], float]):
 
 def tune_search(instances, seed: int, chains: int, nb_list: Sequence[int] = (1, 2, 4), iters: int = 20,
                 candidates: Sequence[dict] = tuple(SEARCH_CANDIDATES)):
-    """Time the first `iters` GVNS iterations (one launch, fresh context) for each (waves, lds) candidate."""
+    """Time the first `iters` GVNS iterations (one launch, fresh context) for each launch-shape candidate."""
     from . import vns
 
     def measure(c):
         with vns.Context(instances, seed=seed, chains=chains, nb_list=nb_list, trace=False,
-                         options={vns.OPT_RUN_WAVES: c["waves"], vns.OPT_RUN_LDS: c["lds"]}) as ctx:
+                         options=search_options(c)) as ctx:
             ctx.run(iters)
             return ctx.stats()["last_run_ms"]
 
     return pick(candidates, measure)
+
+
+def search_options(c: dict) -> dict:
+    """Context options of a search candidate (keys waves, lds, spec, spec_waves; missing keys keep defaults)."""
+    from . import vns
+    opts = {}
+    if "waves" in c:
+        opts[vns.OPT_RUN_WAVES] = c["waves"]
+    if "lds" in c:
+        opts[vns.OPT_RUN_LDS] = c["lds"]
+    if "spec" in c:
+        opts[vns.OPT_SPECULATE] = c["spec"]
+    if "spec_waves" in c:
+        opts[vns.OPT_SPEC_WAVES] = c["spec_waves"]
+    return opts
 
 
 def tune_eval(ctx, nb_mask: int = 7, reps: int = 5, candidates: Sequence[dict] = tuple(EVAL_CANDIDATES)):
@@ -90,10 +107,8 @@ class TuneTable:
         if not e:
             return False
         ch = e["choice"]
-        if "waves" in ch:
-            ctx.set_option(vns.OPT_RUN_WAVES, ch["waves"])
-        if "lds" in ch:
-            ctx.set_option(vns.OPT_RUN_LDS, ch["lds"])
+        for opt, v in search_options(ch).items():
+            ctx.set_option(opt, v)
         if "group" in ch:
             ctx.set_option(vns.OPT_EVAL_GROUP, ch["group"])
         return True

@@ -216,7 +216,30 @@ struct RunShared {
     int32_t nd;
 };
 
-__device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 *s_rows) {
+// Speculative VND (plain search): each product in work is handled by a group of n_nb wavefronts, one per
+// neighbourhood of the list.  In every round the neighbourhoods not yet settled in the current pass are
+// priced in parallel on the group's current pattern; the group's leader then walks them in list order and
+// applies the first strictly improving best move; results priced after an applied move are stale and are
+// priced again in the next round on the new pattern.  The moves applied, and so the result, are those of
+// the sequential pass of Algorithm 1; only the consumed evaluations are counted.
+struct SpecGroup {
+    Bits b;               // current pattern of the group's product
+    int64_t cost;         // its exact cost (kInf until the unchanged pattern of a shaken product is priced)
+    int64_t c_cur;        // cost of the product in x (before the shake)
+    uint64_t res[4];      // best-move key of each neighbourhood priced this round
+    uint64_t ck[4];       // contrast keys for the move log
+    int64_t idc;          // cost of the unchanged pattern (first round of a shaken product)
+    int32_t cnt[4];       // moves priced per neighbourhood this round
+    int32_t p, q, improved, active, need_ident, passes;
+};
+
+struct SpecShared {
+    SpecGroup grp[kMaxWaves];
+    int32_t next;         // next product index to hand out
+};
+
+template <bool SPEC>
+__device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecShared &sp, int2 *s_rows) {
     const int g = blockIdx.x;
     const ChainInfo ci = a.chains[g];
     const int K = ci.K, T = ci.T;
@@ -243,7 +266,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
     LearnedLds L{reinterpret_cast<__bf16 *>(lbase), reinterpret_cast<__bf16 *>(lbase + 64 * 16 * 2),
                  reinterpret_cast<uint16_t *>(lbase + 64 * 16 * 2 + 64 * 64 * 2)};
     mlp::Frags fr;
-    if (a.permille > 0) mlp::load_frags(a.mlp, fr);
+    if constexpr (!SPEC) {
+        if (a.permille > 0) mlp::load_frags(a.mlp, fr);
+    }
     const uint64_t nflip_all = 2ull * (uint64_t)K * (uint64_t)T;
 
     for (int i = 0; i < a.iters; ++i) {
@@ -279,93 +304,218 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
         __syncthreads();
         const int nd = sh.nd;
 
-        // ---- VND (Algorithm 1) per product: the shaken products, or every product until x is known to
-        //      be a local optimum ----
-        const int nprod = cs.lopt ? nd : K;
+        // ---- speculative VND: groups of n_nb wavefronts, one neighbourhood each ----
         int64_t part = 0, shk = 0;
-        for (int idx = wave; idx < nprod; idx += W) {
-            int p, e = -1;
-            if (cs.lopt) {
-                p = sh.dp[idx];
-                e = idx;
-            } else {
-                p = idx;
-                for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
-            }
-            const int64_t cp = cp0 + p;
-            const ProdParams pp = a.prod[ci.prod0 + p];
-            const int2 *row;
-            if (rows_in_lds) {
-                row = s_rows + p * T;
-            } else {
-                int2 *slice = s_rows + wave * kTMax;
-                for (int t = lane; t < T; t += 64) slice[t] = inst_rows[p * T + t];
-                wave_sync_lds();
-                row = slice;
-            }
-            Bits b = e >= 0 ? sh.db[e] : a.work[cp];
-            const int64_t c_cur = a.cur_cost[cp];
-            int64_t cost = e >= 0 ? kInf : a.work_cost[cp];   // a shaken product is priced with its first move list
-            bool need_ident = e >= 0;
-            bool improved = true;
-            int passes = 0;
-            while (improved) {
-                if (++passes > kMaxPasses) {
-                    vnd_err = 1;
-                    break;
+        if constexpr (SPEC) {
+            const int nprod = cs.lopt ? nd : K;
+            const int gsz = a.n_nb, G = W / gsz;
+            const int gid = wave / gsz, role = wave - gid * gsz;
+            int staged = -1;   // product whose row this wavefront holds in its LDS slice (uniform)
+            // hands the group its next product (one lane)
+            auto take = [&](SpecGroup &gr) {
+                const int idx = atomicAdd(&sp.next, 1);
+                if (idx >= nprod) {
+                    gr.active = 0;
+                    return;
                 }
-                improved = false;
-                for (int q = 0; q < a.n_nb; ++q) {
-                    const uint32_t nb = (a.nb_list >> (4 * q)) & 0xFu;
-                    uint64_t key, ckey = kInfKey;
-                    int nitems = 0;
-                    // contrast move for the log: a fixed pseudo-random item of this evaluation
-                    const int chash = a.log_x ? (int)(((uint32_t)it * 2654435761u + (uint32_t)p * 40503u +
-                                                       (uint32_t)(q + 4 * passes) * 97u) & 0x7FFFFFFFu) : -1;
-                    if (a.permille > 0) {
-                        int fb = 0;
-                        const bool id = need_ident;
-                        key = learned_best_move(b, row, T, pp, nb, sh.list[wave], L, fr, a.mlp, a.permille, id, cost,
-                                                evals, fb);
-                        ++nb_evals;
-                        fallbacks += fb;
-                        if (id) {
-                            shk += cost - c_cur;
-                            need_ident = false;
-                        }
+                int p, e = -1;
+                if (cs.lopt) {
+                    p = sh.dp[idx];
+                    e = idx;
+                } else {
+                    p = idx;
+                    for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
+                }
+                const int64_t cp = cp0 + p;
+                gr.p = p;
+                gr.b = e >= 0 ? sh.db[e] : a.work[cp];
+                gr.c_cur = a.cur_cost[cp];
+                gr.cost = e >= 0 ? kInf : a.work_cost[cp];
+                gr.need_ident = e >= 0;
+                gr.q = 0;
+                gr.improved = 0;
+                gr.passes = 0;
+                gr.active = 1;
+            };
+            if (threadIdx.x == 0) sp.next = 0;
+            __syncthreads();
+            if (gid < G && role == 0 && lane == 0) take(sp.grp[gid]);
+            __syncthreads();
+            for (int round = 0;; ++round) {
+                bool any = false;
+                for (int gg = 0; gg < G; ++gg) any |= sp.grp[gg].active != 0;
+                if (!any) break;
+                // pricing: every neighbourhood not settled in this pass, on the group's current pattern
+                if (gid < G && sp.grp[gid].active && role >= sp.grp[gid].q) {
+                    SpecGroup &gr = sp.grp[gid];
+                    const int p = gr.p;
+                    const ProdParams pp = a.prod[ci.prod0 + p];
+                    const int2 *row;
+                    if (rows_in_lds) {
+                        row = s_rows + p * T;
                     } else {
-                        int64_t idc = 0;
-                        key = wave_best_move(b, row, T, pp, nb, sh.list[wave], need_ident, &idc, evals, chash, &ckey,
-                                             &nitems);
-                        if (need_ident) {
-                            cost = idc;
-                            shk += idc - c_cur;
-                            need_ident = false;
+                        int2 *slice = s_rows + wave * kTMax;
+                        if (staged != p) {
+                            for (int t = lane; t < T; t += 64) slice[t] = inst_rows[p * T + t];
+                            wave_sync_lds();
+                            staged = p;
                         }
+                        row = slice;
                     }
-                    if (key != kInfKey) {
-                        const int64_t c = (int64_t)(key >> kSlotBits);
-                        if (c < cost) {
+                    const uint32_t nb = (a.nb_list >> (4 * role)) & 0xFu;
+                    const bool id = gr.need_ident && role == gr.q;
+                    const int chash = a.log_x ? (int)(((uint32_t)it * 2654435761u + (uint32_t)p * 40503u +
+                                                       (uint32_t)(role + 4 * gr.passes) * 97u) & 0x7FFFFFFFu) : -1;
+                    int64_t idc = 0, dummy = 0;
+                    uint64_t ckey = kInfKey;
+                    int nitems = 0;
+                    const Bits b = gr.b;
+                    const uint64_t key = wave_best_move(b, row, T, pp, nb, sh.list[wave], id, &idc, dummy, chash, &ckey,
+                                                        &nitems);
+                    if (lane == 0) {
+                        gr.res[role] = key;
+                        gr.ck[role] = ckey;
+                        gr.cnt[role] = nitems;
+                        if (id) gr.idc = idc;
+                    }
+                }
+                __syncthreads();
+                // resolution in list order by the group's leader lane
+                if (gid < G && role == 0 && lane == 0 && sp.grp[gid].active) {
+                    SpecGroup &gr = sp.grp[gid];
+                    if (gr.need_ident) {
+                        gr.cost = gr.idc;
+                        shk += gr.idc - gr.c_cur;
+                        gr.need_ident = 0;
+                    }
+                    bool applied = false;
+                    for (int j = gr.q; j < gsz; ++j) {
+                        evals += gr.cnt[j];
+                        const uint64_t key = gr.res[j];
+                        if (key != kInfKey && (int64_t)(key >> kSlotBits) < gr.cost) {
                             const int slot = (int)(key & ((1u << kSlotBits) - 1));
-                            if (a.log_x && a.permille == 0) {
-                                const bool has_c = ckey != kInfKey && ckey != key;
-                                log_moves(b, row, T, pp, slot, c - cost, has_c ? (int)(ckey & 0xFFFFu) : -1,
-                                          has_c ? (int64_t)(ckey >> kSlotBits) - cost : 0, a.log_x, a.log_y, a.log_n,
+                            const int64_t c = (int64_t)(key >> kSlotBits);
+                            if (a.log_x) {
+                                const ProdParams pp = a.prod[ci.prod0 + gr.p];
+                                const uint64_t ck = gr.ck[j];
+                                const bool has_c = ck != kInfKey && ck != key;
+                                const int2 *row = rows_in_lds ? s_rows + gr.p * T : inst_rows + gr.p * T;
+                                log_moves(gr.b, row, T, pp, slot, c - gr.cost, has_c ? (int)(ck & 0xFFFFu) : -1,
+                                          has_c ? (int64_t)(ck >> kSlotBits) - gr.cost : 0, a.log_x, a.log_y, a.log_n,
                                           a.log_cap);
                             }
-                            apply_move(b, slot, T);
-                            cost = c;
-                            improved = true;
+                            apply_move(gr.b, slot, T);
+                            gr.cost = c;
+                            gr.improved = 1;
+                            gr.q = j + 1;
+                            applied = true;
+                            break;
                         }
                     }
-                    wave_sync_lds();
+                    if (!applied || gr.q == gsz) {   // the pass is over
+                        if (gr.improved && ++gr.passes <= kMaxPasses) {
+                            gr.q = 0;
+                            gr.improved = 0;
+                        } else {
+                            if (gr.improved) vnd_err = 1;
+                            const int64_t cp = cp0 + gr.p;
+                            a.work[cp] = gr.b;
+                            a.work_cost[cp] = gr.cost;
+                            part += gr.cost - gr.c_cur;
+                            take(gr);
+                        }
+                    }
                 }
+                __syncthreads();
             }
-            if (lane == 0) {
-                a.work[cp] = b;
-                a.work_cost[cp] = cost;
+        } else {
+            // ---- VND (Algorithm 1) per product: the shaken products, or every product until x is known to
+            //      be a local optimum ----
+            const int nprod = cs.lopt ? nd : K;
+            for (int idx = wave; idx < nprod; idx += W) {
+                int p, e = -1;
+                if (cs.lopt) {
+                    p = sh.dp[idx];
+                    e = idx;
+                } else {
+                    p = idx;
+                    for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
+                }
+                const int64_t cp = cp0 + p;
+                const ProdParams pp = a.prod[ci.prod0 + p];
+                const int2 *row;
+                if (rows_in_lds) {
+                    row = s_rows + p * T;
+                } else {
+                    int2 *slice = s_rows + wave * kTMax;
+                    for (int t = lane; t < T; t += 64) slice[t] = inst_rows[p * T + t];
+                    wave_sync_lds();
+                    row = slice;
+                }
+                Bits b = e >= 0 ? sh.db[e] : a.work[cp];
+                const int64_t c_cur = a.cur_cost[cp];
+                int64_t cost = e >= 0 ? kInf : a.work_cost[cp];   // a shaken product is priced with its first move list
+                bool need_ident = e >= 0;
+                bool improved = true;
+                int passes = 0;
+                while (improved) {
+                    if (++passes > kMaxPasses) {
+                        vnd_err = 1;
+                        break;
+                    }
+                    improved = false;
+                    for (int q = 0; q < a.n_nb; ++q) {
+                        const uint32_t nb = (a.nb_list >> (4 * q)) & 0xFu;
+                        uint64_t key, ckey = kInfKey;
+                        int nitems = 0;
+                        // contrast move for the log: a fixed pseudo-random item of this evaluation
+                        const int chash = a.log_x ? (int)(((uint32_t)it * 2654435761u + (uint32_t)p * 40503u +
+                                                           (uint32_t)(q + 4 * passes) * 97u) & 0x7FFFFFFFu) : -1;
+                        if (!SPEC && a.permille > 0) {
+                            int fb = 0;
+                            const bool id = need_ident;
+                            key = learned_best_move(b, row, T, pp, nb, sh.list[wave], L, fr, a.mlp, a.permille, id, cost,
+                                                    evals, fb);
+                            ++nb_evals;
+                            fallbacks += fb;
+                            if (id) {
+                                shk += cost - c_cur;
+                                need_ident = false;
+                            }
+                        } else {
+                            int64_t idc = 0;
+                            key = wave_best_move(b, row, T, pp, nb, sh.list[wave], need_ident, &idc, evals, chash, &ckey,
+                                                 &nitems);
+                            if (need_ident) {
+                                cost = idc;
+                                shk += idc - c_cur;
+                                need_ident = false;
+                            }
+                        }
+                        if (key != kInfKey) {
+                            const int64_t c = (int64_t)(key >> kSlotBits);
+                            if (c < cost) {
+                                const int slot = (int)(key & ((1u << kSlotBits) - 1));
+                                if (a.log_x && a.permille == 0) {
+                                    const bool has_c = ckey != kInfKey && ckey != key;
+                                    log_moves(b, row, T, pp, slot, c - cost, has_c ? (int)(ckey & 0xFFFFu) : -1,
+                                              has_c ? (int64_t)(ckey >> kSlotBits) - cost : 0, a.log_x, a.log_y, a.log_n,
+                                              a.log_cap);
+                                }
+                                apply_move(b, slot, T);
+                                cost = c;
+                                improved = true;
+                            }
+                        }
+                        wave_sync_lds();
+                    }
+                }
+                if (lane == 0) {
+                    a.work[cp] = b;
+                    a.work_cost[cp] = cost;
+                }
+                part += cost - c_cur;
             }
-            part += cost - c_cur;
         }
         if (lane == 0) {
             sh.part[wave] = part;
@@ -443,8 +593,16 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, int2 
 
 __global__ __launch_bounds__(512) void k_run(RunArgs a) {
     __shared__ RunShared sh;
+    __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
-    run_chain(a, sh, s_rows);
+    run_chain<false>(a, sh, sp, s_rows);
+}
+
+__global__ __launch_bounds__(1024) void k_run_spec(RunArgs a) {
+    __shared__ RunShared sh;
+    __shared__ SpecShared sp;
+    extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
+    run_chain<true>(a, sh, sp, s_rows);
 }
 
 // ---------------------------------------------------------------------------------------------------
@@ -513,18 +671,22 @@ hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64
     return hipGetLastError();
 }
 
-hipError_t run_kernel_lds(size_t *static_bytes, size_t dynamic_bytes) {
+hipError_t run_kernel_lds(bool spec, size_t *static_bytes, size_t dynamic_bytes) {
+    const void *fn = spec ? reinterpret_cast<const void *>(&k_run_spec) : reinterpret_cast<const void *>(&k_run);
     hipFuncAttributes fa;
-    hipError_t e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_run));
+    hipError_t e = hipFuncGetAttributes(&fa, fn);
     if (e != hipSuccess) return e;
     *static_bytes = fa.sharedSizeBytes;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)dynamic_bytes);
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes);
 }
 
-hipError_t launch_run(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter, hipStream_t s) {
+hipError_t launch_run(const RunArgs &a, bool spec, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
+                      hipStream_t s) {
     if (n_chains <= 0 || a.iters <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_run, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
+    if (spec)
+        hipLaunchKernelGGL(k_run_spec, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL(k_run, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, it_counter, a.iters);

@@ -31,8 +31,9 @@ struct ChainBestArgs {
     int32_t chain0;
 };
 
-// Static LDS bytes of the search kernel, and permission for it to request dynamic_bytes more.
-hipError_t run_kernel_lds(size_t *static_bytes, size_t dynamic_bytes);
+// Static LDS bytes of the search kernel (sequential or speculative VND), and permission for it to request
+// dynamic_bytes more.
+hipError_t run_kernel_lds(bool spec, size_t *static_bytes, size_t dynamic_bytes);
 // Learned scorer (vns_mlp.hip).  P: 5313 float32 parameters.  Scores of n feature rows [n][16].
 hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *out, hipStream_t s);
 // Gradient (and loss in grad_out[5313]) of the mean squared error over rows idx[0..n) (all rows when idx is
@@ -68,6 +69,7 @@ hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStr
 hipError_t launch_chain_best(const ChainBestArgs &a, int n_chains, hipStream_t s);
 // k_run over n_chains workgroups, then the device iteration counter advances by a.iters (two kernels on s;
 // both can be captured in a graph).
-hipError_t launch_run(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter, hipStream_t s);
+hipError_t launch_run(const RunArgs &a, bool spec, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
+                      hipStream_t s);
 
 }  // namespace vns

@@ -55,6 +55,8 @@ struct vns_ctx {
     int32_t use_graph = 0;
     int64_t max_lds_per_wg = 65536;       // device limit on LDS per workgroup (queried at create)
     int32_t permille = 0;                 // learned scorer: top permille priced exactly (0 = plain search)
+    int32_t speculate = 0;                // plain search: speculative VND (neighbourhoods priced side by side)
+    int32_t spec_waves = 16;
     int64_t log_cap = 0;                  // move-log capacity in records (0 = no log)
 
     // chains (host mirror)
@@ -443,7 +445,7 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             c->trace = (int32_t)v;
             return VNS_OK;
         case VNS_OPT_RUN_WAVES:
-            if (v < 1 || v > kMaxWaves) return fail(c, VNS_EINVAL, "run waves out of range");
+            if (v < 1 || v > 8) return fail(c, VNS_EINVAL, "run waves out of range");
             c->run_waves = (int32_t)v;
             return VNS_OK;
         case VNS_OPT_EVAL_GROUP:
@@ -458,6 +460,14 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "graph must be 0 or 1");
             c->use_graph = (int32_t)v;
             if (!v) drop_graph(c);
+            return VNS_OK;
+        case VNS_OPT_SPECULATE:
+            if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "speculate must be 0 or 1");
+            c->speculate = (int32_t)v;
+            return VNS_OK;
+        case VNS_OPT_SPEC_WAVES:
+            if (v < 1 || v > kMaxWaves) return fail(c, VNS_EINVAL, "speculative waves out of range");
+            c->spec_waves = (int32_t)v;
             return VNS_OK;
         case VNS_OPT_LEARNED:
             if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
@@ -494,6 +504,8 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_RUN_LDS: *v = c->run_lds_budget; return VNS_OK;
         case VNS_OPT_GRAPH: *v = c->use_graph; return VNS_OK;
         case VNS_OPT_LEARNED: *v = c->permille; return VNS_OK;
+        case VNS_OPT_SPECULATE: *v = c->speculate; return VNS_OK;
+        case VNS_OPT_SPEC_WAVES: *v = c->spec_waves; return VNS_OK;
         case VNS_OPT_LOG: *v = c->log_cap; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
@@ -643,24 +655,28 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     int64_t max_rows = 0;
     for (int32_t i = 0; i < c->n_inst; ++i) max_rows = std::max<int64_t>(max_rows, (int64_t)c->K[(size_t)i] * c->T[(size_t)i]);
     // instance rows in LDS for every chain whose instance fits the budget; the others stage one row per wave
+    // speculative VND for plain runs (one wavefront per neighbourhood of each product), else one wavefront
+    // per product
+    const bool spec = c->speculate && c->permille == 0 && c->spec_waves >= c->n_nb;
+    const int waves = spec ? c->spec_waves : c->run_waves;
     size_t static_lds = 0;
-    VNS_HIP(c, run_kernel_lds(&static_lds, 0));
-    const int64_t learned = c->permille > 0 ? (int64_t)c->run_waves * kLearnedWaveBytes : 0;
+    VNS_HIP(c, run_kernel_lds(spec, &static_lds, 0));
+    const int64_t learned = c->permille > 0 ? (int64_t)waves * kLearnedWaveBytes : 0;
     const int64_t room = c->max_lds_per_wg - (int64_t)static_lds - learned;   // dynamic LDS left for rows
-    const int64_t slices = (int64_t)c->run_waves * kTMax;            // per-wave rows when the instance does not fit
+    const int64_t slices = (int64_t)waves * kTMax;                   // per-wave rows when the instance does not fit
     if (room < slices * (int64_t)sizeof(int2)) return fail(c, VNS_EINVAL, "not enough LDS for the search kernel");
     const int64_t budget = std::min<int64_t>(c->run_lds_budget, room) / (int64_t)sizeof(int2);
     ra.lds_rows = (int32_t)std::min<int64_t>(max_rows, budget);
-    const size_t lds = (size_t)run_rows_entries(ra.lds_rows, c->run_waves) * sizeof(int2) + (size_t)learned;
-    VNS_HIP(c, run_kernel_lds(&static_lds, lds));
+    const size_t lds = (size_t)run_rows_entries(ra.lds_rows, waves) * sizeof(int2) + (size_t)learned;
+    VNS_HIP(c, run_kernel_lds(spec, &static_lds, lds));
     if (c->use_graph) {
-        const int64_t key[5] = {iters, G, c->run_waves, (int64_t)lds, (int64_t)(intptr_t)ra.trace};
+        const int64_t key[5] = {iters, G, waves * 2 + (spec ? 1 : 0), (int64_t)lds, (int64_t)(intptr_t)ra.trace};
         bool same = true;
         for (int i = 0; i < 5; ++i) same = same && key[i] == c->graph_key[i];
         if (!same || !c->graph_exec) {
             drop_graph(c);
             VNS_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            hipError_t le = launch_run(ra, (int)G, c->run_waves, lds, c->d_iter, c->stream);
+            hipError_t le = launch_run(ra, spec, (int)G, waves, lds, c->d_iter, c->stream);
             hipGraph_t gr = nullptr;
             hipError_t ce = hipStreamEndCapture(c->stream, &gr);
             if (le != hipSuccess) {
@@ -677,7 +693,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     } else {
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-        VNS_HIP(c, launch_run(ra, (int)G, c->run_waves, lds, c->d_iter, c->stream));
+        VNS_HIP(c, launch_run(ra, spec, (int)G, waves, lds, c->d_iter, c->stream));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     }
     std::vector<ChainState> cs((size_t)G);

@@ -18,7 +18,7 @@ namespace vns {
 constexpr int kWords = 4;          // 32-bit words per setup row: T <= 128
 constexpr int kTMax = 32 * kWords;
 constexpr int kShakeMax = 64;
-constexpr int kMaxWaves = 8;
+constexpr int kMaxWaves = 16;     // wavefronts per search workgroup (8 for the sequential VND, 16 speculative)
 constexpr int kEvalGroup = 16;
 constexpr int64_t kRunLdsMax = 128 * 1024;  // dynamic LDS the search kernel may request for instance rows     // chains of one instance priced by one k_eval workgroup
 constexpr int kMaxPasses = 1 << 16;  // VND passes per product and iteration: a guard, not a limit of the method

@@ -117,3 +117,22 @@ def test_autotuner_choice_runs_and_keeps_results(vns, tmp_path):
         plain.run(5)
         for g in range(ctx.n_chains):
             assert (ctx.trajectory(g) == plain.trajectory(g)).all()
+
+
+@pytest.mark.parametrize("nb", [(1, 2, 4), (4, 2, 1), (1, 2), (2,)])
+def test_speculative_vnd_equals_sequential(vns, nb):
+    """Grouped speculative VND against one wavefront per product: same records, same solutions and the same
+    number of consumed move-evaluations (discarded speculative pricing is not counted)."""
+    insts = [workload("batched_4096", i) for i in range(3)] + [workload("plain_100x52")]
+    say(f"  speculative vs sequential nb={nb}")
+    with vns.Context(insts, seed=3, chains=4, nb_list=nb, options={vns.OPT_SPECULATE: 1}) as sp, \
+            vns.Context(insts, seed=3, chains=4, nb_list=nb, options={vns.OPT_SPECULATE: 0}) as sq:
+        for rep in range(2):
+            sp.run(15)
+            sq.run(15)
+            assert sp.stats()["last_run_evals"] == sq.stats()["last_run_evals"]
+            for g in range(sp.n_chains):
+                assert (sp.trajectory(g) == sq.trajectory(g)).all(), g
+        for g in range(sp.n_chains):
+            a, b = sp.solution(g), sq.solution(g)
+            assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
