@@ -29,6 +29,9 @@ sys.path.insert(0, ROOT)
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 OPS_PER_PERIOD_STEP = 14     # operations of one period-step of the forward decode
 TUNE_FILE = os.path.join(ROOT, "paper_1704_05132_amd", "tune_table.json")
+# learned scorer: 2 x (16*64 + 64*64 + 64) flops per scored move; dense bfloat16 matrix-core peak of MI355X
+MLP_FLOP_PER_ROW = 2 * (16 * 64 + 64 * 64 + 64)
+BF16_PEAK_TFLOPS = 2500.0
 
 
 def kernel_source_hash():
@@ -66,6 +69,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--print-source-hash", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain time-to-best half")
+    ap.add_argument("--chunk", type=int, default=50, help="iterations per launch in the time-to-best runs")
+    ap.add_argument("--learned-permille", type=int, default=100, help="share of moves priced exactly (1/1000)")
+    ap.add_argument("--learned-train-instances", type=int, default=16)
+    ap.add_argument("--learned-log-iters", type=int, default=200)
+    ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration for profiling runs)")
     return ap.parse_args()
@@ -99,6 +108,103 @@ def cpu_baseline(pairs, nb, target_s, label):
     return {"value": evals / dt, "unit": "move-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{threads} chains x {iters} GVNS iterations of {label} from iteration 0, one chain per "
                       f"thread ({evals} move-evaluations in {dt:.1f} s)"}
+
+
+def best_over_chains(ctx, chains):
+    return min(ctx.cost(g)[1] for g in range(chains))
+
+
+def chunked_search(make_ctx, chains, target, max_iters, chunk):
+    """Run a fresh context in launches of `chunk` iterations until the best cost over its chains is <= target
+    (or max_iters).  Returns (device ms until reached or None, iterations, best cost, device ms in total)."""
+    ctx = make_ctx()
+    ms, it, reached = 0.0, 0, None
+    best = best_over_chains(ctx, chains)
+    while it < max_iters:
+        n = min(chunk, max_iters - it)
+        ctx.run(n)
+        ms += ctx.stats()["last_run_ms"]
+        it += n
+        best = best_over_chains(ctx, chains)
+        if target is not None and best <= target and reached is None:
+            reached = (ms, it)
+            break
+    ctx.close()
+    return (reached[0] if reached else None), (reached[1] if reached else it), best, ms
+
+
+def learned_vs_plain(args, vns, stream, table, key):
+    """Time to the plain method's best cost: plain search vs the learned search (scorer trained on moves the
+    search logged on disjoint training instances), same instance, seeds and chains, on this GPU."""
+    import numpy as np
+    from paper_1704_05132_amd.instances import WORKLOADS, workload
+    w = WORKLOADS["learned_100x52"]
+    inst = workload("learned_100x52", 0)
+    seed, chains, chunk = WORKLOADS["plain_100x52"]["seed"], w["chains"], args.chunk
+
+    def make(options=None):
+        c = vns.Context(inst, seed=seed, chains=chains, nb_list=w["nb"], trace=False, options=options)
+        c.bind_stream(stream)
+        table.apply(c, key)
+        return c
+
+    # plain: best over chains after the workload's iterations, and the device time to first reach it
+    _, _, B, plain_total = chunked_search(make, chains, None, args.steps, chunk)
+    plain_ms, plain_it, _, _ = chunked_search(make, chains, B, args.steps, chunk)
+
+    # training set: moves logged by the search on disjoint instances
+    train = [workload("learned_100x52", 100 + j) for j in range(args.learned_train_instances)]
+    t0 = time.perf_counter()
+    with vns.Context(train, seed=w["seed"], chains=16, nb_list=w["nb"], trace=False,
+                     options={vns.OPT_LOG: 2_000_000}) as lg:
+        lg.bind_stream(stream)
+        lg.run(args.learned_log_iters)
+        log_ms = lg.stats()["last_run_ms"]
+        X, y = lg.move_log()
+    with make() as tr:
+        tr.mlp_init(7)
+        t1 = time.perf_counter()
+        loss = tr.mlp_train(X, y, epochs=args.learned_epochs, batch=4096, lr=2e-3, seed=11)
+        train_s = time.perf_counter() - t1
+        st = tr.stats()
+        train_dev_ms, train_rows = st["last_mlp_ms"], st["last_mlp_rows"]
+        params = tr.mlp_get()
+        # scorer alone: one launch over 2^20 feature rows (the logged moves, repeated)
+        Xs = np.resize(X, (1 << 20, X.shape[1])) if len(X) else np.zeros((1 << 20, 16), np.float32)
+        for _ in range(3):
+            tr.mlp_score(Xs)
+        st = tr.stats()
+        score_ms, score_rows = st["last_mlp_ms"], st["last_mlp_rows"]
+    collect_s = time.perf_counter() - t0 - train_s
+
+    def make_learned():
+        c = make({vns.OPT_LEARNED: args.learned_permille})
+        c.mlp_set(params)
+        return c
+
+    lrn_ms, lrn_it, lrn_best, lrn_total = chunked_search(make_learned, chains, B, 2 * args.steps, chunk)
+    return {
+        "plain_best_F": int(B),
+        "plain_ms_to_best": plain_ms, "plain_iters_to_best": plain_it,
+        "learned_ms_to_plain_best": lrn_ms, "learned_iters": lrn_it, "learned_best_F": int(lrn_best),
+        "learned_reached": lrn_ms is not None,
+        "speedup": (plain_ms / lrn_ms) if lrn_ms else None,
+        "permille_priced": args.learned_permille, "chunk_iters": chunk,
+        "training": {"instances": len(train), "logged_moves": int(len(y)),
+                     "improving_share": float(np.mean(y < 0)) if len(y) else 0.0,
+                     "log_search_ms": log_ms, "collect_s": collect_s, "epochs": args.learned_epochs,
+                     "train_s": train_s, "final_loss": loss, "device_ms": train_dev_ms,
+                     "rows_per_s": train_rows / (train_dev_ms / 1e3) if train_dev_ms else None,
+                     "tflops": (train_rows * 3 * MLP_FLOP_PER_ROW / (train_dev_ms / 1e3) / 1e12
+                                if train_dev_ms else None)},
+        "scorer": {"kernel": "k_mlp_score", "rows": score_rows, "ms": score_ms,
+                   "rows_per_s": score_rows / (score_ms / 1e3), "bound": "mfma",
+                   "achieved": score_rows * MLP_FLOP_PER_ROW / (score_ms / 1e3) / 1e12, "peak": BF16_PEAK_TFLOPS,
+                   "unit": "TFLOP/s",
+                   "frac": score_rows * MLP_FLOP_PER_ROW / (score_ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
+                   "flop_per_row": MLP_FLOP_PER_ROW},
+        "note": "device time of the search launches only; scorer training is reported separately",
+    }
 
 
 def main():
@@ -225,6 +331,8 @@ def main():
                   "value": sweep_ev / (sweep_med / 1e3), "unit": "move-evals/s", "achieved": sweep_achieved,
                   "peak": peak, "frac": sweep_achieved / peak, "traffic": measured_traffic("k_eval", name)},
     }
+    if name == "plain_100x52" and not args.no_learned:
+        out["time_to_plain_best"] = learned_vs_plain(args, vns, stream, table, key)
     if not args.no_cpu_baseline:
         rng = __import__("numpy").random.default_rng(0)
         order = rng.permutation(len(insts)) if len(insts) > 1 else [0] * 16

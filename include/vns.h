@@ -111,6 +111,8 @@ typedef struct vns_stats {
     int64_t last_eval_period_steps;  /* the same for the last vns_eval_neighbourhood call                */
     int64_t last_run_learned_evals;  /* learned VND: neighbourhood evaluations of the last run           */
     int64_t last_run_fallbacks;      /*   and how many of them priced the whole neighbourhood            */
+    double last_mlp_ms;              /* device time of the kernels of the last vns_mlp_score / _grad / _train */
+    int64_t last_mlp_rows;           /*   and the feature rows they processed (rows x epochs for training)   */
 } vns_stats;
 
 /*
@@ -199,9 +201,13 @@ vns_status vns_get_stats(const vns_ctx *ctx, vns_stats *out);
  * D(t)/200, R(t)/200, D(t-1)/200, D(t+1)/200 (0 outside the horizon); kM/2000, kR/2000, hM/8, hR/8;
  * (t - last setup <= t)/T (1 if none); (next setup > t - t)/T (T if none).
  * Parameters: VNS_MLP_PARAMS float32 = W1 [16][64] row-major, b1 [64], W2 [64][64], b2 [64], W3 [64], b3.
- * A new context's parameters are all zero.
+ * A new context starts from vns_mlp_init(ctx, seed of the context).
  */
 vns_status vns_mlp_set_params(vns_ctx *ctx, const float *params);   /* also resets the Adam state       */
+/* vns_mlp_init — He-uniform weights (U(-sqrt(6/fan_in), +sqrt(6/fan_in)) per layer), zero biases, Adam
+ * state reset; the uniforms come from splitmix64 of seed + parameter index + 1 Weyl steps, so a seed gives
+ * the same weights on every host. */
+vns_status vns_mlp_init(vns_ctx *ctx, uint64_t seed);
 vns_status vns_mlp_get_params(vns_ctx *ctx, float *params);
 /* Scores of n feature rows ([n][16] float32) into scores [n]. */
 vns_status vns_mlp_score(vns_ctx *ctx, const float *feats, int64_t n, float *scores);

@@ -62,6 +62,18 @@ struct DecodeState {
     int32_t nolast = -1, bad = 0;
 };
 
+// acc += a * b with a, b < 2^24 (the host rejects larger demands and returns), as one v_mad_u32_u24: the
+// compiler would otherwise regroup consecutive periods' products into mul + add3 trees (three instructions
+// per two periods instead of two).
+__device__ __forceinline__ void mad_u24(int32_t &acc, int32_t a, int32_t b) {
+    asm("v_mad_u32_u24 %0, %1, %2, %0" : "+v"(acc) : "v"(a), "v"(b));
+}
+
+// acc |= a & b as one v_and_or_b32.
+__device__ __forceinline__ void and_or(int32_t &acc, int32_t a, int32_t b) {
+    asm("v_and_or_b32 %0, %1, %2, %0" : "+v"(acc) : "v"(a), "v"(b));
+}
+
 // One period-step: sm, sr are the setup bits of period tau as 0 / -1 masks, dp = (D(tau), PR(tau)).
 __device__ __forceinline__ void decode_step(DecodeState &s, int32_t sm, int32_t sr, int32_t tau, int2 dp) {
     s.lim = sel(sm, s.XR, s.lim);         // a manufacturing setup closes the remanufacturing capacity
@@ -72,10 +84,10 @@ __device__ __forceinline__ void decode_step(DecodeState &s, int32_t sm, int32_t 
     const int32_t xn = min(s.XR + dp.x, s.lim);
     const int32_t u = xn - s.XR;          // units remanufactured at lsR for period tau
     s.XR = xn;
-    s.A1 += (int32_t)__umul24((uint32_t)u, (uint32_t)s.lsR);
+    mad_u24(s.A1, u, s.lsR);
     const int32_t rr = dp.x - u;          // units manufactured at lastM for period tau
-    s.A2 += (int32_t)__umul24((uint32_t)rr, (uint32_t)s.lastM);
-    s.bad |= rr & s.nolast;               // demand with no manufacturing setup at or before it
+    mad_u24(s.A2, rr, s.lastM);
+    and_or(s.bad, rr, s.nolast);          // demand with no manufacturing setup at or before it
 }
 
 __device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bits &b, int T, const ProdParams &pp) {
@@ -90,27 +102,53 @@ __device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bit
            (int64_t)pp.hR * (pp.S_PR - (int64_t)T * s.XR + (int64_t)s.A1);
 }
 
+template <class RowPtr>
+__device__ __forceinline__ void load_chunk(RowPtr row, int at, int2 (&c)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c[i] = row[at + i];
+}
+
+// Four period-steps from period tau (a multiple of four) of the setup words m, r that hold it.
+__device__ __forceinline__ void decode_chunk(DecodeState &s, int32_t m, int32_t r, int tau, const int2 (&c)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        decode_step(s, __builtin_amdgcn_sbfe(m, (tau + i) & 31, 1), __builtin_amdgcn_sbfe(r, (tau + i) & 31, 1), tau + i,
+                    c[i]);
+}
+
 // Exact cost of one product's pattern (kInf when infeasible), any T <= kTMax.  row points at the product's
-// (D, PR) pairs; it may be an LDS or a global pointer (after inlining the address space is known).  The row
-// is read two periods ahead of its use so that a lone wavefront does not wait on each load.
+// (D, PR) pairs; it may be an LDS or a global pointer (after inlining the address space is known).  T must
+// be the same in every active lane.  The periods are walked in chunks of four; the rows of the next chunk
+// are read while the current one is decoded, alternating between two register sets so that nothing is
+// copied, and never past period T - 1.
 template <class RowPtr>
 __device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T, const ProdParams &pp) {
+    T = __builtin_amdgcn_readfirstlane(T);
     DecodeState s;
-    int2 ahead1 = row[0];
-    int2 ahead2 = row[T > 1 ? 1 : 0];
+    const int Tc = T - 4;   // start of the last whole chunk
+    int2 ca[4], cb[4];
+    if (Tc >= 0) load_chunk(row, 0, ca);
+    int tau = 0;
 #pragma unroll
     for (int j = 0; j < kWords; ++j) {
         if (32 * j >= T) break;
-        const uint32_t m = b.m[j], r = b.r[j];
-        const int nb = min(32, T - 32 * j);
-#pragma unroll 2
-        for (int q = 0; q < nb; ++q) {
-            const int tau = 32 * j + q;
-            const int2 dp = ahead1;
-            ahead1 = ahead2;
-            ahead2 = row[tau + 2 < T ? tau + 2 : T - 1];
-            decode_step(s, __builtin_amdgcn_sbfe((int32_t)m, q, 1), __builtin_amdgcn_sbfe((int32_t)r, q, 1), tau, dp);
+        const int32_t m = (int32_t)b.m[j], r = (int32_t)b.r[j];
+        const int wend = min(32 * j + 32, T);
+        for (; tau + 8 <= wend; tau += 8) {
+            load_chunk(row, min(tau + 4, Tc), cb);
+            decode_chunk(s, m, r, tau, ca);
+            load_chunk(row, min(tau + 8, Tc), ca);
+            decode_chunk(s, m, r, tau + 4, cb);
         }
+        if (tau + 4 <= wend) {
+            load_chunk(row, min(tau + 4, Tc), cb);
+            decode_chunk(s, m, r, tau, ca);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ca[i] = cb[i];
+            tau += 4;
+        }
+        for (; tau < wend; ++tau)   // the last one to three periods
+            decode_step(s, __builtin_amdgcn_sbfe(m, tau & 31, 1), __builtin_amdgcn_sbfe(r, tau & 31, 1), tau, row[tau]);
     }
     return decode_finish(s, b, T, pp);
 }

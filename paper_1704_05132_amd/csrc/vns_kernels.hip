@@ -9,6 +9,8 @@
 //   k_chain_best    per chain: lexicographic (price, slot) minimum over its products
 //   k_run           one workgroup per chain running whole GVNS iterations (Algorithm 2): Philox shake,
 //                   VND (Algorithm 1) with one wavefront per product that needs it, acceptance
+//   k_run_spec      the same with the neighbourhoods of a product's VND priced side by side
+//   k_run_learned   the same with the learned scorer choosing which moves are priced exactly
 #include <hip/hip_runtime.h>
 
 #include "vns_device.hpp"
@@ -238,8 +240,9 @@ struct SpecShared {
     int32_t next;         // next product index to hand out
 };
 
-template <bool SPEC>
+template <bool SPEC, bool LEARNED>
 __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecShared &sp, int2 *s_rows) {
+    static_assert(!(SPEC && LEARNED), "the speculative VND prices whole neighbourhoods");
     const int g = blockIdx.x;
     const ChainInfo ci = a.chains[g];
     const int K = ci.K, T = ci.T;
@@ -266,9 +269,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     LearnedLds L{reinterpret_cast<__bf16 *>(lbase), reinterpret_cast<__bf16 *>(lbase + 64 * 16 * 2),
                  reinterpret_cast<uint16_t *>(lbase + 64 * 16 * 2 + 64 * 64 * 2)};
     mlp::Frags fr;
-    if constexpr (!SPEC) {
-        if (a.permille > 0) mlp::load_frags(a.mlp, fr);
-    }
+    if constexpr (LEARNED) mlp::load_frags(a.mlp, fr);
     const uint64_t nflip_all = 2ull * (uint64_t)K * (uint64_t)T;
 
     for (int i = 0; i < a.iters; ++i) {
@@ -471,7 +472,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         // contrast move for the log: a fixed pseudo-random item of this evaluation
                         const int chash = a.log_x ? (int)(((uint32_t)it * 2654435761u + (uint32_t)p * 40503u +
                                                            (uint32_t)(q + 4 * passes) * 97u) & 0x7FFFFFFFu) : -1;
-                        if (!SPEC && a.permille > 0) {
+                        if constexpr (LEARNED) {
                             int fb = 0;
                             const bool id = need_ident;
                             key = learned_best_move(b, row, T, pp, nb, sh.list[wave], L, fr, a.mlp, a.permille, id, cost,
@@ -496,7 +497,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                             const int64_t c = (int64_t)(key >> kSlotBits);
                             if (c < cost) {
                                 const int slot = (int)(key & ((1u << kSlotBits) - 1));
-                                if (a.log_x && a.permille == 0) {
+                                if (!LEARNED && a.log_x) {
                                     const bool has_c = ckey != kInfKey && ckey != key;
                                     log_moves(b, row, T, pp, slot, c - cost, has_c ? (int)(ckey & 0xFFFFu) : -1,
                                               has_c ? (int64_t)(ckey >> kSlotBits) - cost : 0, a.log_x, a.log_y, a.log_n,
@@ -595,14 +596,22 @@ __global__ __launch_bounds__(512) void k_run(RunArgs a) {
     __shared__ RunShared sh;
     __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
-    run_chain<false>(a, sh, sp, s_rows);
+    run_chain<false, false>(a, sh, sp, s_rows);
 }
 
 __global__ __launch_bounds__(1024) void k_run_spec(RunArgs a) {
     __shared__ RunShared sh;
     __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
-    run_chain<true>(a, sh, sp, s_rows);
+    run_chain<true, false>(a, sh, sp, s_rows);
+}
+
+// learned VND: the scorer's weight fragments stay in registers for the whole launch
+__global__ __launch_bounds__(512) void k_run_learned(RunArgs a) {
+    __shared__ RunShared sh;
+    __shared__ SpecShared sp;
+    extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
+    run_chain<false, true>(a, sh, sp, s_rows);
 }
 
 // ---------------------------------------------------------------------------------------------------
@@ -671,8 +680,16 @@ hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64
     return hipGetLastError();
 }
 
-hipError_t run_kernel_lds(bool spec, size_t *static_bytes, size_t dynamic_bytes) {
-    const void *fn = spec ? reinterpret_cast<const void *>(&k_run_spec) : reinterpret_cast<const void *>(&k_run);
+static const void *run_kernel(RunKind kind) {
+    switch (kind) {
+        case RunKind::kSpec: return reinterpret_cast<const void *>(&k_run_spec);
+        case RunKind::kLearned: return reinterpret_cast<const void *>(&k_run_learned);
+        default: return reinterpret_cast<const void *>(&k_run);
+    }
+}
+
+hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_bytes) {
+    const void *fn = run_kernel(kind);
     hipFuncAttributes fa;
     hipError_t e = hipFuncGetAttributes(&fa, fn);
     if (e != hipSuccess) return e;
@@ -680,11 +697,13 @@ hipError_t run_kernel_lds(bool spec, size_t *static_bytes, size_t dynamic_bytes)
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes);
 }
 
-hipError_t launch_run(const RunArgs &a, bool spec, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
+hipError_t launch_run(const RunArgs &a, RunKind kind, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
                       hipStream_t s) {
     if (n_chains <= 0 || a.iters <= 0) return hipSuccess;
-    if (spec)
+    if (kind == RunKind::kSpec)
         hipLaunchKernelGGL(k_run_spec, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
+    else if (kind == RunKind::kLearned)
+        hipLaunchKernelGGL(k_run_learned, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
     else
         hipLaunchKernelGGL(k_run, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
     hipError_t e = hipGetLastError();

@@ -31,9 +31,11 @@ struct ChainBestArgs {
     int32_t chain0;
 };
 
-// Static LDS bytes of the search kernel (sequential or speculative VND), and permission for it to request
-// dynamic_bytes more.
-hipError_t run_kernel_lds(bool spec, size_t *static_bytes, size_t dynamic_bytes);
+// Variants of the search kernel: sequential VND, speculative VND, learned VND.
+enum class RunKind { kPlain = 0, kSpec = 1, kLearned = 2 };
+
+// Static LDS bytes of a search kernel variant, and permission for it to request dynamic_bytes more.
+hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_bytes);
 // Learned scorer (vns_mlp.hip).  P: 5313 float32 parameters.  Scores of n feature rows [n][16].
 hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *out, hipStream_t s);
 // Gradient (and loss in grad_out[5313]) of the mean squared error over rows idx[0..n) (all rows when idx is
@@ -67,9 +69,9 @@ hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s);
 hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64_t n_cp, hipStream_t s);
 hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s);
 hipError_t launch_chain_best(const ChainBestArgs &a, int n_chains, hipStream_t s);
-// k_run over n_chains workgroups, then the device iteration counter advances by a.iters (two kernels on s;
+// The search kernel variant `kind` over n_chains workgroups, then the device iteration counter advances by a.iters (two kernels on s;
 // both can be captured in a graph).
-hipError_t launch_run(const RunArgs &a, bool spec, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
+hipError_t launch_run(const RunArgs &a, RunKind kind, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
                       hipStream_t s);
 
 }  // namespace vns

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -22,6 +23,8 @@ using namespace vns;
 static_assert(sizeof(Record) == sizeof(vns_record), "record layout");
 static_assert(sizeof(Bits) == 32, "bits layout");
 static_assert(VNS_MLP_PARAMS == mlp::kParams, "scorer parameter count");
+
+static void mlp_he_uniform(uint64_t seed, std::vector<float> &p);
 
 namespace {
 
@@ -385,7 +388,10 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
     VNS_CREATE_HIP(dmalloc(&c->d_mlp, (size_t)mlp::kParams));
     VNS_CREATE_HIP(dmalloc(&c->d_adam_m, (size_t)mlp::kParams));
     VNS_CREATE_HIP(dmalloc(&c->d_adam_v, (size_t)mlp::kParams));
-    VNS_CREATE_HIP(hipMemsetAsync(c->d_mlp, 0, sizeof(float) * mlp::kParams, c->stream));
+    std::vector<float> init_params;
+    mlp_he_uniform(seed, init_params);
+    VNS_CREATE_HIP(hipMemcpyAsync(c->d_mlp, init_params.data(), sizeof(float) * mlp::kParams, hipMemcpyHostToDevice,
+                                  c->stream));
     VNS_CREATE_HIP(hipMemsetAsync(c->d_adam_m, 0, sizeof(float) * mlp::kParams, c->stream));
     VNS_CREATE_HIP(hipMemsetAsync(c->d_adam_v, 0, sizeof(float) * mlp::kParams, c->stream));
     VNS_CREATE_HIP(hipMemcpyAsync(c->d_rows, rows.data(), sizeof(int2) * (size_t)n_rows, hipMemcpyHostToDevice, c->stream));
@@ -658,9 +664,10 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     // speculative VND for plain runs (one wavefront per neighbourhood of each product), else one wavefront
     // per product
     const bool spec = c->speculate && c->permille == 0 && c->spec_waves >= c->n_nb;
+    const RunKind kind = c->permille > 0 ? RunKind::kLearned : spec ? RunKind::kSpec : RunKind::kPlain;
     const int waves = spec ? c->spec_waves : c->run_waves;
     size_t static_lds = 0;
-    VNS_HIP(c, run_kernel_lds(spec, &static_lds, 0));
+    VNS_HIP(c, run_kernel_lds(kind, &static_lds, 0));
     const int64_t learned = c->permille > 0 ? (int64_t)waves * kLearnedWaveBytes : 0;
     const int64_t room = c->max_lds_per_wg - (int64_t)static_lds - learned;   // dynamic LDS left for rows
     const int64_t slices = (int64_t)waves * kTMax;                   // per-wave rows when the instance does not fit
@@ -668,15 +675,15 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     const int64_t budget = std::min<int64_t>(c->run_lds_budget, room) / (int64_t)sizeof(int2);
     ra.lds_rows = (int32_t)std::min<int64_t>(max_rows, budget);
     const size_t lds = (size_t)run_rows_entries(ra.lds_rows, waves) * sizeof(int2) + (size_t)learned;
-    VNS_HIP(c, run_kernel_lds(spec, &static_lds, lds));
+    VNS_HIP(c, run_kernel_lds(kind, &static_lds, lds));
     if (c->use_graph) {
-        const int64_t key[5] = {iters, G, waves * 2 + (spec ? 1 : 0), (int64_t)lds, (int64_t)(intptr_t)ra.trace};
+        const int64_t key[5] = {iters, G, waves * 4 + (int64_t)kind, (int64_t)lds, (int64_t)(intptr_t)ra.trace};
         bool same = true;
         for (int i = 0; i < 5; ++i) same = same && key[i] == c->graph_key[i];
         if (!same || !c->graph_exec) {
             drop_graph(c);
             VNS_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            hipError_t le = launch_run(ra, spec, (int)G, waves, lds, c->d_iter, c->stream);
+            hipError_t le = launch_run(ra, kind, (int)G, waves, lds, c->d_iter, c->stream);
             hipGraph_t gr = nullptr;
             hipError_t ce = hipStreamEndCapture(c->stream, &gr);
             if (le != hipSuccess) {
@@ -693,7 +700,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     } else {
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-        VNS_HIP(c, launch_run(ra, spec, (int)G, waves, lds, c->d_iter, c->stream));
+        VNS_HIP(c, launch_run(ra, kind, (int)G, waves, lds, c->d_iter, c->stream));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     }
     std::vector<ChainState> cs((size_t)G);
@@ -831,12 +838,27 @@ extern "C" const char *vns_last_error(const vns_ctx *c) {
 // ---------------------------------------------------------------------------------------------------
 // learned scorer
 // ---------------------------------------------------------------------------------------------------
-extern "C" vns_status vns_mlp_set_params(vns_ctx *c, const float *params) {
-    VNS_LIVE(c);
-    if (!params) return fail(c, VNS_EINVAL, "NULL params");
-    for (int i = 0; i < mlp::kParams; ++i)
-        if (!(params[i] == params[i]) || params[i] > 1e30f || params[i] < -1e30f)
-            return fail(c, VNS_EINVAL, "non-finite scorer parameter");
+// He-uniform initial weights (He et al. 2015, uniform form: U(-sqrt(6/fan_in), +sqrt(6/fan_in))), zero
+// biases.  Parameter i draws its uniform from splitmix64 (Steele, Lea & Flood, OOPSLA 2014) of seed + i + 1
+// steps of the generator's Weyl sequence, top 53 bits.
+static void mlp_he_uniform(uint64_t seed, std::vector<float> &p) {
+    p.assign((size_t)mlp::kParams, 0.f);
+    auto uniform = [seed](uint64_t i) {
+        uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * 0x1.0p-53;
+    };
+    const struct { int off, fan_in, n; } layers[3] = {
+        {mlp::oW1, mlp::kF, mlp::kF * mlp::kH}, {mlp::oW2, mlp::kH, mlp::kH * mlp::kH}, {mlp::oW3, mlp::kH, mlp::kH}};
+    for (const auto &L : layers) {
+        const double lim = std::sqrt(6.0 / (double)L.fan_in);
+        for (int j = 0; j < L.n; ++j) p[(size_t)(L.off + j)] = (float)(lim * (2.0 * uniform((uint64_t)(L.off + j)) - 1.0));
+    }
+}
+
+static vns_status upload_mlp(vns_ctx *c, const float *params) {
     VNS_HIP(c, hipMemcpyAsync(c->d_mlp, params, sizeof(float) * mlp::kParams, hipMemcpyHostToDevice, c->stream));
     VNS_HIP(c, hipMemsetAsync(c->d_adam_m, 0, sizeof(float) * mlp::kParams, c->stream));
     VNS_HIP(c, hipMemsetAsync(c->d_adam_v, 0, sizeof(float) * mlp::kParams, c->stream));
@@ -844,6 +866,22 @@ extern "C" vns_status vns_mlp_set_params(vns_ctx *c, const float *params) {
     drop_graph(c);
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     return VNS_OK;
+}
+
+extern "C" vns_status vns_mlp_init(vns_ctx *c, uint64_t seed) {
+    VNS_LIVE(c);
+    std::vector<float> p;
+    mlp_he_uniform(seed, p);
+    return upload_mlp(c, p.data());
+}
+
+extern "C" vns_status vns_mlp_set_params(vns_ctx *c, const float *params) {
+    VNS_LIVE(c);
+    if (!params) return fail(c, VNS_EINVAL, "NULL params");
+    for (int i = 0; i < mlp::kParams; ++i)
+        if (!(params[i] == params[i]) || params[i] > 1e30f || params[i] < -1e30f)
+            return fail(c, VNS_EINVAL, "non-finite scorer parameter");
+    return upload_mlp(c, params);
 }
 
 extern "C" vns_status vns_mlp_get_params(vns_ctx *c, float *params) {
@@ -860,6 +898,15 @@ struct Scoped {
     ~Scoped() { dfree(p); }
 };
 
+// Device time between the context's two events (recorded around a scorer call's kernels) into the stats.
+static vns_status record_mlp_time(vns_ctx *c, int64_t rows) {
+    float ms = 0.f;
+    VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->stats.last_mlp_ms = (double)ms;
+    c->stats.last_mlp_rows = rows;
+    return VNS_OK;
+}
+
 extern "C" vns_status vns_mlp_score(vns_ctx *c, const float *feats, int64_t n, float *scores) {
     VNS_LIVE(c);
     if (n < 0 || (n > 0 && (!feats || !scores))) return fail(c, VNS_EINVAL, "bad arguments");
@@ -868,10 +915,12 @@ extern "C" vns_status vns_mlp_score(vns_ctx *c, const float *feats, int64_t n, f
     VNS_HIP(c, dmalloc(&X.p, (size_t)n * mlp::kF));
     VNS_HIP(c, dmalloc(&S.p, (size_t)n));
     VNS_HIP(c, hipMemcpyAsync(X.p, feats, sizeof(float) * mlp::kF * (size_t)n, hipMemcpyHostToDevice, c->stream));
+    VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
     VNS_HIP(c, launch_mlp_score(c->d_mlp, X.p, n, S.p, c->stream));
+    VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     VNS_HIP(c, hipMemcpyAsync(scores, S.p, sizeof(float) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
-    return VNS_OK;
+    return record_mlp_time(c, n);
 }
 
 // Device scratch of one gradient evaluation over up to n rows.
@@ -901,14 +950,16 @@ extern "C" vns_status vns_mlp_grad(vns_ctx *c, const float *feats, const float *
     GradScratch gs;
     vns_status st = gs.alloc(c, n);
     if (st != VNS_OK) return st;
+    VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
     VNS_HIP(c, launch_mlp_grad(c->d_mlp, X.p, Y.p, nullptr, n, gs.Xb.p, gs.sc.p, gs.z1.p, gs.z2.p, gs.part.p, gs.grad.p,
                                c->stream));
+    VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     std::vector<float> g((size_t)mlp::kParams + 1);
     VNS_HIP(c, hipMemcpyAsync(g.data(), gs.grad.p, sizeof(float) * g.size(), hipMemcpyDeviceToHost, c->stream));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     if (grads) std::memcpy(grads, g.data(), sizeof(float) * mlp::kParams);
     if (loss) *loss = g[(size_t)mlp::kParams];
-    return VNS_OK;
+    return record_mlp_time(c, n);
 }
 
 __global__ void k_batch_index(int64_t *idx, int64_t start, int64_t count, int64_t n, uint64_t mul, uint64_t add) {
@@ -937,6 +988,7 @@ extern "C" vns_status vns_mlp_train(vns_ctx *c, const float *feats, const float 
     while (gcd(mul, (uint64_t)n) != 1) mul += 2;
     uint64_t state = seed * 0x9E3779B97F4A7C15ull + 1;
     float loss = 0.f;
+    VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
     for (int32_t e = 0; e < epochs; ++e) {
         state ^= state >> 33; state *= 0xFF51AFD7ED558CCDull; state ^= state >> 33;
         const uint64_t add = state % (uint64_t)n;
@@ -950,13 +1002,14 @@ extern "C" vns_status vns_mlp_train(vns_ctx *c, const float *feats, const float 
             VNS_HIP(c, launch_adam(c->d_mlp, gs.grad.p, c->d_adam_m, c->d_adam_v, lr, ++c->adam_step, c->stream));
         }
     }
+    VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     if (epochs > 0) {
         VNS_HIP(c, hipMemcpyAsync(&loss, gs.grad.p + mlp::kParams, sizeof(float), hipMemcpyDeviceToHost, c->stream));
     }
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     drop_graph(c);
     if (last_loss) *last_loss = loss;
-    return VNS_OK;
+    return record_mlp_time(c, n * (int64_t)epochs);
 }
 
 extern "C" vns_status vns_get_move_log(vns_ctx *c, float *feats, float *targets, int64_t cap, int64_t *n) {

@@ -48,6 +48,7 @@ SIGNATURES = {
     "vns_get_stats": (_c.c_int, [_P, _P]),
     "vns_instance_size": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     "vns_mlp_set_params": (_c.c_int, [_P, _P]),
+    "vns_mlp_init": (_c.c_int, [_P, _c.c_uint64]),
     "vns_mlp_get_params": (_c.c_int, [_P, _P]),
     "vns_mlp_score": (_c.c_int, [_P, _P, _c.c_int64, _P]),
     "vns_mlp_grad": (_c.c_int, [_P, _P, _P, _c.c_int64, _P, _c.POINTER(_c.c_float)]),
@@ -65,7 +66,8 @@ class VNSStats(ctypes.Structure):
                 ("last_run_ms", ctypes.c_double), ("last_eval_evals", ctypes.c_int64),
                 ("last_eval_ms", ctypes.c_double), ("last_run_period_steps", ctypes.c_int64),
                 ("last_eval_period_steps", ctypes.c_int64), ("last_run_learned_evals", ctypes.c_int64),
-                ("last_run_fallbacks", ctypes.c_int64)]
+                ("last_run_fallbacks", ctypes.c_int64), ("last_mlp_ms", ctypes.c_double),
+                ("last_mlp_rows", ctypes.c_int64)]
 
 
 class VNSError(RuntimeError):
@@ -237,6 +239,10 @@ class Context:
                                     else np.ravel(params), np.float32)
         assert flat.size == MLP_PARAMS
         self._check(lib().vns_mlp_set_params(self.h, _ptr(flat)))
+
+    def mlp_init(self, seed: int):
+        """He-uniform weights, zero biases, Adam state reset (vns_mlp_init)."""
+        self._check(lib().vns_mlp_init(self.h, ctypes.c_uint64(seed)))
 
     def mlp_get(self):
         out = np.empty(MLP_PARAMS, np.float32)

@@ -199,3 +199,34 @@ def test_move_log_and_trained_scorer_gain(vns):
             say(f"  {name}: fallback rate {results[name][0]:.3f}, exact evaluations {results[name][1]}")
     assert results["trained"][0] < results["untrained"][0]
     assert results["trained"][1] < results["untrained"][1]
+
+
+def _he_uniform_reference(seed):
+    """He-uniform weights from splitmix64 (Steele, Lea & Flood 2014), written from its definition."""
+    M = (1 << 64) - 1
+
+    def uniform(i):
+        z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        z ^= z >> 31
+        return (z >> 11) * 2.0 ** -53
+
+    p = np.zeros(5313, np.float32)
+    for off, fan_in, n in ((0, 16, 1024), (1088, 64, 4096), (5248, 64, 64)):
+        lim = np.sqrt(6.0 / fan_in)
+        p[off:off + n] = [np.float32(lim * (2.0 * uniform(off + j) - 1.0)) for j in range(n)]
+    return p
+
+
+def test_mlp_init_is_he_uniform(vns):
+    inst = workload("plain_10x12")
+    with vns.Context(inst, seed=9) as ctx:
+        p0 = ctx.mlp_get()
+        ctx.mlp_init(123)
+        p1 = ctx.mlp_get()
+    assert (p0 == _he_uniform_reference(9)).all()      # a new context starts from its own seed
+    assert (p1 == _he_uniform_reference(123)).all()
+    for off, n, fan_in in ((0, 1024, 16), (1088, 4096, 64)):
+        w = p1[off:off + n]
+        assert np.abs(w).max() <= np.sqrt(6.0 / fan_in) and abs(w.mean()) < 0.1 * np.sqrt(6.0 / fan_in)
