@@ -8,9 +8,14 @@ chains; the K timed steps are one vns_run(K) launch on a fresh context starting 
 so the timed region is exactly the workload's first K iterations.  Inputs are resident in HBM before timing.
 
 Prints one JSON line.  Extra fields: the full-neighbourhood sweep of all chains (the pricing kernel alone),
-the dominant kernel's roofline, and the CPU oracle timed on this host on a bounded sample.  --workload
-batched_4096 runs the 4096-instance batch (K ~ U{10..200}, T in {12, 24, 52}, 8 chains each) in one launch
-instead.
+the dominant kernel's roofline, the CPU oracle timed on this host on a bounded sample, and
+`time_to_plain_best`: the device time the learned search (a scorer trained on moves logged on disjoint
+instances ranks the moves, the best-ranked tenth is priced exactly, the whole neighbourhood when none of them
+improves) needs to reach the plain search's best cost on the same instance, seeds and chains, beside the
+plain search's own time to it, with the scorer's and the training's rates.  --workload batched_4096 runs the
+4096-instance batch (K ~ U{10..200}, T in {12, 24, 52}, 8 chains each) in one launch instead;
+--workload learned_batched_1024 the 1024-instance learned + batched set (K ~ U{100..1000}, T in {52, 104},
+returns U(0.1, 0.9), 16 chains each).
 """
 from __future__ import annotations
 
@@ -61,7 +66,7 @@ def measured_traffic(kernel, workload):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="plain_100x52", choices=["plain_100x52", "plain_10x12", "batched_4096"])
+    ap.add_argument("--workload", default="plain_100x52", choices=["plain_100x52", "plain_10x12", "batched_4096", "learned_batched_1024"])
     ap.add_argument("--graph", action="store_true", help="run the search through a captured HIP graph")
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
@@ -110,52 +115,67 @@ def cpu_baseline(pairs, nb, target_s, label):
                       f"thread ({evals} move-evaluations in {dt:.1f} s)"}
 
 
-def best_over_chains(ctx, chains):
-    return min(ctx.cost(g)[1] for g in range(chains))
-
-
-def chunked_search(make_ctx, chains, target, max_iters, chunk):
-    """Run a fresh context in launches of `chunk` iterations until the best cost over its chains is <= target
-    (or max_iters).  Returns (device ms until reached or None, iterations, best cost, device ms in total)."""
+def chunked_search(make_ctx, n_inst, chains, max_iters, chunk, targets=None, horizon_ms=None):
+    """Run a fresh context in launches of `chunk` iterations.  Per instance, the best cost over its chains
+    is tracked after every launch.  Stops once every instance is at or below `targets` (when given).
+    Returns a dict with the device ms and iterations at which all targets were reached (None if not), the
+    final per-instance bests, the total device ms, the per-launch history (ms, bests), and the share of
+    instances at their target when the device time first reached `horizon_ms`."""
+    import numpy as np
     ctx = make_ctx()
-    ms, it, reached = 0.0, 0, None
-    best = best_over_chains(ctx, chains)
+    ms, it, reached, hist, share_at = 0.0, 0, None, [], None
+    best = ctx.costs()[1].reshape(n_inst, chains).min(1)
     while it < max_iters:
         n = min(chunk, max_iters - it)
         ctx.run(n)
         ms += ctx.stats()["last_run_ms"]
         it += n
-        best = best_over_chains(ctx, chains)
-        if target is not None and best <= target and reached is None:
-            reached = (ms, it)
-            break
+        best = ctx.costs()[1].reshape(n_inst, chains).min(1)
+        hist.append((ms, best.copy()))
+        if targets is not None:
+            if horizon_ms is not None and share_at is None and ms >= horizon_ms:
+                share_at = float(np.mean(best <= targets))
+            if (best <= targets).all():
+                reached = (ms, it)
+                break
     ctx.close()
-    return (reached[0] if reached else None), (reached[1] if reached else it), best, ms
+    return {"ms": reached[0] if reached else None, "iters": reached[1] if reached else it, "best": best,
+            "total_ms": ms, "hist": hist, "share_at_horizon": share_at}
 
 
-def learned_vs_plain(args, vns, stream, table, key):
-    """Time to the plain method's best cost: plain search vs the learned search (scorer trained on moves the
-    search logged on disjoint training instances), same instance, seeds and chains, on this GPU."""
+LEARNED_SETUP = {
+    # evaluation workload -> (training workload, first training index, training instances, chains while logging)
+    "plain_100x52": ("learned_100x52", 100, 16, 16),
+    "learned_batched_1024": ("learned_batched_1024", 4096, 16, 4),
+}
+
+
+def learned_vs_plain(args, vns, stream, table, key, name, insts, seed, chains, nb):
+    """Time to the plain method's best cost, per instance: plain search vs the learned search (scorer
+    trained on moves the search logged on disjoint training instances), same instances, seeds and chains,
+    on this GPU."""
     import numpy as np
-    from paper_1704_05132_amd.instances import WORKLOADS, workload
-    w = WORKLOADS["learned_100x52"]
-    inst = workload("learned_100x52", 0)
-    seed, chains, chunk = WORKLOADS["plain_100x52"]["seed"], w["chains"], args.chunk
+    from paper_1704_05132_amd.instances import workload
+    target = insts[0] if len(insts) == 1 else insts
+    n_inst, chunk = len(insts), args.chunk
 
     def make(options=None):
-        c = vns.Context(inst, seed=seed, chains=chains, nb_list=w["nb"], trace=False, options=options)
+        c = vns.Context(target, seed=seed, chains=chains, nb_list=nb, trace=False, options=options)
         c.bind_stream(stream)
         table.apply(c, key)
         return c
 
-    # plain: best over chains after the workload's iterations, and the device time to first reach it
-    _, _, B, plain_total = chunked_search(make, chains, None, args.steps, chunk)
-    plain_ms, plain_it, _, _ = chunked_search(make, chains, B, args.steps, chunk)
+    # plain: per-instance best after the workload's iterations, and the device time to first reach all
+    plain = chunked_search(make, n_inst, chains, args.steps, chunk)
+    B = plain["best"]
+    plain_ms = next(ms for ms, b in plain["hist"] if (b <= B).all())
+    plain_it = chunk * (1 + next(i for i, (_, b) in enumerate(plain["hist"]) if (b <= B).all()))
 
     # training set: moves logged by the search on disjoint instances
-    train = [workload("learned_100x52", 100 + j) for j in range(args.learned_train_instances)]
+    tw, t0i, n_train, log_chains = LEARNED_SETUP[name]
+    train = [workload(tw, t0i + j) for j in range(min(args.learned_train_instances, n_train))]
     t0 = time.perf_counter()
-    with vns.Context(train, seed=w["seed"], chains=16, nb_list=w["nb"], trace=False,
+    with vns.Context(train, seed=seed, chains=log_chains, nb_list=nb, trace=False,
                      options={vns.OPT_LOG: 2_000_000}) as lg:
         lg.bind_stream(stream)
         lg.run(args.learned_log_iters)
@@ -182,13 +202,15 @@ def learned_vs_plain(args, vns, stream, table, key):
         c.mlp_set(params)
         return c
 
-    lrn_ms, lrn_it, lrn_best, lrn_total = chunked_search(make_learned, chains, B, 2 * args.steps, chunk)
-    return {
-        "plain_best_F": int(B),
-        "plain_ms_to_best": plain_ms, "plain_iters_to_best": plain_it,
-        "learned_ms_to_plain_best": lrn_ms, "learned_iters": lrn_it, "learned_best_F": int(lrn_best),
-        "learned_reached": lrn_ms is not None,
-        "speedup": (plain_ms / lrn_ms) if lrn_ms else None,
+    lrn = chunked_search(make_learned, n_inst, chains, 2 * args.steps, chunk, targets=B, horizon_ms=plain["total_ms"])
+    if lrn["share_at_horizon"] is None:   # reached (or stopped) before the plain run's total time
+        lrn["share_at_horizon"] = float(np.mean(lrn["best"] <= B))
+    out = {
+        "instances": n_inst, "chains": chains,
+        "plain_ms_to_best": plain_ms, "plain_iters_to_best": plain_it, "plain_total_ms": plain["total_ms"],
+        "learned_ms_to_plain_best": lrn["ms"], "learned_iters": lrn["iters"], "learned_reached": lrn["ms"] is not None,
+        "learned_share_at_plain_total_ms": lrn["share_at_horizon"],
+        "speedup": (plain_ms / lrn["ms"]) if lrn["ms"] else None,
         "permille_priced": args.learned_permille, "chunk_iters": chunk,
         "training": {"instances": len(train), "logged_moves": int(len(y)),
                      "improving_share": float(np.mean(y < 0)) if len(y) else 0.0,
@@ -205,6 +227,13 @@ def learned_vs_plain(args, vns, stream, table, key):
                    "flop_per_row": MLP_FLOP_PER_ROW},
         "note": "device time of the search launches only; scorer training is reported separately",
     }
+    if n_inst == 1:
+        out["plain_best_F"] = int(B[0])
+        out["learned_best_F"] = int(lrn["best"][0])
+    else:
+        out["plain_best_F_sum"] = int(B.sum())
+        out["learned_best_F_sum"] = int(lrn["best"].sum())
+    return out
 
 
 def main():
@@ -331,8 +360,12 @@ def main():
                   "value": sweep_ev / (sweep_med / 1e3), "unit": "move-evals/s", "achieved": sweep_achieved,
                   "peak": peak, "frac": sweep_achieved / peak, "traffic": measured_traffic("k_eval", name)},
     }
-    if name == "plain_100x52" and not args.no_learned:
-        out["time_to_plain_best"] = learned_vs_plain(args, vns, stream, table, key)
+    if name in LEARNED_SETUP and not args.no_learned:
+        out["time_to_plain_best"] = learned_vs_plain(args, vns, stream, table, key, name, insts, w["seed"], chains,
+                                                     w["nb"])
+    if name == "learned_batched_1024" and not args.no_cpu_baseline:
+        out["cpu_baseline"] = None   # one oracle iteration from the initial solution of K ~ 550 products takes minutes
+        args.no_cpu_baseline = True
     if not args.no_cpu_baseline:
         rng = __import__("numpy").random.default_rng(0)
         order = rng.permutation(len(insts)) if len(insts) > 1 else [0] * 16

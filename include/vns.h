@@ -179,6 +179,10 @@ vns_status vns_run(vns_ctx *ctx, int32_t iters);
 /* vns_get_cost — current objective F and the best objective seen, of one chain (either may be NULL). */
 vns_status vns_get_cost(vns_ctx *ctx, int32_t chain, int64_t *F, int64_t *F_best);
 
+/* vns_get_costs — F and the best objective of every chain, [vns_num_chains] int64 each (either may be
+ * NULL): one device-to-host copy instead of one call per chain. */
+vns_status vns_get_costs(vns_ctx *ctx, int64_t *F, int64_t *F_best);
+
 /* vns_get_solution — current setup rows of one chain, [K*T] uint8 0/1 each, row-major [k][t]. */
 vns_status vns_get_solution(vns_ctx *ctx, int32_t chain, uint8_t *zM, uint8_t *zR);
 

@@ -266,8 +266,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     // weight fragments
     const int rows_entries = run_rows_entries(a.lds_rows, W);
     char *lbase = reinterpret_cast<char *>(s_rows + rows_entries) + wave * kLearnedWaveBytes;
-    LearnedLds L{reinterpret_cast<__bf16 *>(lbase), reinterpret_cast<__bf16 *>(lbase + 64 * 16 * 2),
-                 reinterpret_cast<uint16_t *>(lbase + 64 * 16 * 2 + 64 * 64 * 2)};
+    LearnedLds L{reinterpret_cast<__bf16 *>(lbase), reinterpret_cast<uint16_t *>(lbase + 64 * 16 * 2)};
     mlp::Frags fr;
     if constexpr (LEARNED) mlp::load_frags(a.mlp, fr);
     const uint64_t nflip_all = 2ull * (uint64_t)K * (uint64_t)T;
@@ -342,7 +341,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             __syncthreads();
             if (gid < G && role == 0 && lane == 0) take(sp.grp[gid]);
             __syncthreads();
-            for (int round = 0;; ++round) {
+            for (;;) {
                 bool any = false;
                 for (int gg = 0; gg < G; ++gg) any |= sp.grp[gg].active != 0;
                 if (!any) break;
@@ -475,7 +474,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         if constexpr (LEARNED) {
                             int fb = 0;
                             const bool id = need_ident;
-                            key = learned_best_move(b, row, T, pp, nb, sh.list[wave], L, fr, a.mlp, a.permille, id, cost,
+                            key = learned_best_move(b, row, T, pp, nb, sh.list[wave], L, fr, a.permille, id, cost,
                                                     evals, fb);
                             ++nb_evals;
                             fallbacks += fb;
@@ -623,7 +622,6 @@ __global__ __launch_bounds__(64) void k_eval_learned(EvalLearnedArgs a, int64_t 
     __shared__ uint16_t s_list[2 * kTMax];
     __shared__ uint16_t s_sel[2 * kTMax];
     __shared__ __attribute__((aligned(16))) __bf16 s_x[64 * 16];   // read as 16-byte vectors
-    __shared__ __attribute__((aligned(16))) __bf16 s_h[64 * 64];
     const int64_t cp = cp_begin + blockIdx.x;
     const int g = a.cp_chain[cp];
     const ChainInfo ci = a.chains[g];
@@ -638,8 +636,8 @@ __global__ __launch_bounds__(64) void k_eval_learned(EvalLearnedArgs a, int64_t 
     int64_t cost = a.cur_cost[cp], evals = 0;
     int fb = 0;
     const int64_t off = a.slot_off[g] + (int64_t)p * 4 * T;
-    LearnedLds L{s_x, s_h, s_sel};
-    const uint64_t key = learned_best_move(b, s_row, T, pp, a.nb, s_list, L, fr, a.mlp, a.permille, false, cost, evals,
+    LearnedLds L{s_x, s_sel};
+    const uint64_t key = learned_best_move(b, s_row, T, pp, a.nb, s_list, L, fr, a.permille, false, cost, evals,
                                            fb, a.scores ? a.scores + off : nullptr, a.selected ? a.selected + off : nullptr);
     if (threadIdx.x == 0) {
         const int64_t F = a.cstate[g].F;

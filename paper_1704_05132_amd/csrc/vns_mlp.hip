@@ -29,12 +29,12 @@ __device__ __forceinline__ void stage_features(const float *__restrict__ X, int6
 __global__ __launch_bounds__(64) void k_mlp_score(const float *__restrict__ P, const float *__restrict__ X, int64_t n,
                                                   float *__restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) __bf16 s_mlp[];
-    __bf16 *sx = s_mlp, *sh = s_mlp + 64 * kF;
+    __bf16 *sx = s_mlp;
     Frags fr;
     load_frags(P, fr);
     const int64_t row = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
     stage_features(X, row, n, sx);
-    const float s = forward64(sx, sh, fr, P);
+    const float s = forward64(sx, fr);
     if (row < n) out[row] = s;
 }
 
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(64) void k_mlp_fwd_cache(const float *__restrict__ 
                                                       float *__restrict__ s_out, float *__restrict__ z1,
                                                       float *__restrict__ z2) {
     extern __shared__ __attribute__((aligned(16))) __bf16 s_mlp[];
-    __bf16 *sx = s_mlp, *sh = s_mlp + 64 * kF;
+    __bf16 *sx = s_mlp;
     Frags fr;
     load_frags(P, fr);
     const int lane = threadIdx.x & 63;
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(64) void k_mlp_fwd_cache(const float *__restrict__ 
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const float s = forward64(sx, sh, fr, P, z1 + base * kH, z2 + base * kH);
+    const float s = forward64(sx, fr, z1 + base * kH, z2 + base * kH);
     if (r < n) s_out[r] = s;
 }
 

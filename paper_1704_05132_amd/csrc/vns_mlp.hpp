@@ -8,8 +8,8 @@
 //   setup period > t (T if none).
 // Parameters (float32 master copy, 5313 values): W1 [16][64] row-major, b1 [64], W2 [64][64], b2 [64],
 // W3 [64], b3.  The forward pass rounds weights and every layer's input to bfloat16 (nearest even); the
-// products are accumulated in float32 by v_mfma_f32_16x16x32_bf16 (layers 1 and 2) and by a float32 dot
-// product (layer 3).
+// products are accumulated in float32 by v_mfma_f32_16x16x32_bf16 (layers 1 and 2) and by float32 dot
+// products (layer 3).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,100 +23,96 @@ constexpr int kF = 16;
 constexpr int kH = 64;
 constexpr int kParams = 5313;
 constexpr int oW1 = 0, oB1 = 1024, oW2 = 1088, oB2 = 5184, oW3 = 5248, oB3 = 5312;
-constexpr int kWaveLdsBytes = 64 * kF * 2 + 64 * kH * 2;   // feature tile + hidden tile, bfloat16
+constexpr int kWaveLdsBytes = 64 * kF * 2;   // feature tile of 64 moves, bfloat16
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-// Per-lane B-operand fragments of W1 and W2 (lane l: column l % 16, rows 8*(l/16) .. +7 of a 32-row slice).
+// The network is evaluated transposed, H^T = W^T X^T, on v_mfma_f32_16x16x32_bf16 (lane l = 16 g + c holds
+// A[c][8g..8g+7], B[8g..8g+7][c] and D[4g..4g+3][c]): with hidden units as the M dimension and moves as N,
+// the D fragment of layer 1 is, unchanged, the B fragment of layer 2 once layer 2's input units are taken
+// in the order pi(kt, 8g + e) = 32 kt + 16 (e / 4) + 4 g + e % 4 (D of hidden tiles 2kt and 2kt+1), so no
+// activation leaves the registers.  Biases initialise the accumulators.
 struct Frags {
-    bf8 w1[4];      // [n-tile], rows 16..31 of the zero-padded W1 are 0
-    bf8 w2[2][4];   // [k-slice][n-tile]
+    bf8 w1t[4];       // [hidden tile]: W1^T rows 16mt + c, features 8g..8g+7 (features >= 16 are zero)
+    bf8 w2t[4][2];    // [output tile][k-slice]: W2^T rows 16mo + c, inputs pi(kt, 8g..8g+7)
+    f4 b1[4];         // [hidden tile]: b1[16mt + 4g + e]
+    f4 b2[4];         // [output tile]: b2[16mo + 4g + e]
+    f4 w3[4];         // [output tile]: bfloat16-rounded W3[16mo + 4g + e]
+    float b3;
 };
 
 __device__ __forceinline__ void load_frags(const float *__restrict__ P, Frags &fr) {
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt)
+    for (int mt = 0; mt < 4; ++mt) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int k = 8 * g + e;
-            fr.w1[nt][e] = k < kF ? (__bf16)P[oW1 + k * kH + 16 * nt + c] : (__bf16)0.f;
+            fr.w1t[mt][e] = k < kF ? (__bf16)P[oW1 + k * kH + 16 * mt + c] : (__bf16)0.f;
         }
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt)
+        for (int e = 0; e < 4; ++e) {
+            fr.b1[mt][e] = P[oB1 + 16 * mt + 4 * g + e];
+            fr.b2[mt][e] = P[oB2 + 16 * mt + 4 * g + e];
+            fr.w3[mt][e] = (float)(__bf16)P[oW3 + 16 * mt + 4 * g + e];
+        }
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+        for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-            for (int e = 0; e < 8; ++e) fr.w2[kt][nt][e] = (__bf16)P[oW2 + (32 * kt + 8 * g + e) * kH + 16 * nt + c];
+            for (int e = 0; e < 8; ++e) {
+                const int in = 32 * kt + 16 * (e >> 2) + 4 * g + (e & 3);
+                fr.w2t[mt][kt][e] = (__bf16)P[oW2 + in * kH + 16 * mt + c];
+            }
+    }
+    fr.b3 = P[oB3];
 }
 
-// Scores of 64 rows whose features sit in sx ([64][16] bfloat16); sh is a [64][64] bfloat16 scratch tile.
-// Every lane of the wavefront must call it; lane l receives the score of row l.  When z1 / z2 are given, the
-// pre-activations of the two hidden layers (float32, [64][64] row-major) are stored there as well.
-__device__ __forceinline__ float forward64(const __bf16 *sx, __bf16 *sh, const Frags &fr,
-                                           const float *__restrict__ P, float *z1 = nullptr, float *z2 = nullptr) {
+// Scores of 64 rows whose features sit in sx ([64][16] bfloat16).  Every lane of the wavefront must call it;
+// lane l receives the score of row l.  When z1 / z2 are given, the pre-activations of the two hidden layers
+// (float32, [64][64] row-major) are stored there as well.
+__device__ __forceinline__ float forward64(const __bf16 *sx, const Frags &fr, float *z1 = nullptr,
+                                           float *z2 = nullptr) {
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
     const bf8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-    // layer 1: [64 x 32(16 used)] x [32 x 64]
+    float mine = 0.f;
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {       // 16 moves at a time
+        const int row = 16 * nt + c;
+        const bf8 x = g < 2 ? *reinterpret_cast<const bf8 *>(sx + row * kF + 8 * g) : zero8;
+        f4 d1[4];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const bf8 a = g < 2 ? *reinterpret_cast<const bf8 *>(sx + (16 * mt + c) * kF + 8 * g) : zero8;
-        f4 acc[4];
+        for (int mt = 0; mt < 4; ++mt) d1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w1t[mt], x, fr.b1[mt], 0, 0, 0);
+        if (z1) {
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const f4 z = {0.f, 0.f, 0.f, 0.f};
-            acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, fr.w1[nt], z, 0, 0, 0);
+            for (int mt = 0; mt < 4; ++mt) *reinterpret_cast<f4 *>(z1 + row * kH + 16 * mt + 4 * g) = d1[mt];
         }
+        bf8 h[2];
 #pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
+        for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float z = acc[nt][e] + P[oB1 + 16 * nt + c];
-                if (z1) z1[(16 * mt + 4 * g + e) * kH + 16 * nt + c] = z;
-                sh[(16 * mt + 4 * g + e) * kH + 16 * nt + c] = (__bf16)fmaxf(z, 0.f);
+                h[kt][e] = (__bf16)fmaxf(d1[2 * kt][e], 0.f);
+                h[kt][4 + e] = (__bf16)fmaxf(d1[2 * kt + 1][e], 0.f);
             }
+        float acc3 = 0.f;
+#pragma unroll
+        for (int mo = 0; mo < 4; ++mo) {
+            f4 d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][0], h[0], fr.b2[mo], 0, 0, 0);
+            d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][1], h[1], d2, 0, 0, 0);
+            if (z2) *reinterpret_cast<f4 *>(z2 + row * kH + 16 * mo + 4 * g) = d2;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc3 += (float)(__bf16)fmaxf(d2[e], 0.f) * fr.w3[mo][e];
+        }
+        // layer 3: sum the four lane groups' partial dot products of each column; lane 16 nt + c keeps it
+        acc3 += __shfl_xor(acc3, 16, 64);
+        acc3 += __shfl_xor(acc3, 32, 64);
+        mine = nt == g ? acc3 : mine;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // layer 2: [64 x 64] x [64 x 64]; all outputs are kept in registers before the tile is overwritten
-    f4 h2[4][4];
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const bf8 a0 = *reinterpret_cast<const bf8 *>(sh + (16 * mt + c) * kH + 8 * g);
-        const bf8 a1 = *reinterpret_cast<const bf8 *>(sh + (16 * mt + c) * kH + 32 + 8 * g);
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const f4 z = {0.f, 0.f, 0.f, 0.f};
-            f4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, fr.w2[0][nt], z, 0, 0, 0);
-            h2[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, fr.w2[1][nt], acc, 0, 0, 0);
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int mt = 0; mt < 4; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float z = h2[mt][nt][e] + P[oB2 + 16 * nt + c];
-                if (z2) z2[(16 * mt + 4 * g + e) * kH + 16 * nt + c] = z;
-                sh[(16 * mt + 4 * g + e) * kH + 16 * nt + c] = (__bf16)fmaxf(z, 0.f);
-            }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // layer 3: dot product of row `lane` with W3
-    float s = P[oB3];
-#pragma unroll 8
-    for (int j = 0; j < kH; ++j) s += (float)sh[lane * kH + j] * (float)(__bf16)P[oW3 + j];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    return s;
+    return fr.b3 + mine;
 }
 
 // Last setup period <= t and first setup period > t of the pattern s (either type); -1 / T when none.

@@ -744,6 +744,18 @@ extern "C" vns_status vns_get_cost(vns_ctx *c, int32_t chain, int64_t *F, int64_
     return VNS_OK;
 }
 
+extern "C" vns_status vns_get_costs(vns_ctx *c, int64_t *F, int64_t *F_best) {
+    VNS_LIVE(c);
+    std::vector<ChainState> cs(c->chains.size());
+    VNS_HIP(c, hipMemcpyAsync(cs.data(), c->d_cs, sizeof(ChainState) * cs.size(), hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    for (size_t g = 0; g < cs.size(); ++g) {
+        if (F) F[g] = cs[g].F;
+        if (F_best) F_best[g] = cs[g].F_best;
+    }
+    return VNS_OK;
+}
+
 extern "C" vns_status vns_get_solution(vns_ctx *c, int32_t chain, uint8_t *zM, uint8_t *zR) {
     VNS_LIVE(c);
     vns_status s = check_chain(c, chain);

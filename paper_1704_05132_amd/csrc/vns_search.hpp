@@ -118,10 +118,9 @@ __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *ro
     return wave_min_u64(best);
 }
 
-// Per-wavefront LDS of the learned search: the scorer's feature and hidden tiles and the selected moves.
+// Per-wavefront LDS of the learned search: the scorer's feature tile and the selected moves.
 struct LearnedLds {
     __bf16 *sx;        // [64][16]
-    __bf16 *sh;        // [64][64]
     uint16_t *sel;     // [2 * kTMax]
 };
 
@@ -133,7 +132,7 @@ struct LearnedLds {
 // the scores and the selection.
 __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 *row, int T, const ProdParams &pp,
                                                       uint32_t nb, uint16_t *list, const LearnedLds &L,
-                                                      const mlp::Frags &fr, const float *__restrict__ P, int permille,
+                                                      const mlp::Frags &fr, int permille,
                                                       bool ident, int64_t &cost, int64_t &evals, int &fallback,
                                                       float *score_out = nullptr, uint8_t *sel_out = nullptr) {
     const int lane = threadIdx.x & 63;
@@ -157,7 +156,7 @@ __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 
 #pragma unroll
         for (int i = 0; i < mlp::kF; ++i) L.sx[lane * mlp::kF + i] = (__bf16)f[i];
         wave_sync_lds();
-        const float s = mlp::forward64(L.sx, L.sh, fr, P);
+        const float s = mlp::forward64(L.sx, fr);
         if (idx < nitems) {
             sk[ch] = ((uint64_t)mlp::sortable(s) << 32) | (uint64_t)slot;
             if (score_out) score_out[slot] = s;

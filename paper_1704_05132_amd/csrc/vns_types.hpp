@@ -92,7 +92,7 @@ struct RunArgs {
 
 // Dynamic LDS of the search kernel: the rows region (int2 entries, an even number so that what follows is
 // 16-byte aligned), then per wavefront the learned-search tiles.
-constexpr int kLearnedWaveBytes = 64 * 16 * 2 + 64 * 64 * 2 + 2 * kTMax * 2;
+constexpr int kLearnedWaveBytes = 64 * 16 * 2 + 2 * kTMax * 2;
 static_assert(kLearnedWaveBytes % 16 == 0, "learned tiles stay 16-byte aligned");
 __host__ __device__ inline int run_rows_entries(int lds_rows, int waves) {
     const int e = lds_rows > waves * kTMax ? lds_rows : waves * kTMax;

@@ -42,6 +42,7 @@ SIGNATURES = {
     "vns_eval_neighbourhood": (_c.c_int, [_P, _c.c_uint32, _c.c_int32, _P, _P, _P, _P, _P]),
     "vns_run": (_c.c_int, [_P, _c.c_int32]),
     "vns_get_cost": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64)]),
+    "vns_get_costs": (_c.c_int, [_P, _P, _P]),
     "vns_get_solution": (_c.c_int, [_P, _c.c_int32, _P, _P]),
     "vns_set_solution": (_c.c_int, [_P, _c.c_int32, _P, _P]),
     "vns_get_trajectory": (_c.c_int, [_P, _c.c_int32, _P, _c.c_int64, _c.POINTER(_c.c_int64)]),
@@ -211,6 +212,13 @@ class Context:
         F, Fb = ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().vns_get_cost(self.h, int(chain), ctypes.byref(F), ctypes.byref(Fb)))
         return int(F.value), int(Fb.value)
+
+    def costs(self):
+        """(F, F_best) of every chain as int64 arrays (one copy)."""
+        F = np.empty(self.n_chains, np.int64)
+        Fb = np.empty(self.n_chains, np.int64)
+        self._check(lib().vns_get_costs(self.h, _ptr(F), _ptr(Fb)))
+        return F, Fb
 
     def solution(self, chain: int):
         inst = self.chain_instance(chain)

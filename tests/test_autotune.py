@@ -28,3 +28,21 @@ def test_table_round_trip(tmp_path):
     t2 = autotune.TuneTable(tmp_path / "tune.json")
     assert t2.get("k")["choice"] == {"waves": 4, "lds": 0}
     assert t2.get("k")["timings_ms"] == [[{"waves": 4, "lds": 0}, 1.5]]
+
+
+def test_search_options_map_every_key():
+    from paper_1704_05132_amd import vns
+    assert autotune.search_options(dict(waves=4, lds=0, spec=0)) == {vns.OPT_RUN_WAVES: 4, vns.OPT_RUN_LDS: 0,
+                                                                      vns.OPT_SPECULATE: 0}
+    assert autotune.search_options(dict(spec=1, spec_waves=9, lds=65536)) == {vns.OPT_SPECULATE: 1,
+                                                                               vns.OPT_SPEC_WAVES: 9,
+                                                                               vns.OPT_RUN_LDS: 65536}
+    assert autotune.search_options({"group": 8}) == {}
+
+
+def test_candidates_cover_both_search_kernels():
+    kinds = {c.get("spec", 0) for c in autotune.SEARCH_CANDIDATES}
+    assert kinds == {0, 1}
+    for c in autotune.SEARCH_CANDIDATES:
+        if c.get("spec"):
+            assert c["spec_waves"] % 3 == 0 and 3 <= c["spec_waves"] <= 16   # whole groups of three waves
