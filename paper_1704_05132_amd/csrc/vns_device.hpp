@@ -90,11 +90,14 @@ __device__ __forceinline__ void decode_step(DecodeState &s, int32_t sm, int32_t 
     and_or(s.bad, rr, s.nolast);          // demand with no manufacturing setup at or before it
 }
 
+// Cost from the final decode state; only the first NW setup words of b are read (the others are zero when
+// T <= 32 NW).
+template <int NW = kWords>
 __device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bits &b, int T, const ProdParams &pp) {
     if (s.bad) return kInf;
     int32_t nM = 0, nR = 0;
 #pragma unroll
-    for (int j = 0; j < kWords; ++j) {
+    for (int j = 0; j < NW; ++j) {
         nM += __popc(b.m[j]);
         nR += __popc(b.r[j]);
     }
@@ -121,8 +124,9 @@ __device__ __forceinline__ void decode_chunk(DecodeState &s, int32_t m, int32_t 
 // be the same in every active lane.  The periods are walked in chunks of four; the rows of the next chunk
 // are read while the current one is decoded, alternating between two register sets so that nothing is
 // copied, and never past period T - 1.
-template <class RowPtr>
+template <int NW = kWords, class RowPtr>
 __device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T, const ProdParams &pp) {
+    static_assert(NW >= 1 && NW <= kWords, "setup words");
     T = __builtin_amdgcn_readfirstlane(T);
     DecodeState s;
     const int Tc = T - 4;   // start of the last whole chunk
@@ -130,7 +134,7 @@ __device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T,
     if (Tc >= 0) load_chunk(row, 0, ca);
     int tau = 0;
 #pragma unroll
-    for (int j = 0; j < kWords; ++j) {
+    for (int j = 0; j < NW; ++j) {
         if (32 * j >= T) break;
         const int32_t m = (int32_t)b.m[j], r = (int32_t)b.r[j];
         const int wend = min(32 * j + 32, T);
@@ -150,7 +154,37 @@ __device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T,
         for (; tau < wend; ++tau)   // the last one to three periods
             decode_step(s, __builtin_amdgcn_sbfe(m, tau & 31, 1), __builtin_amdgcn_sbfe(r, tau & 31, 1), tau, row[tau]);
     }
-    return decode_finish(s, b, T, pp);
+    return decode_finish<NW>(s, b, T, pp);
+}
+
+// Apply a move given as (block, t) to the first NW setup words of b: block 0 flips zM(t), 1 flips zR(t),
+// 2 swaps zM(t), zM(t+1), 3 swaps zR(t), zR(t+1) (a valid swap: the two bits differ, so the swap flips
+// both).  The change is one XOR mask over the 32 NW bits of the pattern.
+template <int NW>
+__device__ __forceinline__ void xor_move(Bits &b, int blk, int t) {
+    static_assert(NW == 2 || NW == 4, "setup words");
+    const uint64_t w = blk >= 2 ? 3ull : 1ull;
+    const bool on_r = blk & 1;
+    uint64_t lo, hi = 0;
+    if constexpr (NW == 2) {
+        lo = w << t;
+    } else {
+        const uint64_t sh = w << (t & 63);
+        lo = t < 64 ? sh : 0ull;
+        hi = t >= 64 ? sh : (t == 63 ? (w >> 1) : 0ull);   // a swap at 63 reaches bit 64
+    }
+    const uint64_t xm0 = on_r ? 0ull : lo, xr0 = on_r ? lo : 0ull;
+    b.m[0] ^= (uint32_t)xm0;
+    b.m[1] ^= (uint32_t)(xm0 >> 32);
+    b.r[0] ^= (uint32_t)xr0;
+    b.r[1] ^= (uint32_t)(xr0 >> 32);
+    if constexpr (NW == 4) {
+        const uint64_t xm1 = on_r ? 0ull : hi, xr1 = on_r ? hi : 0ull;
+        b.m[2] ^= (uint32_t)xm1;
+        b.m[3] ^= (uint32_t)(xm1 >> 32);
+        b.r[2] ^= (uint32_t)xr1;
+        b.r[3] ^= (uint32_t)(xr1 >> 32);
+    }
 }
 
 // Feasibility of a pattern: only the periods before the first manufacturing setup can fail (afterwards

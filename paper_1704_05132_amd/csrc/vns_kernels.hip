@@ -78,24 +78,26 @@ struct EvalShared {
     int64_t out_off[kEvalGroup];
     int32_t off[kEvalGroup + 1];
     int32_t nswap[kEvalGroup];
-    uint16_t swap[kEvalGroup][2 * kTMax];
+    // the workgroup's moves, chain by chain (flips, then zM swaps, then zR swaps): chain << 9 | block << 7 | t
+    uint16_t item[kEvalGroup * 4 * kTMax];
 };
+static_assert(kEvalGroup <= 16 && kTMax <= 128, "item packing");
 
-__device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, int n, int nflip, bool fm, int T,
-                                           const ProdParams &pp) {
+__device__ __forceinline__ uint16_t pack_item(int j, int blk, int t) { return (uint16_t)((j << 9) | (blk << 7) | t); }
+
+// One lane per item: apply the move to the chain's pattern, decode, fold (cost, slot) into the chain's key.
+template <int NW>
+__device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, int N, int T, const ProdParams &pp) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int N = sh.off[n];
     for (int basei = wave * 64; basei < N; basei += blockDim.x) {
         const int idx = basei + lane;
         const bool in = idx < N;
-        int j = 0;
-        for (int q = 1; q < n; ++q) j += (idx >= sh.off[q]) ? 1 : 0;
-        const int i = idx - sh.off[j];
-        int slot = 0;
-        if (in) slot = i < nflip ? (fm ? i : T + i) : (int)sh.swap[j][i - nflip];
+        const int e = sh.item[in ? idx : basei];
+        const int j = e >> 9, blk = (e >> 7) & 3, t = e & 127;
+        const int slot = blk * T + t;
         Bits mb = sh.bits[j];
-        apply_move(mb, slot, T);
-        const int64_t c = decode_cost(mb, sh.row, T, pp);
+        xor_move<NW>(mb, blk, t);
+        const int64_t c = decode_cost<NW>(mb, sh.row, T, pp);
         if (in) {
             if (c != kInf) atomicMin(&sh.key[j], ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
             if (a.slot_price) a.slot_price[sh.out_off[j] + slot] = c == kInf ? kInf : sh.F[j] - sh.cost[j] + c;
@@ -128,9 +130,15 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restri
 
     const bool fm = a.nb_mask & 1u, fr = a.nb_mask & 2u, shift = a.nb_mask & 4u;
     const int nflip = (fm ? T : 0) + (fr ? T : 0);
+    // swap counts per chain
     for (int j = wave; j < n; j += nw) {
         int ns = 0;
-        if (shift) ns = build_swap_list(sh.bits[j], T, sh.swap[j], lane);
+        if (shift) {
+            uint32_t vm[kWords], vr[kWords];
+            swap_valid(sh.bits[j].m, T, vm);
+            swap_valid(sh.bits[j].r, T, vr);
+            ns = popc_words(vm) + popc_words(vr);
+        }
         if (lane == 0) sh.nswap[j] = ns;
     }
     if (a.slot_price) {  // every slot of the group starts as "not a priced move"
@@ -147,13 +155,41 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restri
         sh.off[n] = o;
     }
     __syncthreads();
+    // the item table: flips (zM then zR), then each chain's valid swaps in period order
+    const int fblk0 = fm ? 0 : 1;
+    for (int j = wave; j < n; j += nw) {
+        uint16_t *it = sh.item + sh.off[j];
+        for (int i = lane; i < nflip; i += 64) {
+            const int blk = fblk0 + (i >= T ? 1 : 0);
+            it[i] = pack_item(j, blk, i - (i >= T ? T : 0));
+        }
+        if (shift) {
+            uint32_t vm[kWords], vr[kWords];
+            swap_valid(sh.bits[j].m, T, vm);
+            swap_valid(sh.bits[j].r, T, vr);
+            const int nm = popc_words(vm);
+            for (int t = lane; t < T - 1; t += 64) {
+                bool sm, sr;
+                const int pm = rank_bit(vm, t, sm);
+                const int pr = rank_bit(vr, t, sr);
+                if (sm) it[nflip + pm] = pack_item(j, 2, t);
+                if (sr) it[nflip + nm + pr] = pack_item(j, 3, t);
+            }
+        }
+    }
+    __syncthreads();
 
-    eval_items(a, sh, n, nflip, fm, T, pp);
+    const int N = sh.off[n];
+    if (T <= 64)
+        eval_items<2>(a, sh, N, T, pp);
+    else
+        eval_items<4>(a, sh, N, T, pp);
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x) a.prod_key[d.cp + (int64_t)j * K] = sh.key[j];
     if (threadIdx.x == 0) {
-        atomicAdd(a.evals, (unsigned long long)sh.off[n]);
-        atomicAdd(a.evals + 1, (unsigned long long)sh.off[n] * (unsigned long long)T);
+        unsigned long long *ctr = a.evals + (size_t)(blockIdx.x & (kCounterSlots - 1)) * kCounterStride;
+        atomicAdd(ctr, (unsigned long long)N);
+        atomicAdd(ctr + 1, (unsigned long long)N * (unsigned long long)T);
     }
 }
 
@@ -644,7 +680,7 @@ __global__ __launch_bounds__(64) void k_eval_learned(EvalLearnedArgs a, int64_t 
         a.prod_price[cp] = key == kInfKey ? kInf : F - cost + (int64_t)(key >> kSlotBits);
         a.prod_slot[cp] = key == kInfKey ? -1 : (int32_t)(key & 0xFFFFu);
         a.fallback[cp] = (uint8_t)fb;
-        atomicAdd(a.evals, (unsigned long long)evals);
+        atomicAdd(a.evals + (size_t)(blockIdx.x & (kCounterSlots - 1)) * kCounterStride, (unsigned long long)evals);
     }
 }
 

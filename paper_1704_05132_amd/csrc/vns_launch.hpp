@@ -60,7 +60,7 @@ struct EvalLearnedArgs {
     int64_t *prod_price;       // [cp]
     int32_t *prod_slot;        // [cp]
     uint8_t *fallback;         // [cp]
-    unsigned long long *evals;
+    unsigned long long *evals; // kCounterSlots slots of kCounterStride words: [0] move-evaluations
     uint32_t nb;
     int32_t permille;
 };

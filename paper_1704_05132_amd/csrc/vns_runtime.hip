@@ -384,7 +384,7 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
     VNS_CREATE_HIP(hipEventCreate(&c->ev1));
     VNS_CREATE_HIP(dmalloc(&c->d_rows, (size_t)n_rows));
     VNS_CREATE_HIP(dmalloc(&c->d_prod, (size_t)n_prod));
-    VNS_CREATE_HIP(dmalloc(&c->d_evals, 2));
+    VNS_CREATE_HIP(dmalloc(&c->d_evals, (size_t)counter_words()));
     VNS_CREATE_HIP(dmalloc(&c->d_mlp, (size_t)mlp::kParams));
     VNS_CREATE_HIP(dmalloc(&c->d_adam_m, (size_t)mlp::kParams));
     VNS_CREATE_HIP(dmalloc(&c->d_adam_v, (size_t)mlp::kParams));
@@ -528,6 +528,20 @@ extern "C" vns_status vns_bind_stream(vns_ctx *c, void *s) {
 // ---------------------------------------------------------------------------------------------------
 // pricing
 // ---------------------------------------------------------------------------------------------------
+// Sums of the spread workgroup counters (waits for the stream).
+static hipError_t read_counters(vns_ctx *c, unsigned long long (&ev)[2]) {
+    std::vector<unsigned long long> h((size_t)counter_words());
+    hipError_t e = hipMemcpyAsync(h.data(), c->d_evals, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    ev[0] = ev[1] = 0;
+    for (int s = 0; s < kCounterSlots; ++s) {
+        ev[0] += h[(size_t)s * kCounterStride];
+        ev[1] += h[(size_t)s * kCounterStride + 1];
+    }
+    return e;
+}
+
 extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32_t chain, int64_t *slot_price,
                                              int64_t *prod_best, int32_t *prod_best_slot, int64_t *best,
                                              int32_t *best_slot) {
@@ -588,7 +602,7 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     ea.prod_key = c->d_prod_key;
     ea.evals = c->d_evals;
     ea.nb_mask = nb_mask;
-    VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, 2 * sizeof(unsigned long long), c->stream));
+    VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long) * counter_words(), c->stream));
     VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
     VNS_HIP(c, launch_eval(ea, c->d_eval_wg, c->eval_wg_n, c->stream));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
@@ -605,8 +619,7 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     if (best_slot)
         VNS_HIP(c, hipMemcpyAsync(best_slot, c->d_best_slot, sizeof(int32_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
     unsigned long long ev[2] = {0, 0};
-    VNS_HIP(c, hipMemcpyAsync(ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost, c->stream));
-    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    VNS_HIP(c, read_counters(c, ev));
     float ms = 0.f;
     VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.last_eval_evals = (int64_t)ev[0];
@@ -1068,7 +1081,7 @@ extern "C" vns_status vns_eval_learned(vns_ctx *c, uint32_t nb, int32_t chain, i
     hipLaunchKernelGGL(k_fill_nan, dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, c->stream, S.p, n_slots);
     VNS_HIP(c, hipGetLastError());
     VNS_HIP(c, hipMemsetAsync(Sel.p, 0, (size_t)n_slots, c->stream));
-    VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, 2 * sizeof(unsigned long long), c->stream));
+    VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long) * counter_words(), c->stream));
     EvalLearnedArgs a{};
     a.cp_chain = c->d_cp_chain;
     a.chains = c->d_chains;
@@ -1094,8 +1107,7 @@ extern "C" vns_status vns_eval_learned(vns_ctx *c, uint32_t nb, int32_t chain, i
     if (prod_best_slot) VNS_HIP(c, hipMemcpyAsync(prod_best_slot, c->d_prod_slot + ci.cp0, sizeof(int32_t) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
     if (fallback) VNS_HIP(c, hipMemcpyAsync(fallback, Fb.p, (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
     unsigned long long ev[2] = {0, 0};
-    VNS_HIP(c, hipMemcpyAsync(ev, c->d_evals, sizeof(ev), hipMemcpyDeviceToHost, c->stream));
-    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    VNS_HIP(c, read_counters(c, ev));
     c->stats.last_eval_evals = (int64_t)ev[0];
     c->stats.last_eval_period_steps = (int64_t)ev[0] * ci.T;
     return VNS_OK;

@@ -88,7 +88,8 @@ __device__ __forceinline__ int move_list(const Bits &b, int T, uint32_t nb, uint
 
 // Exact best move of one neighbourhood for one product, computed by one wavefront: key = cost << 16 | slot.
 // With `ident`, one more item prices the unchanged pattern and its cost is returned in *ident_cost.  With
-// contrast >= 0, *contrast_key receives the key of item contrast (kInfKey when infeasible).
+// contrast >= 0 (any non-negative hash), *contrast_key receives the key of item contrast mod the number of
+// moves (kInfKey when infeasible or when there is no move).
 __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *row, int T, const ProdParams &pp,
                                                    uint32_t nb, uint16_t *list, bool ident, int64_t *ident_cost,
                                                    int64_t &evals, int contrast = -1, uint64_t *contrast_key = nullptr,
@@ -102,6 +103,7 @@ __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *ro
     evals += nitems;
     uint64_t best = kInfKey, ck = kInfKey;
     int64_t idc = 0;
+    const int citem = (contrast >= 0 && nitems > 0) ? contrast % nitems : -1;
     for (int basei = 0; basei < total; basei += 64) {
         const int idx = basei + lane;
         const int slot = idx < nitems ? item_slot(idx, nflip, fm, T, list) : -1;
@@ -110,11 +112,11 @@ __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *ro
         const int64_t c = decode_cost(mb, row, T, pp);
         if (idx == nitems) idc = c;
         const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
-        if (idx == contrast) ck = key;
+        if (idx == citem) ck = key;
         best = key < best ? key : best;
     }
     if (ident) *ident_cost = __shfl(idc, nitems & 63, 64);
-    if (contrast >= 0 && contrast_key) *contrast_key = __shfl(ck, contrast & 63, 64);
+    if (contrast_key) *contrast_key = citem >= 0 ? __shfl(ck, citem & 63, 64) : kInfKey;
     return wave_min_u64(best);
 }
 

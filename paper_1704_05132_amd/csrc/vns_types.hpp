@@ -20,6 +20,11 @@ constexpr int kTMax = 32 * kWords;
 constexpr int kShakeMax = 64;
 constexpr int kMaxWaves = 16;     // wavefronts per search workgroup (8 for the sequential VND, 16 speculative)
 constexpr int kEvalGroup = 16;
+// Workgroup counters are spread over kCounterSlots slots, kCounterStride words apart (one 64-byte line
+// each): every workgroup adding to one device-scope address serialises the launch on that address.
+constexpr int kCounterSlots = 256;
+constexpr int kCounterStride = 8;
+__host__ __device__ constexpr int counter_words() { return kCounterSlots * kCounterStride; }
 constexpr int64_t kRunLdsMax = 128 * 1024;  // dynamic LDS the search kernel may request for instance rows     // chains of one instance priced by one k_eval workgroup
 constexpr int kMaxPasses = 1 << 16;  // VND passes per product and iteration: a guard, not a limit of the method
 constexpr int64_t kInf = INT64_MAX;
@@ -118,7 +123,7 @@ struct EvalArgs {
     int64_t *slot_price;         // optional [sum over chains of 4*K*T]
     const int64_t *price_off;    // [G] offset of each chain's slot block in slot_price
     uint64_t *prod_key;          // [sum over chains of K]: cost << 16 | slot of each product's best move
-    unsigned long long *evals;   // device counters: [0] move-evaluations, [1] their period-steps
+    unsigned long long *evals;   // device counters, kCounterSlots slots: [0] move-evaluations, [1] their period-steps
     uint32_t nb_mask;
 };
 

@@ -184,7 +184,8 @@ def test_move_log_and_trained_scorer_gain(vns):
         ctx.run(60)
         X, y = ctx.move_log()
     say(f"  logged {len(y)} moves, {np.mean(y < 0):.2f} improving")
-    assert len(y) > 1000 and (y < 0).mean() > 0.3
+    # applied moves improve; the contrast moves of the same evaluations are mostly not improving
+    assert len(y) > 1000 and 0.3 < (y < 0).mean() < 0.9
     assert (X[:, :4].sum(1) == 1).all() and (X[:, 14:] >= 0).all() and (X[:, 14:] <= 1).all()
     results = {}
     for name in ("untrained", "trained"):
