@@ -30,9 +30,14 @@ from concurrent.futures import ThreadPoolExecutor
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# int32 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one int32 op per lane per clock)
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+# int32 VALU peak of MI355X for the decode's own operation mix.  256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz give
+# 39.3e12 lane-slots/s.  Of the 14 operations of a period-step, 10 (bfe x2, bfi x4, min, mad x2, and_or) take a
+# lane-slot each and 4 (add, sub x2, the bitop3 of the no-setup mask) take half of one: gfx950 issues that
+# class at twice the rate (measured on the device: ~114-119 against ~62.5 lane-ops per CU per clock).
+# 12 lane-slots per period-step make the peak 3.28e12 period-steps/s, 45.9e12 of these operations per second.
 OPS_PER_PERIOD_STEP = 14     # operations of one period-step of the forward decode
+LANE_SLOTS_PER_STEP = 12
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9 * OPS_PER_PERIOD_STEP / LANE_SLOTS_PER_STEP
 TUNE_FILE = os.path.join(ROOT, "paper_1704_05132_amd", "tune_table.json")
 # learned scorer: 2 x (16*64 + 64*64 + 64) flops per scored move; dense bfloat16 matrix-core peak of MI355X
 MLP_FLOP_PER_ROW = 2 * (16 * 64 + 64 * 64 + 64)

@@ -18,7 +18,7 @@ from typing import Callable, Iterable, Sequence
 
 SEARCH_CANDIDATES = ([dict(waves=w, lds=l, spec=0) for w in (2, 4, 8) for l in (0, 65536)] +
                      [dict(spec=1, spec_waves=s, lds=l) for s in (6, 9, 15) for l in (0, 65536)])
-EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 4, 8, 16)]
+EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 3, 4, 5, 6, 8, 12, 16)]
 
 
 def signature(instances, chains: int) -> str:
@@ -41,13 +41,17 @@ def pick(candidates: Iterable[dict], measure: Callable[[dict], float]):
 
 
 def tune_search(instances, seed: int, chains: int, nb_list: Sequence[int] = (1, 2, 4), iters: int = 20,
-                candidates: Sequence[dict] = tuple(SEARCH_CANDIDATES)):
-    """Time the first `iters` GVNS iterations (one launch, fresh context) for each launch-shape candidate."""
+                candidates: Sequence[dict] = tuple(SEARCH_CANDIDATES), warmup: int = 0):
+    """Time `iters` GVNS iterations (one launch) after `warmup` untimed ones, on a fresh context, for each
+    launch-shape candidate.  The first iterations run the VND of every product; later ones only of the
+    shaken products, so a warm-up tunes for the steady state."""
     from . import vns
 
     def measure(c):
         with vns.Context(instances, seed=seed, chains=chains, nb_list=nb_list, trace=False,
                          options=search_options(c)) as ctx:
+            if warmup > 0:
+                ctx.run(warmup)
             ctx.run(iters)
             return ctx.stats()["last_run_ms"]
 

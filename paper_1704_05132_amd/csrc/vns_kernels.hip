@@ -110,14 +110,10 @@ __device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, in
 __global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restrict__ wg) {
     __shared__ EvalShared sh;
     const EvalWg d = wg[blockIdx.x];
-    const int g0 = a.cp_chain[d.cp];
-    const ChainInfo ci = a.chains[g0];
-    const int K = ci.K, T = ci.T;
-    const int p = (int)(d.cp - ci.cp0);
-    const int n = d.n;
-    const ProdParams pp = a.prod[ci.prod0 + p];
+    const int g0 = d.g0, K = d.K, T = d.T, p = d.p, n = d.n;
+    const ProdParams pp = a.prod[d.prod];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int t = threadIdx.x; t < T; t += blockDim.x) sh.row[t] = a.rows[pp.row + t];
+    for (int t = threadIdx.x; t < T; t += blockDim.x) sh.row[t] = a.rows[d.row + t];
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const int64_t cp = d.cp + (int64_t)j * K;
         sh.bits[j] = a.cur[cp];

@@ -42,6 +42,7 @@ struct vns_ctx {
     // instance data (host)
     int32_t n_inst = 0;
     std::vector<int32_t> K, T, prod0;
+    std::vector<int32_t> prod_row;        // row offset of every product (as in the device product table)
     int64_t n_prod = 0;
     uint64_t seed = 0;
     int device = 0;
@@ -359,6 +360,8 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
     c->T.assign(T, T + n_inst);
     c->prod0 = prod0;
     c->n_prod = n_prod;
+    c->prod_row.resize((size_t)n_prod);
+    for (int64_t q = 0; q < n_prod; ++q) c->prod_row[(size_t)q] = prod[(size_t)q].row;
     c->seed = seed;
     vns_status st = VNS_OK;
     auto bail = [&](vns_status s) {
@@ -578,7 +581,18 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
             const ChainInfo &ci = c->chains[(size_t)g];
             int32_t n = 1;
             while (n < c->eval_group && g + n < g0 + ng && c->chains[(size_t)(g + n)].inst == ci.inst) ++n;
-            for (int32_t p = 0; p < ci.K; ++p) tab.push_back(EvalWg{ci.cp0 + p, n, 0});
+            for (int32_t p = 0; p < ci.K; ++p) {
+                EvalWg w{};
+                w.cp = ci.cp0 + p;
+                w.g0 = g;
+                w.n = n;
+                w.K = ci.K;
+                w.T = ci.T;
+                w.p = p;
+                w.prod = ci.prod0 + p;
+                w.row = c->prod_row[(size_t)(ci.prod0 + p)];
+                tab.push_back(w);
+            }
             g += n;
         }
         dfree(c->d_eval_wg);

@@ -106,9 +106,15 @@ __host__ __device__ inline int run_rows_entries(int lds_rows, int waves) {
 
 // One k_eval workgroup: product cp - chains[cp_chain[cp]].cp0 of the n consecutive chains starting with the
 // chain of cp (chains of one instance are consecutive, their products K apart).
+// One pricing workgroup: product p of chains g0 .. g0+n-1 of one instance.  Everything the workgroup needs
+// to start is here, so its first loads do not wait on one another.
 struct EvalWg {
-    int64_t cp;
-    int32_t n;
+    int64_t cp;      // (chain g0, product p) index into the solution arrays
+    int32_t g0, n;   // first chain, number of chains
+    int32_t K, T;    // the instance's products and periods
+    int32_t p;       // product index within the instance
+    int32_t prod;    // global product index (ProdParams)
+    int32_t row;     // offset of the product's row
     int32_t pad;
 };
 
