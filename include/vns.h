@@ -80,13 +80,17 @@ enum vns_option {
     VNS_OPT_LOG = 10,      /* move-log capacity in records (0 = off, default); a plain vns_run appends, for
                               every applied move, its features and cost change and those of one other
                               priced move of the same evaluation                                       */
-    VNS_OPT_SPECULATE = 11, /* plain search only: 1 (default) = each product's VND runs on a group of
-                              wavefronts, one per neighbourhood of the list, pricing the neighbourhoods
-                              not yet settled in the current pass side by side and applying, in list
-                              order, the first improving one (the others are priced again); the moves
-                              applied are those of the sequential pass and only consumed evaluations
-                              are counted.  0 = one wavefront per product, neighbourhoods in turn      */
-    VNS_OPT_SPEC_WAVES = 12 /* wavefronts per workgroup of the speculative search, 1..16 (default 16)   */
+    VNS_OPT_SPECULATE = 11, /* plain search only: 1 = each product's VND runs on a group of wavefronts,
+                              one per neighbourhood of the list, pricing the neighbourhoods not yet
+                              settled in the current pass side by side and applying, in list order, the
+                              first improving one (the others are priced again); the moves applied are
+                              those of the sequential pass and only consumed evaluations are counted.
+                              0 (default) = one wavefront per product, neighbourhoods in turn           */
+    VNS_OPT_SPEC_WAVES = 12, /* wavefronts per workgroup of the speculative search, 1..16 (default 16)  */
+    VNS_OPT_STATE_LDS = 13  /* 1 (default) = the search kernel keeps each chain's current and working
+                              solutions and costs (80 bytes per product) in LDS for the whole launch
+                              when they fit beside the per-wavefront row slices; 0 = in device memory.
+                              Results do not depend on it                                             */
 };
 
 /* One GVNS iteration of one chain. */

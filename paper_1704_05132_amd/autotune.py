@@ -16,7 +16,7 @@ import json
 from pathlib import Path
 from typing import Callable, Iterable, Sequence
 
-SEARCH_CANDIDATES = ([dict(waves=w, lds=l, spec=0) for w in (2, 4, 8) for l in (0, 65536)] +
+SEARCH_CANDIDATES = ([dict(waves=w, lds=l, spec=0, state=st) for w in (2, 4, 8) for l in (0, 65536) for st in (0, 1)] +
                      [dict(spec=1, spec_waves=s, lds=l) for s in (6, 9, 15) for l in (0, 65536)])
 EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 3, 4, 5, 6, 8, 12, 16)]
 
@@ -59,7 +59,8 @@ def tune_search(instances, seed: int, chains: int, nb_list: Sequence[int] = (1, 
 
 
 def search_options(c: dict) -> dict:
-    """Context options of a search candidate (keys waves, lds, spec, spec_waves; missing keys keep defaults)."""
+    """Context options of a search candidate (keys waves, lds, spec, spec_waves, state; missing keys keep
+    defaults)."""
     from . import vns
     opts = {}
     if "waves" in c:
@@ -70,6 +71,8 @@ def search_options(c: dict) -> dict:
         opts[vns.OPT_SPECULATE] = c["spec"]
     if "spec_waves" in c:
         opts[vns.OPT_SPEC_WAVES] = c["spec_waves"]
+    if "state" in c:
+        opts[vns.OPT_STATE_LDS] = c["state"]
     return opts
 
 

@@ -289,6 +289,29 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         for (int i = threadIdx.x; i < K * T; i += blockDim.x) s_rows[i] = inst_rows[i];
         __syncthreads();
     }
+    // the chain's solution state, indexed by product: in LDS for the whole launch when it fits (copied in
+    // here and back at the end), else in device memory
+    Bits *s_cur, *s_work;
+    int64_t *s_cur_cost, *s_work_cost;
+    if (a.state_off >= 0) {
+        char *base = reinterpret_cast<char *>(s_rows) + a.state_off;
+        s_cur = reinterpret_cast<Bits *>(base);
+        s_work = s_cur + K;
+        s_cur_cost = reinterpret_cast<int64_t *>(s_work + K);
+        s_work_cost = s_cur_cost + K;
+        for (int i = threadIdx.x; i < K; i += blockDim.x) {
+            s_cur[i] = a.cur[cp0 + i];
+            s_work[i] = a.work[cp0 + i];
+            s_cur_cost[i] = a.cur_cost[cp0 + i];
+            s_work_cost[i] = a.work_cost[cp0 + i];
+        }
+        __syncthreads();
+    } else {
+        s_cur = a.cur + cp0;
+        s_work = a.work + cp0;
+        s_cur_cost = a.cur_cost + cp0;
+        s_work_cost = a.work_cost + cp0;
+    }
 
     ChainState cs = a.cstate[g];
     int64_t evals = 0;   // per wavefront (uniform)
@@ -317,7 +340,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 const int l = (int)(f - (uint32_t)p * (uint32_t)(2 * T));
                 int e = -1;
                 for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
-                Bits b = e >= 0 ? sh.db[e] : a.work[cp0 + p];
+                Bits b = e >= 0 ? sh.db[e] : s_work[p];
                 apply_move(b, l, T);
                 // a manufacturing setup in period 0 makes any pattern feasible; otherwise check the prefix
                 bool ok = (b.m[0] & 1u) != 0u;
@@ -358,11 +381,10 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     p = idx;
                     for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
                 }
-                const int64_t cp = cp0 + p;
                 gr.p = p;
-                gr.b = e >= 0 ? sh.db[e] : a.work[cp];
-                gr.c_cur = a.cur_cost[cp];
-                gr.cost = e >= 0 ? kInf : a.work_cost[cp];
+                gr.b = e >= 0 ? sh.db[e] : s_work[p];
+                gr.c_cur = s_cur_cost[p];
+                gr.cost = e >= 0 ? kInf : s_work_cost[p];
                 gr.need_ident = e >= 0;
                 gr.q = 0;
                 gr.improved = 0;
@@ -450,9 +472,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                             gr.improved = 0;
                         } else {
                             if (gr.improved) vnd_err = 1;
-                            const int64_t cp = cp0 + gr.p;
-                            a.work[cp] = gr.b;
-                            a.work_cost[cp] = gr.cost;
+                            s_work[gr.p] = gr.b;
+                            s_work_cost[gr.p] = gr.cost;
                             part += gr.cost - gr.c_cur;
                             take(gr);
                         }
@@ -473,7 +494,6 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     p = idx;
                     for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
                 }
-                const int64_t cp = cp0 + p;
                 const ProdParams pp = a.prod[ci.prod0 + p];
                 const int2 *row;
                 if (rows_in_lds) {
@@ -484,9 +504,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     wave_sync_lds();
                     row = slice;
                 }
-                Bits b = e >= 0 ? sh.db[e] : a.work[cp];
-                const int64_t c_cur = a.cur_cost[cp];
-                int64_t cost = e >= 0 ? kInf : a.work_cost[cp];   // a shaken product is priced with its first move list
+                Bits b = e >= 0 ? sh.db[e] : s_work[p];
+                const int64_t c_cur = s_cur_cost[p];
+                int64_t cost = e >= 0 ? kInf : s_work_cost[p];   // a shaken product is priced with its first move list
                 bool need_ident = e >= 0;
                 bool improved = true;
                 int passes = 0;
@@ -543,8 +563,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     }
                 }
                 if (lane == 0) {
-                    a.work[cp] = b;
-                    a.work_cost[cp] = cost;
+                    s_work[p] = b;
+                    s_work_cost[p] = cost;
                 }
                 part += cost - c_cur;
             }
@@ -566,13 +586,12 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         const int ntouch = cs.lopt ? nd : K;
         for (int idx = threadIdx.x; idx < ntouch; idx += blockDim.x) {
             const int p = cs.lopt ? sh.dp[idx] : idx;
-            const int64_t cp = cp0 + p;
             if (accepted) {
-                a.cur[cp] = a.work[cp];
-                a.cur_cost[cp] = a.work_cost[cp];
+                s_cur[p] = s_work[p];
+                s_cur_cost[p] = s_work_cost[p];
             } else {
-                a.work[cp] = a.cur[cp];
-                a.work_cost[cp] = a.cur_cost[cp];
+                s_work[p] = s_cur[p];
+                s_work_cost[p] = s_cur_cost[p];
             }
         }
         if (a.trace && threadIdx.x == 0) {
@@ -597,6 +616,14 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         __syncthreads();
     }
 
+    if (a.state_off >= 0) {   // every iteration ended with a barrier
+        for (int i = threadIdx.x; i < K; i += blockDim.x) {
+            a.cur[cp0 + i] = s_cur[i];
+            a.work[cp0 + i] = s_work[i];
+            a.cur_cost[cp0 + i] = s_cur_cost[i];
+            a.work_cost[cp0 + i] = s_work_cost[i];
+        }
+    }
     if (lane == 0) {
         sh.ev[wave] = evals;
         sh.part[wave] = vnd_err;

@@ -60,6 +60,7 @@ struct vns_ctx {
     int64_t max_lds_per_wg = 65536;       // device limit on LDS per workgroup (queried at create)
     int32_t permille = 0;                 // learned scorer: top permille priced exactly (0 = plain search)
     int32_t speculate = 0;                // plain search: speculative VND (neighbourhoods priced side by side)
+    int32_t state_lds = 1;                // search kernel: chains' solution state in LDS when it fits
     int32_t spec_waves = 16;
     int64_t log_cap = 0;                  // move-log capacity in records (0 = no log)
 
@@ -478,6 +479,10 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v < 1 || v > kMaxWaves) return fail(c, VNS_EINVAL, "speculative waves out of range");
             c->spec_waves = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_STATE_LDS:
+            if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "state_lds must be 0 or 1");
+            c->state_lds = (int32_t)v;
+            return VNS_OK;
         case VNS_OPT_LEARNED:
             if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
             c->permille = (int32_t)v;
@@ -515,6 +520,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_LEARNED: *v = c->permille; return VNS_OK;
         case VNS_OPT_SPECULATE: *v = c->speculate; return VNS_OK;
         case VNS_OPT_SPEC_WAVES: *v = c->spec_waves; return VNS_OK;
+        case VNS_OPT_STATE_LDS: *v = c->state_lds; return VNS_OK;
         case VNS_OPT_LOG: *v = c->log_cap; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
@@ -699,9 +705,16 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     const int64_t room = c->max_lds_per_wg - (int64_t)static_lds - learned;   // dynamic LDS left for rows
     const int64_t slices = (int64_t)waves * kTMax;                   // per-wave rows when the instance does not fit
     if (room < slices * (int64_t)sizeof(int2)) return fail(c, VNS_EINVAL, "not enough LDS for the search kernel");
-    const int64_t budget = std::min<int64_t>(c->run_lds_budget, room) / (int64_t)sizeof(int2);
+    // the chains' solution state (80 bytes per product) when it fits beside the per-wave row slices
+    int64_t max_K = 0;
+    for (int32_t i = 0; i < c->n_inst; ++i) max_K = std::max<int64_t>(max_K, c->K[(size_t)i]);
+    int64_t state_bytes = c->state_lds ? (int64_t)(2 * sizeof(Bits) + 2 * sizeof(int64_t)) * max_K : 0;
+    if (room - state_bytes < slices * (int64_t)sizeof(int2)) state_bytes = 0;
+    const int64_t budget = std::min<int64_t>(c->run_lds_budget, room - state_bytes) / (int64_t)sizeof(int2);
     ra.lds_rows = (int32_t)std::min<int64_t>(max_rows, budget);
-    const size_t lds = (size_t)run_rows_entries(ra.lds_rows, waves) * sizeof(int2) + (size_t)learned;
+    const size_t rows_bytes = (size_t)run_rows_entries(ra.lds_rows, waves) * sizeof(int2);
+    ra.state_off = state_bytes > 0 ? (int32_t)(rows_bytes + (size_t)learned) : -1;
+    const size_t lds = rows_bytes + (size_t)learned + (size_t)state_bytes;
     VNS_HIP(c, run_kernel_lds(kind, &static_lds, lds));
     if (c->use_graph) {
         const int64_t key[5] = {iters, G, waves * 4 + (int64_t)kind, (int64_t)lds, (int64_t)(intptr_t)ra.trace};

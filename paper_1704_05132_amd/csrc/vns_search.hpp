@@ -86,6 +86,30 @@ __device__ __forceinline__ int move_list(const Bits &b, int T, uint32_t nb, uint
     return nflip + nswap;
 }
 
+// One lane per item of a neighbourhood's move list (plus, at index nitems, the unchanged pattern when
+// total > nitems): exact costs folded into the lane's best key; the contrast item's key and the unchanged
+// pattern's cost are kept by the lanes that priced them.  NW setup words (2 when T <= 64).
+template <int NW>
+__device__ __forceinline__ void price_items(const Bits &b, const int2 *row, int T, const ProdParams &pp,
+                                            const uint16_t *list, int nitems, int nflip, bool fm, int total,
+                                            int citem, uint64_t &best, uint64_t &ck, int64_t &idc) {
+    const int lane = threadIdx.x & 63;
+    for (int basei = 0; basei < total; basei += 64) {
+        const int idx = basei + lane;
+        const int slot = idx < nitems ? item_slot(idx, nflip, fm, T, list) : -1;
+        Bits mb = b;
+        if (slot >= 0) {
+            const int blk = (slot >= T) + (slot >= 2 * T) + (slot >= 3 * T);
+            xor_move<NW>(mb, blk, slot - blk * T);
+        }
+        const int64_t c = decode_cost<NW>(mb, row, T, pp);
+        if (idx == nitems) idc = c;
+        const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
+        if (idx == citem) ck = key;
+        best = key < best ? key : best;
+    }
+}
+
 // Exact best move of one neighbourhood for one product, computed by one wavefront: key = cost << 16 | slot.
 // With `ident`, one more item prices the unchanged pattern and its cost is returned in *ident_cost.  With
 // contrast >= 0 (any non-negative hash), *contrast_key receives the key of item contrast mod the number of
@@ -94,7 +118,6 @@ __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *ro
                                                    uint32_t nb, uint16_t *list, bool ident, int64_t *ident_cost,
                                                    int64_t &evals, int contrast = -1, uint64_t *contrast_key = nullptr,
                                                    int *n_items = nullptr) {
-    const int lane = threadIdx.x & 63;
     int nflip;
     bool fm;
     const int nitems = move_list(b, T, nb, list, nflip, fm);
@@ -104,17 +127,10 @@ __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *ro
     uint64_t best = kInfKey, ck = kInfKey;
     int64_t idc = 0;
     const int citem = (contrast >= 0 && nitems > 0) ? contrast % nitems : -1;
-    for (int basei = 0; basei < total; basei += 64) {
-        const int idx = basei + lane;
-        const int slot = idx < nitems ? item_slot(idx, nflip, fm, T, list) : -1;
-        Bits mb = b;
-        if (slot >= 0) apply_move(mb, slot, T);
-        const int64_t c = decode_cost(mb, row, T, pp);
-        if (idx == nitems) idc = c;
-        const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
-        if (idx == citem) ck = key;
-        best = key < best ? key : best;
-    }
+    if (T <= 64)
+        price_items<2>(b, row, T, pp, list, nitems, nflip, fm, total, citem, best, ck, idc);
+    else
+        price_items<4>(b, row, T, pp, list, nitems, nflip, fm, total, citem, best, ck, idc);
     if (ident) *ident_cost = __shfl(idc, nitems & 63, 64);
     if (contrast_key) *contrast_key = citem >= 0 ? __shfl(ck, citem & 63, 64) : kInfKey;
     return wave_min_u64(best);

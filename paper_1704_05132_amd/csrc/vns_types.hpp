@@ -93,10 +93,13 @@ struct RunArgs {
     float *log_y;
     unsigned long long *log_n;
     int64_t log_cap;
+    int32_t state_off;      // byte offset in dynamic LDS of the chain's solution state (cur, work, their
+                            // costs: 80 bytes per product, 16-byte aligned); -1 = kept in device memory
 };
 
 // Dynamic LDS of the search kernel: the rows region (int2 entries, an even number so that what follows is
-// 16-byte aligned), then per wavefront the learned-search tiles.
+// 16-byte aligned), then per wavefront the learned-search tiles, then (optionally) the chain's solution
+// state.
 constexpr int kLearnedWaveBytes = 64 * 16 * 2 + 2 * kTMax * 2;
 static_assert(kLearnedWaveBytes % 16 == 0, "learned tiles stay 16-byte aligned");
 __host__ __device__ inline int run_rows_entries(int lds_rows, int waves) {

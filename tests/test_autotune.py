@@ -38,6 +38,7 @@ def test_search_options_map_every_key():
                                                                                vns.OPT_SPEC_WAVES: 9,
                                                                                vns.OPT_RUN_LDS: 65536}
     assert autotune.search_options({"group": 8}) == {}
+    assert autotune.search_options(dict(waves=2, state=1)) == {vns.OPT_RUN_WAVES: 2, vns.OPT_STATE_LDS: 1}
 
 
 def test_candidates_cover_both_search_kernels():

@@ -136,3 +136,23 @@ def test_speculative_vnd_equals_sequential(vns, nb):
         for g in range(sp.n_chains):
             a, b = sp.solution(g), sq.solution(g)
             assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
+
+
+@pytest.mark.parametrize("learned", [0, 100])
+def test_state_in_lds_does_not_change_results(vns, learned):
+    """The chains' solution state kept in LDS for the launch, or in device memory: same records, solutions
+    and costs, for the plain and the learned search."""
+    insts = [workload("batched_4096", i) for i in range(5)] + [workload("plain_100x52")]
+    say(f"  state in LDS vs device memory, learned={learned}")
+    opts = {vns.OPT_LEARNED: learned} if learned else {}
+    with vns.Context(insts, seed=3, chains=3, options={**opts, vns.OPT_STATE_LDS: 1}) as a, \
+            vns.Context(insts, seed=3, chains=3, options={**opts, vns.OPT_STATE_LDS: 0}) as b:
+        for rep in range(2):
+            a.run(9)
+            b.run(9)
+            for g in range(a.n_chains):
+                assert (a.trajectory(g) == b.trajectory(g)).all(), g
+        assert (a.costs()[0] == b.costs()[0]).all() and (a.costs()[1] == b.costs()[1]).all()
+        for g in range(a.n_chains):
+            sa, sb = a.solution(g), b.solution(g)
+            assert (sa[0] == sb[0]).all() and (sa[1] == sb[1]).all()
