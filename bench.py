@@ -176,6 +176,9 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, seed, chains, n
     plain_ms = next(ms for ms, b in plain["hist"] if (b <= B).all())
     plain_it = chunk * (1 + next(i for i, (_, b) in enumerate(plain["hist"]) if (b <= B).all()))
 
+    # the plain search with neighbourhoods not re-priced on an unchanged pattern: same moves, less work
+    pm = chunked_search(lambda: make({vns.OPT_VND_MEMO: 1}), n_inst, chains, args.steps, chunk, targets=B)
+
     # training set: moves logged by the search on disjoint instances
     tw, t0i, n_train, log_chains = LEARNED_SETUP[name]
     train = [workload(tw, t0i + j) for j in range(min(args.learned_train_instances, n_train))]
@@ -213,6 +216,7 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, seed, chains, n
     out = {
         "instances": n_inst, "chains": chains,
         "plain_ms_to_best": plain_ms, "plain_iters_to_best": plain_it, "plain_total_ms": plain["total_ms"],
+        "plain_memo_ms_to_best": pm["ms"],
         "learned_ms_to_plain_best": lrn["ms"], "learned_iters": lrn["iters"], "learned_reached": lrn["ms"] is not None,
         "learned_share_at_plain_total_ms": lrn["share_at_horizon"],
         "speedup": (plain_ms / lrn["ms"]) if lrn["ms"] else None,
@@ -310,6 +314,22 @@ def main():
         bests.append((bF, bit))
     last_it = max(it for _, it in bests)
 
+    # --- the same search with neighbourhoods not re-priced on an unchanged pattern (same moves applied) ---
+    memo = None
+    if name != "learned_batched_1024":
+        with vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=False,
+                         options={vns.OPT_VND_MEMO: 1}) as mctx:
+            mctx.bind_stream(stream)
+            table.apply(mctx, key)
+            mctx.set_option(vns.OPT_VND_MEMO, 1)
+            mctx.run(args.steps)
+            ms_ = mctx.stats()
+            mb = mctx.costs()[1].reshape(len(insts), chains).min(1)
+            memo = {"kernel_ms": ms_["last_run_ms"], "move_evals": ms_["last_run_evals"],
+                    "iterations_per_s": args.steps / (ms_["last_run_ms"] / 1e3),
+                    "speedup_vs_every_neighbourhood": run_ms / ms_["last_run_ms"],
+                    "same_best": bool((mb == [b for b, _ in bests]).all())}
+
     # --- full-neighbourhood sweep of all chains (pricing kernel alone) ---
     sweep_ms, sweep_ev, sweep_steps = [], 0, 0
     for _ in range(args.sweep_reps):
@@ -358,6 +378,7 @@ def main():
                        if len(insts) == 1 else
                        {"F_sum": int(sum(f for f, _ in bests)), "last_iteration_improved": last_it,
                         "ms": (last_it + 1) * ms_per_step}),
+        "vnd_memo": memo,
         "roofline": {"kernel": "k_run", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic("k_run", name),
                      "ops_per_period_step": OPS_PER_PERIOD_STEP},

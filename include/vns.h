@@ -87,10 +87,16 @@ enum vns_option {
                               those of the sequential pass and only consumed evaluations are counted.
                               0 (default) = one wavefront per product, neighbourhoods in turn           */
     VNS_OPT_SPEC_WAVES = 12, /* wavefronts per workgroup of the speculative search, 1..16 (default 16)  */
-    VNS_OPT_STATE_LDS = 13  /* 1 (default) = the search kernel keeps each chain's current and working
+    VNS_OPT_STATE_LDS = 13, /* 1 (default) = the search kernel keeps each chain's current and working
                               solutions and costs (80 bytes per product) in LDS for the whole launch
                               when they fit beside the per-wavefront row slices; 0 = in device memory.
                               Results do not depend on it                                             */
+    VNS_OPT_VND_MEMO = 14   /* 1 = a VND pass skips a neighbourhood already priced without improvement
+                              since the product's last applied move (its pattern has not changed, so it
+                              would find nothing again): the same moves are applied and the records are
+                              the same, with fewer move-evaluations.  0 (default) = every neighbourhood
+                              is priced in every pass, as Algorithm 1 states.  Not used by the
+                              speculative search                                                      */
 };
 
 /* One GVNS iteration of one chain. */

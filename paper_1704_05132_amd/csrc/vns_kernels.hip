@@ -510,6 +510,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 bool need_ident = e >= 0;
                 bool improved = true;
                 int passes = 0;
+                uint32_t clean = 0;   // neighbourhoods priced without improvement since the last applied move
                 while (improved) {
                     if (++passes > kMaxPasses) {
                         vnd_err = 1;
@@ -517,6 +518,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     }
                     improved = false;
                     for (int q = 0; q < a.n_nb; ++q) {
+                        if (a.memo && ((clean >> q) & 1u)) continue;   // same pattern: nothing to find
+                        bool applied = false;
                         const uint32_t nb = (a.nb_list >> (4 * q)) & 0xFu;
                         uint64_t key, ckey = kInfKey;
                         int nitems = 0;
@@ -557,8 +560,11 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                                 apply_move(b, slot, T);
                                 cost = c;
                                 improved = true;
+                                applied = true;
                             }
                         }
+                        // a move changes the pattern: every earlier pricing is stale
+                        clean = applied ? 0u : (clean | (1u << q));
                         wave_sync_lds();
                     }
                 }

@@ -61,6 +61,7 @@ struct vns_ctx {
     int32_t permille = 0;                 // learned scorer: top permille priced exactly (0 = plain search)
     int32_t speculate = 0;                // plain search: speculative VND (neighbourhoods priced side by side)
     int32_t state_lds = 1;                // search kernel: chains' solution state in LDS when it fits
+    int32_t vnd_memo = 0;                 // VND: skip neighbourhoods priced without improvement on this pattern
     int32_t spec_waves = 16;
     int64_t log_cap = 0;                  // move-log capacity in records (0 = no log)
 
@@ -483,6 +484,10 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "state_lds must be 0 or 1");
             c->state_lds = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_VND_MEMO:
+            if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "vnd_memo must be 0 or 1");
+            c->vnd_memo = (int32_t)v;
+            return VNS_OK;
         case VNS_OPT_LEARNED:
             if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
             c->permille = (int32_t)v;
@@ -521,6 +526,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_SPECULATE: *v = c->speculate; return VNS_OK;
         case VNS_OPT_SPEC_WAVES: *v = c->spec_waves; return VNS_OK;
         case VNS_OPT_STATE_LDS: *v = c->state_lds; return VNS_OK;
+        case VNS_OPT_VND_MEMO: *v = c->vnd_memo; return VNS_OK;
         case VNS_OPT_LOG: *v = c->log_cap; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
@@ -691,6 +697,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     ra.log_y = c->d_log_y;
     ra.log_n = c->d_log_n;
     ra.log_cap = c->log_cap;
+    ra.memo = c->vnd_memo;
     int64_t max_rows = 0;
     for (int32_t i = 0; i < c->n_inst; ++i) max_rows = std::max<int64_t>(max_rows, (int64_t)c->K[(size_t)i] * c->T[(size_t)i]);
     // instance rows in LDS for every chain whose instance fits the budget; the others stage one row per wave

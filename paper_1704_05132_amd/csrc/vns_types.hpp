@@ -95,6 +95,7 @@ struct RunArgs {
     int64_t log_cap;
     int32_t state_off;      // byte offset in dynamic LDS of the chain's solution state (cur, work, their
                             // costs: 80 bytes per product, 16-byte aligned); -1 = kept in device memory
+    int32_t memo;           // 1 = skip a neighbourhood priced without improvement on the current pattern
 };
 
 // Dynamic LDS of the search kernel: the rows region (int2 entries, an even number so that what follows is

@@ -156,3 +156,26 @@ def test_state_in_lds_does_not_change_results(vns, learned):
         for g in range(a.n_chains):
             sa, sb = a.solution(g), b.solution(g)
             assert (sa[0] == sb[0]).all() and (sa[1] == sb[1]).all()
+
+
+@pytest.mark.parametrize("learned", [0, 100])
+def test_vnd_memo_keeps_the_trajectory(vns, learned):
+    """Skipping neighbourhoods already priced without improvement on the same pattern applies the same
+    moves: identical records and solutions (and the oracle's, for the plain search), fewer evaluations."""
+    insts = [workload("batched_4096", i) for i in range(4)] + [workload("plain_100x52")]
+    say(f"  VND memo on vs off, learned={learned}")
+    opts = {vns.OPT_LEARNED: learned} if learned else {}
+    with vns.Context(insts, seed=3, chains=3, options={**opts, vns.OPT_VND_MEMO: 1}) as a, \
+            vns.Context(insts, seed=3, chains=3, options={**opts, vns.OPT_VND_MEMO: 0}) as b:
+        a.run(25)
+        b.run(25)
+        ea, eb = a.stats()["last_run_evals"], b.stats()["last_run_evals"]
+        say(f"    evaluations {ea} with the skip, {eb} without")
+        assert ea < eb
+        for g in range(a.n_chains):
+            assert (a.trajectory(g) == b.trajectory(g)).all(), g
+            sa, sb = a.solution(g), b.solution(g)
+            assert (sa[0] == sb[0]).all() and (sa[1] == sb[1]).all()
+        if not learned:
+            for g in (0, 7, 14):
+                check_chain(a, g, insts[g // 3], 3, 25)
