@@ -332,27 +332,54 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
 
         // ---- Shake(x, k): wavefront 0 draws k flips and keeps the feasible ones in the dirty list ----
         if (wave == 0) {
-            const uint32_t my = lane < kshake ? shake_draw(a.seed, (uint64_t)g, (uint64_t)it, (uint64_t)lane, nflip_all) : 0u;
-            int nd = 0;
+            const bool draw = lane < kshake;
+            const uint32_t my = draw ? shake_draw(a.seed, (uint64_t)g, (uint64_t)it, (uint64_t)lane, nflip_all) : 0u;
+            const int pd = (int)(my / (uint32_t)(2 * T));          // lane j: product and flip slot of draw j
+            const int ld = (int)(my - (uint32_t)pd * (uint32_t)(2 * T));
+            bool dup = false;                                        // an earlier draw hit the same product
             for (int j = 0; j < kshake; ++j) {
-                const uint32_t f = (uint32_t)__shfl((int)my, j, 64);
-                const int p = (int)(f / (uint32_t)(2 * T));
-                const int l = (int)(f - (uint32_t)p * (uint32_t)(2 * T));
-                int e = -1;
-                for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
-                Bits b = e >= 0 ? sh.db[e] : s_work[p];
-                apply_move(b, l, T);
-                // a manufacturing setup in period 0 makes any pattern feasible; otherwise check the prefix
-                bool ok = (b.m[0] & 1u) != 0u;
-                if (!ok) ok = rows_in_lds ? feasible(b, s_rows + p * T, T) : feasible(b, inst_rows + p * T, T);
-                if (ok) {
-                    if (e < 0) {
-                        e = nd++;
-                        if (lane == 0) sh.dp[e] = p;
-                    }
-                    if (lane == 0) sh.db[e] = b;
+                const int pj = __shfl(pd, j, 64);
+                dup |= draw && j < lane && pj == pd;
+            }
+            int nd = 0;
+            if (!__any(dup)) {
+                // distinct products: the draws are independent, so each lane resolves its own and the
+                // feasible ones are compacted in draw order
+                bool ok = false;
+                Bits b = s_work[draw ? pd : 0];
+                if (draw) {
+                    apply_move(b, ld, T);
+                    ok = (b.m[0] & 1u) != 0u;   // a manufacturing setup in period 0 makes any pattern feasible
+                    if (!ok) ok = rows_in_lds ? feasible(b, s_rows + pd * T, T) : feasible(b, inst_rows + pd * T, T);
                 }
-                wave_sync_lds();
+                const unsigned long long okm = __ballot(ok);
+                if (ok) {
+                    const int e = __popcll(okm & ((1ull << lane) - 1ull));
+                    sh.dp[e] = pd;
+                    sh.db[e] = b;
+                }
+                nd = __popcll(okm);
+            } else {
+                for (int j = 0; j < kshake; ++j) {
+                    const uint32_t f = (uint32_t)__shfl((int)my, j, 64);
+                    const int p = (int)(f / (uint32_t)(2 * T));
+                    const int l = (int)(f - (uint32_t)p * (uint32_t)(2 * T));
+                    int e = -1;
+                    for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
+                    Bits b = e >= 0 ? sh.db[e] : s_work[p];
+                    apply_move(b, l, T);
+                    // a manufacturing setup in period 0 makes any pattern feasible; otherwise check the prefix
+                    bool ok = (b.m[0] & 1u) != 0u;
+                    if (!ok) ok = rows_in_lds ? feasible(b, s_rows + p * T, T) : feasible(b, inst_rows + p * T, T);
+                    if (ok) {
+                        if (e < 0) {
+                            e = nd++;
+                            if (lane == 0) sh.dp[e] = p;
+                        }
+                        if (lane == 0) sh.db[e] = b;
+                    }
+                    wave_sync_lds();
+                }
             }
             if (lane == 0) sh.nd = nd;
         }
