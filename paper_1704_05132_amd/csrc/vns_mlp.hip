@@ -6,6 +6,8 @@
 // mixed-precision rule; the backward pass runs in float32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "vns_launch.hpp"
 #include "vns_mlp.hpp"
 
@@ -25,17 +27,20 @@ __device__ __forceinline__ void stage_features(const float *__restrict__ X, int6
 
 }  // namespace
 
-// Scores of n feature rows; one wavefront per 64 rows.
+// Scores of n feature rows: each wavefront loads the weight fragments once and scores tiles of 64 rows
+// blockIdx.x, blockIdx.x + gridDim.x, ...
 __global__ __launch_bounds__(64) void k_mlp_score(const float *__restrict__ P, const float *__restrict__ X, int64_t n,
                                                   float *__restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) __bf16 s_mlp[];
     __bf16 *sx = s_mlp;
     Frags fr;
     load_frags(P, fr);
-    const int64_t row = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-    stage_features(X, row, n, sx);
-    const float s = forward64(sx, fr);
-    if (row < n) out[row] = s;
+    for (int64_t tile = blockIdx.x; tile * 64 < n; tile += gridDim.x) {
+        const int64_t row = tile * 64 + (threadIdx.x & 63);
+        stage_features(X, row, n, sx);
+        const float s = forward64(sx, fr);   // ends with a wavefront barrier: sx may be rewritten
+        if (row < n) out[row] = s;
+    }
 }
 
 // The same forward pass for the rows idx[0..n) of a training set (all rows when idx is null): stores the rows
@@ -172,7 +177,9 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, const float
 
 hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp::k_mlp_score, dim3((unsigned)((n + 63) / 64)), dim3(64), mlp::kWaveLdsBytes, s, P, X, n, out);
+    const int64_t tiles = (n + 63) / 64;
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 256 * 16);   // 16 wavefronts per CU, each a few tiles
+    hipLaunchKernelGGL(mlp::k_mlp_score, dim3(grid), dim3(64), mlp::kWaveLdsBytes, s, P, X, n, out);
     return hipGetLastError();
 }
 

@@ -26,7 +26,18 @@ constexpr int oW1 = 0, oB1 = 1024, oW2 = 1088, oB2 = 5184, oW3 = 5248, oB3 = 531
 constexpr int kWaveLdsBytes = 64 * kF * 2;   // feature tile of 64 moves, bfloat16
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef short s2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// ReLU of two float32 values rounded to bfloat16 (nearest even), packed: one v_cvt_pk_bf16_f32 and one
+// v_pk_max_i16 (a negative bfloat16, -0 included, is a negative int16; rounding keeps the sign, so the
+// order of rounding and ReLU does not matter).
+__device__ __forceinline__ bf2 relu_pack(float a, float b) {
+    const bf2 p = {(__bf16)a, (__bf16)b};
+    const s2 zero = {0, 0};
+    return __builtin_bit_cast(bf2, __builtin_elementwise_max(__builtin_bit_cast(s2, p), zero));
+}
 
 // The network is evaluated transposed, H^T = W^T X^T, on v_mfma_f32_16x16x32_bf16 (lane l = 16 g + c holds
 // A[c][8g..8g+7], B[8g..8g+7][c] and D[4g..4g+3][c]): with hidden units as the M dimension and moves as N,
@@ -38,7 +49,7 @@ struct Frags {
     bf8 w2t[4][2];    // [output tile][k-slice]: W2^T rows 16mo + c, inputs pi(kt, 8g..8g+7)
     f4 b1[4];         // [hidden tile]: b1[16mt + 4g + e]
     f4 b2[4];         // [output tile]: b2[16mo + 4g + e]
-    f4 w3[4];         // [output tile]: bfloat16-rounded W3[16mo + 4g + e]
+    bf2 w3[4][2];     // [output tile][pair]: W3[16mo + 4g + 2pair + (0, 1)] in bfloat16
     float b3;
 };
 
@@ -55,7 +66,7 @@ __device__ __forceinline__ void load_frags(const float *__restrict__ P, Frags &f
         for (int e = 0; e < 4; ++e) {
             fr.b1[mt][e] = P[oB1 + 16 * mt + 4 * g + e];
             fr.b2[mt][e] = P[oB2 + 16 * mt + 4 * g + e];
-            fr.w3[mt][e] = (float)(__bf16)P[oW3 + 16 * mt + 4 * g + e];
+            fr.w3[mt][e >> 1][e & 1] = (__bf16)P[oW3 + 16 * mt + 4 * g + e];
         }
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt)
@@ -91,9 +102,13 @@ __device__ __forceinline__ float forward64(const __bf16 *sx, const Frags &fr, fl
 #pragma unroll
         for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                h[kt][e] = (__bf16)fmaxf(d1[2 * kt][e], 0.f);
-                h[kt][4 + e] = (__bf16)fmaxf(d1[2 * kt + 1][e], 0.f);
+            for (int e = 0; e < 4; e += 2) {
+                const bf2 lo = relu_pack(d1[2 * kt][e], d1[2 * kt][e + 1]);
+                const bf2 hi = relu_pack(d1[2 * kt + 1][e], d1[2 * kt + 1][e + 1]);
+                h[kt][e] = lo[0];
+                h[kt][e + 1] = lo[1];
+                h[kt][4 + e] = hi[0];
+                h[kt][4 + e + 1] = hi[1];
             }
         float acc3 = 0.f;
 #pragma unroll
@@ -101,8 +116,9 @@ __device__ __forceinline__ float forward64(const __bf16 *sx, const Frags &fr, fl
             f4 d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][0], h[0], fr.b2[mo], 0, 0, 0);
             d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][1], h[1], d2, 0, 0, 0);
             if (z2) *reinterpret_cast<f4 *>(z2 + row * kH + 16 * mo + 4 * g) = d2;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) acc3 += (float)(__bf16)fmaxf(d2[e], 0.f) * fr.w3[mo][e];
+            // layer 3: bfloat16 activations against bfloat16 W3, two products per v_dot2 (float32 sum)
+            acc3 = __builtin_amdgcn_fdot2_f32_bf16(relu_pack(d2[0], d2[1]), fr.w3[mo][0], acc3, false);
+            acc3 = __builtin_amdgcn_fdot2_f32_bf16(relu_pack(d2[2], d2[3]), fr.w3[mo][1], acc3, false);
         }
         // layer 3: sum the four lane groups' partial dot products of each column; lane 16 nt + c keeps it
         acc3 += __shfl_xor(acc3, 16, 64);
