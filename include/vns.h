@@ -91,12 +91,23 @@ enum vns_option {
                               solutions and costs (80 bytes per product) in LDS for the whole launch
                               when they fit beside the per-wavefront row slices; 0 = in device memory.
                               Results do not depend on it                                             */
-    VNS_OPT_VND_MEMO = 14   /* 1 = a VND pass skips a neighbourhood already priced without improvement
+    VNS_OPT_VND_MEMO = 14,  /* 1 = a VND pass skips a neighbourhood already priced without improvement
                               since the product's last applied move (its pattern has not changed, so it
                               would find nothing again): the same moves are applied and the records are
                               the same, with fewer move-evaluations.  0 (default) = every neighbourhood
                               is priced in every pass, as Algorithm 1 states.  Not used by the
                               speculative search                                                      */
+    VNS_OPT_SPEC_ITERS = 15 /* m in 1..8 (default 1 = off): a rejected iteration leaves x unchanged and
+                              the shake of an iteration depends only on (seed, chain, iteration, k), so
+                              m workgroups per chain compute the next m iterations side by side as if
+                              the earlier ones were rejected; they are resolved in order and what
+                              follows the first accepted one is discarded.  Records, solutions and
+                              counted move-evaluations equal those of the one-workgroup search.  Used
+                              for the plain search when every workgroup of the launch can be resident
+                              at once, the move log is off and the run is not captured in a graph;
+                              otherwise the run falls back to one workgroup per chain
+                              (vns_stats.last_run_spec_iters = 1).  A chain's workgroups wait for each
+                              other with bounded spins: if one runs out, vns_run returns VNS_EDEVICE */
 };
 
 /* One GVNS iteration of one chain. */
@@ -123,6 +134,8 @@ typedef struct vns_stats {
     int64_t last_run_fallbacks;      /*   and how many of them priced the whole neighbourhood            */
     double last_mlp_ms;              /* device time of the kernels of the last vns_mlp_score / _grad / _train */
     int64_t last_mlp_rows;           /*   and the feature rows they processed (rows x epochs for training)   */
+    int64_t last_run_spec_iters;     /* iterations computed side by side per chain by the last vns_run (1 or
+                                        VNS_OPT_SPEC_ITERS)                                               */
 } vns_stats;
 
 /*

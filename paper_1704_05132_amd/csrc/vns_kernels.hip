@@ -247,8 +247,25 @@ struct RunShared {
     int64_t shk[kMaxWaves];
     int64_t ev[kMaxWaves];
     int64_t fb[kMaxWaves];
+    int32_t verr[kMaxWaves];
     int32_t nd;
+    // speculative iterations: the chain's state at a round start (read by one thread, so that the whole
+    // workgroup decides alike), the round's accepted slot (-1: none) and abort flag
+    ChainState coop_cs;
+    int64_t coop_done_it;
+    int32_t coop_stop;
+    int32_t coop_acc;
+    int32_t coop_abort;
 };
+
+// Bounded wait until *p >= v (acquire, agent scope): false if the wait ran out.
+__device__ __forceinline__ bool coop_wait_ge(int32_t *p, int32_t v) {
+    for (uint32_t n = 0; n < kCoopSpinLimit; ++n) {
+        if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
 
 // Speculative VND (plain search): each product in work is handled by a group of n_nb wavefronts, one per
 // neighbourhood of the list.  In every round the neighbourhoods not yet settled in the current pass are
@@ -272,10 +289,22 @@ struct SpecShared {
     int32_t next;         // next product index to hand out
 };
 
-template <bool SPEC, bool LEARNED>
+template <bool SPEC, bool LEARNED, bool COOP = false>
 __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecShared &sp, int2 *s_rows) {
     static_assert(!(SPEC && LEARNED), "the speculative VND prices whole neighbourhoods");
-    const int g = blockIdx.x;
+    static_assert(!(COOP && (SPEC || LEARNED)), "speculative iterations run the plain sequential VND");
+    int g = blockIdx.x, slot = 0;   // chain, and (speculative iterations) the iteration of a round it computes
+    if constexpr (COOP) {
+        const int m = a.coop_m;
+        if (a.coop_xcd) {   // consecutive workgroups go to consecutive XCDs: keep a chain's m on one
+            const int xcd = blockIdx.x & 7, w = blockIdx.x >> 3;
+            g = (w / m) * 8 + xcd;
+            slot = w % m;
+        } else {
+            g = blockIdx.x / m;
+            slot = blockIdx.x % m;
+        }
+    }
     const ChainInfo ci = a.chains[g];
     const int K = ci.K, T = ci.T;
     const int64_t cp0 = ci.cp0;
@@ -293,7 +322,13 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     // here and back at the end), else in device memory
     Bits *s_cur, *s_work;
     int64_t *s_cur_cost, *s_work_cost;
-    if (a.state_off >= 0) {
+    if (COOP) {   // x in device memory, shared by the chain's workgroups; each iteration's VND into its slot
+        const int64_t sb = ((int64_t)g * a.coop_m + slot) * a.coop_kmax;
+        s_cur = a.cur + cp0;
+        s_cur_cost = a.cur_cost + cp0;
+        s_work = a.coop_res + sb;
+        s_work_cost = a.coop_res_cost + sb;
+    } else if (a.state_off >= 0) {
         char *base = reinterpret_cast<char *>(s_rows) + a.state_off;
         s_cur = reinterpret_cast<Bits *>(base);
         s_work = s_cur + K;
@@ -326,9 +361,35 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     if constexpr (LEARNED) mlp::load_frags(a.mlp, fr);
     const uint64_t nflip_all = 2ull * (uint64_t)K * (uint64_t)T;
 
-    for (int i = 0; i < a.iters; ++i) {
-        const int64_t it = it_first + i;
-        const int kshake = cs.k;
+    int32_t coop_round = 0;   // rounds this workgroup has seen completed
+    int64_t done_it = 0;      // speculative iterations: iterations resolved before this round
+    for (int i = 0; COOP || i < a.iters; ++i) {
+        int64_t it = it_first + i;
+        int kshake = cs.k;
+        bool go = true;           // this workgroup has an iteration to compute in this round
+        int active = 1;           // iterations computed in this round
+        const int64_t ev_round = evals;
+        if constexpr (COOP) {
+            // the chain's state as the leader left it (acquired at the end of the previous round)
+            if (threadIdx.x == 0) {
+                sh.coop_cs = a.cstate[g];
+                sh.coop_done_it = a.coop_ctl[g].iters_done;
+                sh.coop_stop = sh.coop_done_it >= a.iters ||
+                               __hip_atomic_load(&a.coop_ctl[g].abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __syncthreads();
+            cs = sh.coop_cs;
+            done_it = sh.coop_done_it;
+            if (sh.coop_stop) break;
+            active = cs.lopt ? (int)min<int64_t>(a.coop_m, a.iters - done_it) : 1;
+            go = slot < active;
+            it = it_first + done_it + slot;
+            kshake = cs.k;   // the shake size after this workgroup's slot rejections
+            for (int q = 0; q < slot; ++q) kshake = kshake >= a.kmax ? 1 : kshake + 1;
+        }
+        int nd = 0;
+        int64_t part = 0, shk = 0;
+        if (go) {
 
         // ---- Shake(x, k): wavefront 0 draws k flips and keeps the feasible ones in the dirty list ----
         if (wave == 0) {
@@ -346,7 +407,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 // distinct products: the draws are independent, so each lane resolves its own and the
                 // feasible ones are compacted in draw order
                 bool ok = false;
-                Bits b = s_work[draw ? pd : 0];
+                Bits b = s_cur[draw ? pd : 0];
                 if (draw) {
                     apply_move(b, ld, T);
                     ok = (b.m[0] & 1u) != 0u;   // a manufacturing setup in period 0 makes any pattern feasible
@@ -366,7 +427,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     const int l = (int)(f - (uint32_t)p * (uint32_t)(2 * T));
                     int e = -1;
                     for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
-                    Bits b = e >= 0 ? sh.db[e] : s_work[p];
+                    Bits b = e >= 0 ? sh.db[e] : s_cur[p];
                     apply_move(b, l, T);
                     // a manufacturing setup in period 0 makes any pattern feasible; otherwise check the prefix
                     bool ok = (b.m[0] & 1u) != 0u;
@@ -384,10 +445,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             if (lane == 0) sh.nd = nd;
         }
         __syncthreads();
-        const int nd = sh.nd;
+        nd = sh.nd;
 
         // ---- speculative VND: groups of n_nb wavefronts, one neighbourhood each ----
-        int64_t part = 0, shk = 0;
         if constexpr (SPEC) {
             const int nprod = cs.lopt ? nd : K;
             const int gsz = a.n_nb, G = W / gsz;
@@ -409,9 +469,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
                 }
                 gr.p = p;
-                gr.b = e >= 0 ? sh.db[e] : s_work[p];
+                gr.b = e >= 0 ? sh.db[e] : s_cur[p];
                 gr.c_cur = s_cur_cost[p];
-                gr.cost = e >= 0 ? kInf : s_work_cost[p];
+                gr.cost = e >= 0 ? kInf : gr.c_cur;
                 gr.need_ident = e >= 0;
                 gr.q = 0;
                 gr.improved = 0;
@@ -531,9 +591,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     wave_sync_lds();
                     row = slice;
                 }
-                Bits b = e >= 0 ? sh.db[e] : s_work[p];
+                Bits b = e >= 0 ? sh.db[e] : s_cur[p];
                 const int64_t c_cur = s_cur_cost[p];
-                int64_t cost = e >= 0 ? kInf : s_work_cost[p];   // a shaken product is priced with its first move list
+                int64_t cost = e >= 0 ? kInf : c_cur;   // a shaken product is priced with its first move list
                 bool need_ident = e >= 0;
                 bool improved = true;
                 int passes = 0;
@@ -602,11 +662,118 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 part += cost - c_cur;
             }
         }
+        }   // go
         if (lane == 0) {
             sh.part[wave] = part;
             sh.shk[wave] = shk;
+            if constexpr (COOP) {
+                sh.ev[wave] = evals - ev_round;
+                sh.verr[wave] = vnd_err;
+            }
         }
         __syncthreads();
+
+        if constexpr (COOP) {
+            CoopCtl *ctl = a.coop_ctl + g;
+            CoopSlot *mine = a.coop_slot + (int64_t)g * a.coop_m + slot;
+            if (go && threadIdx.x == 0) {   // this iteration's summary
+                int64_t delta = 0, dshake = 0, ev = 0;
+                int err = 0;
+                for (int w = 0; w < W; ++w) {
+                    delta += sh.part[w];
+                    dshake += sh.shk[w];
+                    ev += sh.ev[w];
+                    err |= sh.verr[w];
+                }
+                mine->F_local = cs.F + delta;
+                mine->F_shaken = cs.F + dshake;
+                mine->evals = ev;
+                mine->err = err;
+                mine->n_touch = cs.lopt ? nd : -1;   // -1: every product
+                for (int q = 0; q < nd; ++q) mine->dp[q] = sh.dp[q];
+            }
+            __threadfence();   // the VND results (written by the wavefronts) and the summary, before the count
+            __syncthreads();
+            // every workgroup of the chain checks in, idle or not, so that none can still be reading this
+            // round's starting state when the leader replaces it
+            if (threadIdx.x == 0) __hip_atomic_fetch_add(&ctl->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (slot == 0) {
+                // the leader resolves the round in iteration order: the first accepted iteration ends it
+                if (threadIdx.x == 0) {
+                    const bool ok = coop_wait_ge(&ctl->done, a.coop_m);
+                    int acc = -1, consumed = active, k = cs.k, err = ok ? 0 : 2;
+                    int64_t F = cs.F, Fb = cs.F_best, ev = 0;
+                    for (int j = 0; j < active && ok; ++j) {
+                        const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + j;
+                        const int64_t Fl = sj->F_local;
+                        ev += sj->evals;
+                        err |= sj->err;
+                        const int accepted = Fl < F;
+                        if (a.trace) {
+                            Record r;
+                            r.iter = (int32_t)(it_first + done_it + j);
+                            r.k = k;
+                            r.accepted = accepted;
+                            r.pad = 0;
+                            r.F_shaken = sj->F_shaken;
+                            r.F_local = Fl;
+                            r.F_best = (accepted && Fl < Fb) ? Fl : Fb;
+                            a.trace[(int64_t)g * a.iters + done_it + j] = r;
+                        }
+                        if (accepted) {
+                            acc = j;
+                            consumed = j + 1;
+                            F = Fl;
+                            Fb = Fl < Fb ? Fl : Fb;
+                            k = 1;
+                            break;
+                        }
+                        k = k >= a.kmax ? 1 : k + 1;
+                    }
+                    sh.coop_acc = ok ? acc : -1;
+                    sh.coop_abort = !ok;
+                    if (ok) {
+                        cs.F = F;
+                        cs.F_best = Fb;
+                        cs.k = k;
+                        if (acc >= 0) cs.lopt = 1;
+                        ctl->iters_done = done_it + consumed;
+                        ctl->evals += ev;
+                    }
+                    if (err) atomicOr(&ctl->err, err);
+                }
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the slots' results, for every thread
+                const int acc = sh.coop_acc;
+                if (acc >= 0) {   // x takes the accepted iteration's VND results
+                    const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + acc;
+                    const int64_t sb = ((int64_t)g * a.coop_m + acc) * a.coop_kmax;
+                    const int n = sj->n_touch < 0 ? K : sj->n_touch;
+                    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+                        const int p = sj->n_touch < 0 ? q : sj->dp[q];
+                        a.cur[cp0 + p] = a.coop_res[sb + p];
+                        a.cur_cost[cp0 + p] = a.coop_res_cost[sb + p];
+                    }
+                }
+                __threadfence();
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    a.cstate[g] = cs;
+                    if (sh.coop_abort) ctl->abort = 1;
+                    ctl->done = 0;
+                    __hip_atomic_fetch_add(&ctl->round, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            } else if (threadIdx.x == 0) {
+                if (!coop_wait_ge(&ctl->round, coop_round + 1)) {
+                    __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    atomicOr(&ctl->err, 2);
+                }
+            }
+            ++coop_round;
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the leader's writes, for every thread
+            continue;
+        }
 
         // ---- acceptance ----
         int64_t delta = 0, dshake = 0;
@@ -649,6 +816,23 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         __syncthreads();
     }
 
+    if constexpr (COOP) {
+        if (slot == 0) {   // the leader: this launch's counters, and work == cur for the other search kernels
+            __syncthreads();
+            for (int q = threadIdx.x; q < K; q += blockDim.x) {
+                a.work[cp0 + q] = a.cur[cp0 + q];
+                a.work_cost[cp0 + q] = a.cur_cost[cp0 + q];
+            }
+            if (threadIdx.x == 0) {
+                cs.evals = a.coop_ctl[g].evals;
+                cs.err |= a.coop_ctl[g].err;
+                cs.nb_evals = 0;
+                cs.fallbacks = 0;
+                a.cstate[g] = cs;
+            }
+        }
+        return;
+    }
     if (a.state_off >= 0) {   // every iteration ended with a barrier
         for (int i = threadIdx.x; i < K; i += blockDim.x) {
             a.cur[cp0 + i] = s_cur[i];
@@ -695,6 +879,15 @@ __global__ __launch_bounds__(1024) void k_run_spec(RunArgs a) {
     __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
     run_chain<true, false>(a, sh, sp, s_rows);
+}
+
+// speculative iterations: m workgroups per chain compute the next m iterations side by side (cooperative
+// launch: every workgroup of a chain is resident while it waits for the others)
+__global__ __launch_bounds__(512) void k_run_coop(RunArgs a) {
+    __shared__ RunShared sh;
+    __shared__ SpecShared sp;
+    extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
+    run_chain<false, false, true>(a, sh, sp, s_rows);
 }
 
 // learned VND: the scorer's weight fragments stay in registers for the whole launch
@@ -785,6 +978,36 @@ hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_byt
     if (e != hipSuccess) return e;
     *static_bytes = fa.sharedSizeBytes;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes);
+}
+
+hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits) {
+    *fits = false;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run_coop),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    int per_cu = 0, dev = 0, cus = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_run_coop), 64 * waves,
+                                                     lds_bytes);
+    if (e != hipSuccess) return e;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    *fits = (int64_t)per_cu * cus >= blocks;
+    return hipSuccess;
+}
+
+hipError_t launch_run_coop(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
+                           hipStream_t s) {
+    if (n_chains <= 0 || a.iters <= 0) return hipSuccess;
+    RunArgs args = a;
+    void *params[] = {&args};
+    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_run_coop),
+                                              dim3((unsigned)(n_chains * a.coop_m)), dim3(64 * waves), params,
+                                              (unsigned)lds_bytes, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, it_counter, a.iters);
+    return hipGetLastError();
 }
 
 hipError_t launch_run(const RunArgs &a, RunKind kind, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,

@@ -62,6 +62,12 @@ struct vns_ctx {
     int32_t speculate = 0;                // plain search: speculative VND (neighbourhoods priced side by side)
     int32_t state_lds = 1;                // search kernel: chains' solution state in LDS when it fits
     int32_t vnd_memo = 0;                 // VND: skip neighbourhoods priced without improvement on this pattern
+    int32_t spec_iters = 1;               // iterations speculated side by side per chain (1 = off)
+    CoopCtl *d_coop_ctl = nullptr;        // speculative iterations: per-chain control, per-slot summaries and
+    CoopSlot *d_coop_slot = nullptr;      //   VND results
+    Bits *d_coop_res = nullptr;
+    int64_t *d_coop_res_cost = nullptr;
+    size_t coop_cap_ctl = 0, coop_cap_slot = 0, coop_cap_res = 0;
     int32_t spec_waves = 16;
     int64_t log_cap = 0;                  // move-log capacity in records (0 = no log)
 
@@ -209,6 +215,10 @@ static void free_all(vns_ctx *c) {
     dfree(c->d_rows);
     dfree(c->d_prod);
     dfree(c->d_evals);
+    dfree(c->d_coop_ctl);
+    dfree(c->d_coop_slot);
+    dfree(c->d_coop_res);
+    dfree(c->d_coop_res_cost);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -488,6 +498,10 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "vnd_memo must be 0 or 1");
             c->vnd_memo = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_SPEC_ITERS:
+            if (v < 1 || v > 8) return fail(c, VNS_EINVAL, "spec_iters must be in 1..8");
+            c->spec_iters = (int32_t)v;
+            return VNS_OK;
         case VNS_OPT_LEARNED:
             if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
             c->permille = (int32_t)v;
@@ -527,6 +541,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_SPEC_WAVES: *v = c->spec_waves; return VNS_OK;
         case VNS_OPT_STATE_LDS: *v = c->state_lds; return VNS_OK;
         case VNS_OPT_VND_MEMO: *v = c->vnd_memo; return VNS_OK;
+        case VNS_OPT_SPEC_ITERS: *v = c->spec_iters; return VNS_OK;
         case VNS_OPT_LOG: *v = c->log_cap; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
@@ -723,7 +738,49 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     ra.state_off = state_bytes > 0 ? (int32_t)(rows_bytes + (size_t)learned) : -1;
     const size_t lds = rows_bytes + (size_t)learned + (size_t)state_bytes;
     VNS_HIP(c, run_kernel_lds(kind, &static_lds, lds));
-    if (c->use_graph) {
+    // speculative iterations: plain search without the move log (a discarded iteration's moves must not be
+    // logged), not captured, and every workgroup of the launch resident at once
+    const int m = c->spec_iters;
+    bool coop = false;
+    const size_t lds_coop = rows_bytes;   // x stays in device memory: no state region
+    if (m > 1 && kind == RunKind::kPlain && !c->use_graph && ra.log_x == nullptr)
+        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop));
+    c->stats.last_run_spec_iters = coop ? m : 1;
+    if (coop) {
+        const size_t n_res = (size_t)G * (size_t)m * (size_t)max_K;
+        if ((size_t)G > c->coop_cap_ctl) {
+            dfree(c->d_coop_ctl);
+            c->coop_cap_ctl = 0;
+            VNS_HIP(c, dmalloc(&c->d_coop_ctl, (size_t)G));
+            c->coop_cap_ctl = (size_t)G;
+        }
+        if ((size_t)(G * m) > c->coop_cap_slot) {
+            dfree(c->d_coop_slot);
+            c->coop_cap_slot = 0;
+            VNS_HIP(c, dmalloc(&c->d_coop_slot, (size_t)(G * m)));
+            c->coop_cap_slot = (size_t)(G * m);
+        }
+        if (n_res > c->coop_cap_res) {
+            dfree(c->d_coop_res);
+            dfree(c->d_coop_res_cost);
+            c->coop_cap_res = 0;
+            VNS_HIP(c, dmalloc(&c->d_coop_res, n_res));
+            VNS_HIP(c, dmalloc(&c->d_coop_res_cost, n_res));
+            c->coop_cap_res = n_res;
+        }
+        VNS_HIP(c, hipMemsetAsync(c->d_coop_ctl, 0, sizeof(CoopCtl) * (size_t)G, c->stream));
+        ra.state_off = -1;
+        ra.coop_m = m;
+        ra.coop_xcd = G % 8 == 0;
+        ra.coop_kmax = (int32_t)max_K;
+        ra.coop_ctl = c->d_coop_ctl;
+        ra.coop_slot = c->d_coop_slot;
+        ra.coop_res = c->d_coop_res;
+        ra.coop_res_cost = c->d_coop_res_cost;
+        VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
+        VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream));
+        VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
+    } else if (c->use_graph) {
         const int64_t key[5] = {iters, G, waves * 4 + (int64_t)kind, (int64_t)lds, (int64_t)(intptr_t)ra.trace};
         bool same = true;
         for (int i = 0; i < 5; ++i) same = same && key[i] == c->graph_key[i];
@@ -766,6 +823,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     }
     c->stats.last_run_learned_evals = nbe;
     c->stats.last_run_fallbacks = fbs;
+    if (err & 2) return fail(c, VNS_EDEVICE, "speculative iterations: a workgroup's wait for its chain ran out");
     if (err) return fail(c, VNS_EDEVICE, "a VND exceeded its pass guard (inconsistent costs)");
     c->iteration += iters;
     c->stats.iterations = c->iteration;

@@ -96,7 +96,36 @@ struct RunArgs {
     int32_t state_off;      // byte offset in dynamic LDS of the chain's solution state (cur, work, their
                             // costs: 80 bytes per product, 16-byte aligned); -1 = kept in device memory
     int32_t memo;           // 1 = skip a neighbourhood priced without improvement on the current pattern
+    // speculative iterations (cooperative launch): m workgroups per chain, see CoopCtl
+    int32_t coop_m;             // iterations speculated per round
+    int32_t coop_xcd;           // 1 = a chain's m workgroups are placed on one XCD (chains % 8 == 0)
+    int32_t coop_kmax;          // products per chain slot in coop_res (the largest K)
+    struct CoopCtl *coop_ctl;   // [chains]
+    struct CoopSlot *coop_slot; // [chains][m]
+    Bits *coop_res;             // [chains][m][coop_kmax] VND results of a slot
+    int64_t *coop_res_cost;     // [chains][m][coop_kmax]
 };
+
+// Speculative iterations.  A rejected GVNS iteration leaves x unchanged, and its shake depends only on
+// (seed, chain, iteration, k), so the m iterations that follow a state are computed side by side, each by
+// its own workgroup, as if the earlier ones were rejected; they are then resolved in order and everything
+// after the first accepted one is discarded.  Records, moves and counted evaluations are those of the
+// sequential search.  Per chain, in device memory (set up by the host before each launch):
+struct CoopCtl {
+    int32_t round;        // rounds completed (the leader increments it to start the next round)
+    int32_t done;         // workgroups that finished the current round's iteration
+    int64_t iters_done;   // iterations of this launch resolved so far
+    int64_t evals;        // move-evaluations of the resolved iterations
+    int32_t abort;        // a bounded wait ran out: every workgroup of the chain leaves
+    int32_t err;
+};
+struct CoopSlot {
+    int64_t F_local, F_shaken, evals;
+    int32_t n_touch;      // products in dp (K = every product: the VND of a state not yet a local optimum)
+    int32_t err;
+    int32_t dp[kShakeMax];
+};
+constexpr uint32_t kCoopSpinLimit = 1u << 23;   // s_sleep polls before a wait gives up (about a second)
 
 // Dynamic LDS of the search kernel: the rows region (int2 entries, an even number so that what follows is
 // 16-byte aligned), then per wavefront the learned-search tiles, then (optionally) the chain's solution
