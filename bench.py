@@ -347,7 +347,12 @@ def main():
         torch.cuda.synchronize()
 
     peak = VALU_PEAK_OPS / 1e12
+    # algorithmic work = the iterations the search consumed; speculative iterations computed after an
+    # accepted one in their round are thrown away and counted apart (executed_frac includes them)
     achieved = st["last_run_period_steps"] * OPS_PER_PERIOD_STEP / (run_ms / 1e3) / 1e12
+    spec_m, discarded = st["last_run_spec_iters"], st["last_run_discarded_evals"]
+    executed = (evals + discarded) / evals if evals else 1.0
+    run_kernel = "k_run_coop" if spec_m > 1 else "k_run"
     sweep_achieved = sweep_steps * OPS_PER_PERIOD_STEP / (sweep_med / 1e3) / 1e12
     Ks = [i.K for i in insts]
     Ts = sorted({i.T for i in insts})
@@ -379,9 +384,12 @@ def main():
                        {"F_sum": int(sum(f for f, _ in bests)), "last_iteration_improved": last_it,
                         "ms": (last_it + 1) * ms_per_step}),
         "vnd_memo": memo,
-        "roofline": {"kernel": "k_run", "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic("k_run", name),
-                     "ops_per_period_step": OPS_PER_PERIOD_STEP},
+        "roofline": {"kernel": run_kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
+                     "frac": achieved / peak, "traffic": measured_traffic(run_kernel, name),
+                     "ops_per_period_step": OPS_PER_PERIOD_STEP,
+                     "executed_frac": achieved * executed / peak},
+        "speculative_iterations": {"per_chain": spec_m, "discarded_move_evals": discarded,
+                                   "executed_over_consumed": executed},
         "sweep": {"kernel": "k_eval", "move_evals": sweep_ev, "median_ms": sweep_med,
                   "value": sweep_ev / (sweep_med / 1e3), "unit": "move-evals/s", "achieved": sweep_achieved,
                   "peak": peak, "frac": sweep_achieved / peak, "traffic": measured_traffic("k_eval", name)},

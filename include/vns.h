@@ -136,6 +136,9 @@ typedef struct vns_stats {
     int64_t last_mlp_rows;           /*   and the feature rows they processed (rows x epochs for training)   */
     int64_t last_run_spec_iters;     /* iterations computed side by side per chain by the last vns_run (1 or
                                         VNS_OPT_SPEC_ITERS)                                               */
+    int64_t last_run_discarded_evals;/*   and the move-evaluations of its iterations that followed an accepted
+                                        one in their round, computed and thrown away (not in
+                                        last_run_evals)                                                   */
 } vns_stats;
 
 /*

@@ -17,7 +17,9 @@ from pathlib import Path
 from typing import Callable, Iterable, Sequence
 
 SEARCH_CANDIDATES = ([dict(waves=w, lds=l, spec=0, state=st) for w in (2, 4, 8) for l in (0, 65536) for st in (0, 1)] +
-                     [dict(spec=1, spec_waves=s, lds=l) for s in (6, 9, 15) for l in (0, 65536)])
+                     [dict(spec=1, spec_waves=s, lds=l) for s in (6, 9, 15) for l in (0, 65536)] +
+                     [dict(waves=w, lds=65536, spec=0, iters=m) for w, m in
+                      ((8, 2), (8, 3), (8, 4), (4, 3), (4, 4), (4, 6), (4, 8), (2, 6), (2, 8))])
 EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 3, 4, 5, 6, 8, 12, 16)]
 
 
@@ -44,7 +46,9 @@ def tune_search(instances, seed: int, chains: int, nb_list: Sequence[int] = (1, 
                 candidates: Sequence[dict] = tuple(SEARCH_CANDIDATES), warmup: int = 0):
     """Time `iters` GVNS iterations (one launch) after `warmup` untimed ones, on a fresh context, for each
     launch-shape candidate.  The first iterations run the VND of every product; later ones only of the
-    shaken products, so a warm-up tunes for the steady state."""
+    shaken products, so a warm-up tunes for the steady state.  A speculative-iterations candidate whose run
+    fell back to one workgroup per chain (its workgroups do not all fit at once) is timed as infinite: it
+    is another candidate under a different name."""
     from . import vns
 
     def measure(c):
@@ -53,14 +57,17 @@ def tune_search(instances, seed: int, chains: int, nb_list: Sequence[int] = (1, 
             if warmup > 0:
                 ctx.run(warmup)
             ctx.run(iters)
-            return ctx.stats()["last_run_ms"]
+            st = ctx.stats()
+            if st["last_run_spec_iters"] != c.get("iters", 1):
+                return float("inf")
+            return st["last_run_ms"]
 
     return pick(candidates, measure)
 
 
 def search_options(c: dict) -> dict:
-    """Context options of a search candidate (keys waves, lds, spec, spec_waves, state; missing keys keep
-    defaults)."""
+    """Context options of a search candidate (keys waves, lds, spec, spec_waves, state, iters = speculative
+    iterations per chain; missing keys keep defaults)."""
     from . import vns
     opts = {}
     if "waves" in c:
@@ -73,6 +80,8 @@ def search_options(c: dict) -> dict:
         opts[vns.OPT_SPEC_WAVES] = c["spec_waves"]
     if "state" in c:
         opts[vns.OPT_STATE_LDS] = c["state"]
+    if "iters" in c:
+        opts[vns.OPT_SPEC_ITERS] = c["iters"]
     return opts
 
 

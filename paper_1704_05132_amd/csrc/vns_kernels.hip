@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void k_init_costs(InitArgs a) {
         cs.pad = 0;
         cs.nb_evals = 0;
         cs.fallbacks = 0;
+        cs.discarded = 0;
         a.cstate[g] = cs;
     }
 }
@@ -258,10 +259,14 @@ struct RunShared {
     int32_t coop_abort;
 };
 
-// Bounded wait until *p >= v (acquire, agent scope): false if the wait ran out.
+// Bounded wait until *p >= v, false if the wait ran out.  The polls are relaxed (an acquire per poll would
+// invalidate the caches the other workgroups of the XCD are working from); one acquire follows success.
 __device__ __forceinline__ bool coop_wait_ge(int32_t *p, int32_t v) {
     for (uint32_t n = 0; n < kCoopSpinLimit; ++n) {
-        if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= v) return true;
+        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
         __builtin_amdgcn_s_sleep(2);
     }
     return false;
@@ -692,7 +697,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 mine->n_touch = cs.lopt ? nd : -1;   // -1: every product
                 for (int q = 0; q < nd; ++q) mine->dp[q] = sh.dp[q];
             }
-            __threadfence();   // the VND results (written by the wavefronts) and the summary, before the count
+            // the VND results (written by every wavefront) and the summary, before the count
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             // every workgroup of the chain checks in, idle or not, so that none can still be reading this
             // round's starting state when the leader replaces it
@@ -730,6 +736,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         }
                         k = k >= a.kmax ? 1 : k + 1;
                     }
+                    int64_t thrown = 0;   // iterations after the accepted one
+                    for (int j = consumed; j < active && ok; ++j) thrown += a.coop_slot[(int64_t)g * a.coop_m + j].evals;
                     sh.coop_acc = ok ? acc : -1;
                     sh.coop_abort = !ok;
                     if (ok) {
@@ -739,6 +747,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         if (acc >= 0) cs.lopt = 1;
                         ctl->iters_done = done_it + consumed;
                         ctl->evals += ev;
+                        ctl->discarded += thrown;
                     }
                     if (err) atomicOr(&ctl->err, err);
                 }
@@ -755,7 +764,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         a.cur_cost[cp0 + p] = a.coop_res_cost[sb + p];
                     }
                 }
-                __threadfence();
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // x, before the round count
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     a.cstate[g] = cs;
@@ -825,6 +834,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             }
             if (threadIdx.x == 0) {
                 cs.evals = a.coop_ctl[g].evals;
+                cs.discarded = a.coop_ctl[g].discarded;
                 cs.err |= a.coop_ctl[g].err;
                 cs.nb_evals = 0;
                 cs.fallbacks = 0;
@@ -861,6 +871,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         cs.err |= err;
         cs.nb_evals = ne;
         cs.fallbacks = nf;
+        cs.discarded = 0;
         a.cstate[g] = cs;
     }
 }

@@ -812,10 +812,11 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     float ms = 0.f;
     VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    int64_t ev = 0, steps = 0, nbe = 0, fbs = 0;
+    int64_t ev = 0, steps = 0, nbe = 0, fbs = 0, thrown = 0;
     int32_t err = 0;
     for (size_t g = 0; g < cs.size(); ++g) {
         ev += cs[g].evals;
+        thrown += cs[g].discarded;
         steps += cs[g].evals * c->chains[g].T;
         nbe += cs[g].nb_evals;
         fbs += cs[g].fallbacks;
@@ -823,6 +824,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     }
     c->stats.last_run_learned_evals = nbe;
     c->stats.last_run_fallbacks = fbs;
+    c->stats.last_run_discarded_evals = thrown;
     if (err & 2) return fail(c, VNS_EDEVICE, "speculative iterations: a workgroup's wait for its chain ran out");
     if (err) return fail(c, VNS_EDEVICE, "a VND exceeded its pass guard (inconsistent costs)");
     c->iteration += iters;

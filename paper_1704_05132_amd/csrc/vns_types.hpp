@@ -25,7 +25,7 @@ constexpr int kEvalGroup = 16;
 constexpr int kCounterSlots = 256;
 constexpr int kCounterStride = 8;
 __host__ __device__ constexpr int counter_words() { return kCounterSlots * kCounterStride; }
-constexpr int64_t kRunLdsMax = 128 * 1024;  // dynamic LDS the search kernel may request for instance rows     // chains of one instance priced by one k_eval workgroup
+constexpr int64_t kRunLdsMax = 128 * 1024;  // dynamic LDS the search kernel may request for instance rows
 constexpr int kMaxPasses = 1 << 16;  // VND passes per product and iteration: a guard, not a limit of the method
 constexpr int64_t kInf = INT64_MAX;
 constexpr uint64_t kInfKey = ~0ull;
@@ -62,6 +62,7 @@ struct ChainState {
     int32_t pad;
     int64_t nb_evals;   // learned mode: neighbourhood evaluations during the last run
     int64_t fallbacks;  //   and how many of them priced the whole neighbourhood
+    int64_t discarded;  // speculative iterations: move-evaluations of iterations computed and thrown away
 };
 
 struct Record {    // identical layout to vns_record
@@ -111,11 +112,12 @@ struct RunArgs {
 // its own workgroup, as if the earlier ones were rejected; they are then resolved in order and everything
 // after the first accepted one is discarded.  Records, moves and counted evaluations are those of the
 // sequential search.  Per chain, in device memory (set up by the host before each launch):
-struct CoopCtl {
+struct alignas(128) CoopCtl {   // one cache line per chain
     int32_t round;        // rounds completed (the leader increments it to start the next round)
-    int32_t done;         // workgroups that finished the current round's iteration
+    int32_t done;         // workgroups of the chain done with the current round
     int64_t iters_done;   // iterations of this launch resolved so far
     int64_t evals;        // move-evaluations of the resolved iterations
+    int64_t discarded;    //   and of the iterations computed after an accepted one, thrown away
     int32_t abort;        // a bounded wait ran out: every workgroup of the chain leaves
     int32_t err;
 };
@@ -125,7 +127,7 @@ struct CoopSlot {
     int32_t err;
     int32_t dp[kShakeMax];
 };
-constexpr uint32_t kCoopSpinLimit = 1u << 23;   // s_sleep polls before a wait gives up (about a second)
+constexpr uint32_t kCoopSpinLimit = 1u << 23;   // polls before a wait gives up (seconds, not a round's microseconds)
 
 // Dynamic LDS of the search kernel: the rows region (int2 entries, an even number so that what follows is
 // 16-byte aligned), then per wavefront the learned-search tiles, then (optionally) the chain's solution

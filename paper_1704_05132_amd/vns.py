@@ -69,7 +69,8 @@ class VNSStats(ctypes.Structure):
                 ("last_eval_ms", ctypes.c_double), ("last_run_period_steps", ctypes.c_int64),
                 ("last_eval_period_steps", ctypes.c_int64), ("last_run_learned_evals", ctypes.c_int64),
                 ("last_run_fallbacks", ctypes.c_int64), ("last_mlp_ms", ctypes.c_double),
-                ("last_mlp_rows", ctypes.c_int64), ("last_run_spec_iters", ctypes.c_int64)]
+                ("last_mlp_rows", ctypes.c_int64), ("last_run_spec_iters", ctypes.c_int64),
+                ("last_run_discarded_evals", ctypes.c_int64)]
 
 
 class VNSError(RuntimeError):

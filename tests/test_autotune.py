@@ -39,6 +39,7 @@ def test_search_options_map_every_key():
                                                                                vns.OPT_RUN_LDS: 65536}
     assert autotune.search_options({"group": 8}) == {}
     assert autotune.search_options(dict(waves=2, state=1)) == {vns.OPT_RUN_WAVES: 2, vns.OPT_STATE_LDS: 1}
+    assert autotune.search_options(dict(waves=4, iters=6)) == {vns.OPT_RUN_WAVES: 4, vns.OPT_SPEC_ITERS: 6}
 
 
 def test_candidates_cover_both_search_kernels():
@@ -47,3 +48,6 @@ def test_candidates_cover_both_search_kernels():
     for c in autotune.SEARCH_CANDIDATES:
         if c.get("spec"):
             assert c["spec_waves"] % 3 == 0 and 3 <= c["spec_waves"] <= 16   # whole groups of three waves
+            assert "iters" not in c   # speculative iterations run the one-wavefront-per-product VND
+        assert 1 <= c.get("iters", 1) <= 8
+    assert any(c.get("iters", 1) > 1 for c in autotune.SEARCH_CANDIDATES)

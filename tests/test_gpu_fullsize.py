@@ -74,6 +74,9 @@ def test_plain_100x52_bench_launch(vns):
     with tuned_context(vns, name, [inst]) as ctx:
         say(f"  {name}: {w['chains']} chains x {w['iters']} iterations, one launch")
         ctx.run(w["iters"])
+        from paper_1704_05132_amd import autotune
+        choice = autotune.TuneTable(TUNE).get(autotune.signature([inst], w["chains"]))["choice"]
+        assert ctx.stats()["last_run_spec_iters"] == choice.get("iters", 1)   # the launch bench.py times
         for g in range(ctx.n_chains):
             rec = ctx.trajectory(g)
             assert len(rec) == w["iters"] and (rec["iter"] == np.arange(w["iters"])).all()

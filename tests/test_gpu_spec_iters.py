@@ -56,8 +56,11 @@ def test_speculative_iterations_equal_one_workgroup(vns, m, layout):
         for iters in (1, 40, 97):   # a chain's first iteration (a full sweep), then runs that continue it
             ref.run(iters)
             ctx.run(iters)
-            assert ctx.stats()["last_run_spec_iters"] == m
-            assert ref.stats()["last_run_spec_iters"] == 1
+            st, rst = ctx.stats(), ref.stats()
+            assert st["last_run_spec_iters"] == m and rst["last_run_spec_iters"] == 1
+            assert rst["last_run_discarded_evals"] == 0
+            # the first iteration of a chain runs alone; later rounds throw away what follows an acceptance
+            assert (st["last_run_discarded_evals"] > 0) == (iters > 1)
             same_search(ctx, ref, ctx.n_chains)
         acc = sum(int(ctx.trajectory(g)["accepted"].sum()) for g in range(ctx.n_chains))
         assert 0 < acc < 97 * ctx.n_chains   # both outcomes occur, so rounds end early and run to the end
