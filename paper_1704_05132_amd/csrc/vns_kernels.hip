@@ -331,7 +331,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         const int64_t sb = ((int64_t)g * a.coop_m + slot) * a.coop_kmax;
         s_cur = a.cur + cp0;
         s_cur_cost = a.cur_cost + cp0;
-        s_work = a.coop_res + sb;
+        s_work = a.coop_res + sb;   // (a split round uses slot 0's region)
         s_work_cost = a.coop_res_cost + sb;
     } else if (a.state_off >= 0) {
         char *base = reinterpret_cast<char *>(s_rows) + a.state_off;
@@ -373,6 +373,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         int kshake = cs.k;
         bool go = true;           // this workgroup has an iteration to compute in this round
         int active = 1;           // iterations computed in this round
+        bool split = false;       // one iteration whose products are shared out over the chain's workgroups
+        int vfirst = wave, vstep = W;   // this wavefront's products in the VND loop
         const int64_t ev_round = evals;
         if constexpr (COOP) {
             // the chain's state as the leader left it (acquired at the end of the previous round)
@@ -386,11 +388,24 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             cs = sh.coop_cs;
             done_it = sh.coop_done_it;
             if (sh.coop_stop) break;
-            active = cs.lopt ? (int)min<int64_t>(a.coop_m, a.iters - done_it) : 1;
-            go = slot < active;
-            it = it_first + done_it + slot;
+            // Until x is known to be a local optimum an iteration runs the VND of every product (the first
+            // iteration from the initial solution is most of a short run's time): then the m workgroups
+            // share that one iteration's products, which are independent (Section 3), each shaking alike
+            // and writing its products' results into slot 0's region.  Otherwise each workgroup computes
+            // its own iteration of the round.
+            split = !cs.lopt;
+            active = split ? 1 : (int)min<int64_t>(a.coop_m, a.iters - done_it);
+            go = split || slot < active;
+            it = it_first + done_it + (split ? 0 : slot);
             kshake = cs.k;   // the shake size after this workgroup's slot rejections
-            for (int q = 0; q < slot; ++q) kshake = kshake >= a.kmax ? 1 : kshake + 1;
+            for (int q = 0; q < slot && !split; ++q) kshake = kshake >= a.kmax ? 1 : kshake + 1;
+            const int64_t sb = ((int64_t)g * a.coop_m + (split ? 0 : slot)) * a.coop_kmax;
+            s_work = a.coop_res + sb;
+            s_work_cost = a.coop_res_cost + sb;
+            if (split) {
+                vfirst = slot * W + wave;
+                vstep = a.coop_m * W;
+            }
         }
         int nd = 0;
         int64_t part = 0, shk = 0;
@@ -577,7 +592,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             // ---- VND (Algorithm 1) per product: the shaken products, or every product until x is known to
             //      be a local optimum ----
             const int nprod = cs.lopt ? nd : K;
-            for (int idx = wave; idx < nprod; idx += W) {
+            for (int idx = vfirst; idx < nprod; idx += vstep) {
                 int p, e = -1;
                 if (cs.lopt) {
                     p = sh.dp[idx];
@@ -704,24 +719,43 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             // round's starting state when the leader replaces it
             if (threadIdx.x == 0) __hip_atomic_fetch_add(&ctl->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (slot == 0) {
-                // the leader resolves the round in iteration order: the first accepted iteration ends it
-                if (threadIdx.x == 0) {
-                    const bool ok = coop_wait_ge(&ctl->done, a.coop_m);
+                // the leader resolves the round in iteration order: the first accepted iteration ends it.
+                // Wavefront 0 loads the m summaries side by side (lane j: slot j) and resolves them with
+                // wave-uniform arithmetic; lane 0 writes.
+                if (wave == 0) {
+                    int okl = 1;
+                    if (lane == 0) okl = coop_wait_ge(&ctl->done, a.coop_m);
+                    const bool ok = __shfl(okl, 0, 64) != 0;
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    int64_t dl = 0, ds = 0, le = 0;   // lane j: slot j's F_local - F, F_shaken - F, evaluations
+                    int lerr = 0;
+                    if (ok && lane < a.coop_m) {
+                        const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + lane;
+                        dl = sj->F_local - cs.F;
+                        ds = sj->F_shaken - cs.F;
+                        le = sj->evals;
+                        lerr = sj->err;
+                    }
+                    if (split) {   // the one iteration is the sum of every slot's share
+                        dl = wave_sum_i64(dl);
+                        ds = wave_sum_i64(ds);
+                        le = wave_sum_i64(le);
+                        lerr = __any(lerr != 0) ? 1 : 0;
+                    }
                     int acc = -1, consumed = active, k = cs.k, err = ok ? 0 : 2;
-                    int64_t F = cs.F, Fb = cs.F_best, ev = 0;
+                    int64_t F = cs.F, Fb = cs.F_best, ev = 0, thrown = 0;
                     for (int j = 0; j < active && ok; ++j) {
-                        const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + j;
-                        const int64_t Fl = sj->F_local;
-                        ev += sj->evals;
-                        err |= sj->err;
+                        const int64_t Fl = cs.F + __shfl(dl, j, 64), Fs = cs.F + __shfl(ds, j, 64);
+                        ev += __shfl(le, j, 64);
+                        err |= __shfl(lerr, j, 64);
                         const int accepted = Fl < F;
-                        if (a.trace) {
+                        if (a.trace && lane == 0) {
                             Record r;
                             r.iter = (int32_t)(it_first + done_it + j);
                             r.k = k;
                             r.accepted = accepted;
                             r.pad = 0;
-                            r.F_shaken = sj->F_shaken;
+                            r.F_shaken = Fs;
                             r.F_local = Fl;
                             r.F_best = (accepted && Fl < Fb) ? Fl : Fb;
                             a.trace[(int64_t)g * a.iters + done_it + j] = r;
@@ -736,20 +770,22 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         }
                         k = k >= a.kmax ? 1 : k + 1;
                     }
-                    int64_t thrown = 0;   // iterations after the accepted one
-                    for (int j = consumed; j < active && ok; ++j) thrown += a.coop_slot[(int64_t)g * a.coop_m + j].evals;
-                    sh.coop_acc = ok ? acc : -1;
-                    sh.coop_abort = !ok;
-                    if (ok) {
-                        cs.F = F;
-                        cs.F_best = Fb;
-                        cs.k = k;
-                        if (acc >= 0) cs.lopt = 1;
-                        ctl->iters_done = done_it + consumed;
-                        ctl->evals += ev;
-                        ctl->discarded += thrown;
+                    // iterations after the accepted one are thrown away (none in a split round: active = 1)
+                    for (int j = consumed; j < active && ok; ++j) thrown += __shfl(le, j, 64);
+                    if (lane == 0) {
+                        sh.coop_acc = ok ? acc : -1;
+                        sh.coop_abort = !ok;
+                        if (ok) {
+                            cs.F = F;
+                            cs.F_best = Fb;
+                            cs.k = k;
+                            if (acc >= 0) cs.lopt = 1;
+                            ctl->iters_done = done_it + consumed;
+                            ctl->evals += ev;
+                            ctl->discarded += thrown;
+                        }
+                        if (err) atomicOr(&ctl->err, err);
                     }
-                    if (err) atomicOr(&ctl->err, err);
                 }
                 __syncthreads();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the slots' results, for every thread
