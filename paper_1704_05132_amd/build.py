@@ -16,6 +16,9 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
     # packed FP32 instructions stay off for every HIP object of the project
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary VGPRs: with the accumulator-register form the scorer's MFMAs all went
+    # through one accumulator and ran one after another
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     f"-I{ROOT / 'include'}", f"-I{CSRC}",
 ]
 

@@ -14,31 +14,46 @@
 namespace vns {
 namespace mlp {
 
-namespace {
-
-__device__ __forceinline__ void stage_features(const float *__restrict__ X, int64_t row, int64_t n, __bf16 *sx) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int f = 0; f < kF; ++f) sx[lane * kF + f] = (__bf16)(row < n ? X[row * kF + f] : 0.f);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-}  // namespace
-
-// Scores of n feature rows: each wavefront loads the weight fragments once and scores tiles of 64 rows
-// blockIdx.x, blockIdx.x + gridDim.x, ...
+// Scores of n feature rows (X 16-byte aligned): each wavefront loads the weight fragments once and scores
+// tiles of 64 rows blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's rows (one 64-byte row per lane,
+// four 16-byte loads) are in flight while the current tile is scored.
 __global__ __launch_bounds__(64) void k_mlp_score(const float *__restrict__ P, const float *__restrict__ X, int64_t n,
                                                   float *__restrict__ out) {
     extern __shared__ __attribute__((aligned(16))) __bf16 s_mlp[];
     __bf16 *sx = s_mlp;
+    const int lane = threadIdx.x & 63;
+    const float4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    float4 v[4];
+    auto fetch = [&](int64_t tile) {   // rows past n read row n-1 and score zeros
+        const int64_t row = tile * 64 + lane;
+        const float4 *src = reinterpret_cast<const float4 *>(X + (row < n ? row : n - 1) * kF);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 w = src[q];
+            v[q] = row < n ? w : zero4;
+        }
+    };
+    int64_t tile = blockIdx.x;
+    if (tile * 64 < n) fetch(tile);
     Frags fr;
     load_frags(P, fr);
-    for (int64_t tile = blockIdx.x; tile * 64 < n; tile += gridDim.x) {
-        const int64_t row = tile * 64 + (threadIdx.x & 63);
-        stage_features(X, row, n, sx);
+    for (; tile * 64 < n; tile += gridDim.x) {
+        bf8 lo, hi;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                lo[4 * q + e] = (__bf16)v[q][e];
+                hi[4 * q + e] = (__bf16)v[2 + q][e];
+            }
+        *reinterpret_cast<bf8 *>(sx + lane * kF) = lo;
+        *reinterpret_cast<bf8 *>(sx + lane * kF + 8) = hi;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if ((tile + gridDim.x) * 64 < n) fetch(tile + gridDim.x);
         const float s = forward64(sx, fr);   // ends with a wavefront barrier: sx may be rewritten
+        const int64_t row = tile * 64 + lane;
         if (row < n) out[row] = s;
     }
 }
@@ -178,7 +193,7 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, const float
 hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t tiles = (n + 63) / 64;
-    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 256 * 16);   // 16 wavefronts per CU, each a few tiles
+    const unsigned grid = (unsigned)std::min<int64_t>(tiles, 256 * 8);   // 8 wavefronts per CU, each many tiles
     hipLaunchKernelGGL(mlp::k_mlp_score, dim3(grid), dim3(64), mlp::kWaveLdsBytes, s, P, X, n, out);
     return hipGetLastError();
 }

@@ -32,9 +32,12 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 // ReLU of two float32 values rounded to bfloat16 (nearest even), packed: one v_cvt_pk_bf16_f32 and one
 // v_pk_max_i16 (a negative bfloat16, -0 included, is a negative int16; rounding keeps the sign, so the
-// order of rounding and ReLU does not matter).
+// order of rounding and ReLU does not matter).  The pair is converted as one 2-vector: converting the two
+// values one by one costs two conversions and a permute.
 __device__ __forceinline__ bf2 relu_pack(float a, float b) {
-    const bf2 p = {(__bf16)a, (__bf16)b};
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = {a, b};
+    const bf2 p = __builtin_convertvector(v, bf2);
     const s2 zero = {0, 0};
     return __builtin_bit_cast(bf2, __builtin_elementwise_max(__builtin_bit_cast(s2, p), zero));
 }
