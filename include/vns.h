@@ -97,7 +97,7 @@ enum vns_option {
                               the same, with fewer move-evaluations.  0 (default) = every neighbourhood
                               is priced in every pass, as Algorithm 1 states.  Not used by the
                               speculative search                                                      */
-    VNS_OPT_SPEC_ITERS = 15 /* m in 1..8 (default 1 = off): a rejected iteration leaves x unchanged and
+    VNS_OPT_SPEC_ITERS = 15 /* m in 1..16 (default 1 = off): a rejected iteration leaves x unchanged and
                               the shake of an iteration depends only on (seed, chain, iteration, k), so
                               m workgroups per chain compute the next m iterations side by side as if
                               the earlier ones were rejected; they are resolved in order and what

@@ -499,7 +499,7 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             c->vnd_memo = (int32_t)v;
             return VNS_OK;
         case VNS_OPT_SPEC_ITERS:
-            if (v < 1 || v > 8) return fail(c, VNS_EINVAL, "spec_iters must be in 1..8");
+            if (v < 1 || v > 16) return fail(c, VNS_EINVAL, "spec_iters must be in 1..16");
             c->spec_iters = (int32_t)v;
             return VNS_OK;
         case VNS_OPT_LEARNED:

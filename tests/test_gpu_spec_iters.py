@@ -43,7 +43,7 @@ def same_search(a, b, n_chains):
 
 
 # 8 instances x 4 chains = 32 chains (the XCD-aware placement) and 1 instance x 3 chains (the plain one)
-@pytest.mark.parametrize("m", [2, 4, 8])
+@pytest.mark.parametrize("m", [2, 4, 8, 16])
 @pytest.mark.parametrize("layout", ["xcd", "plain"])
 def test_speculative_iterations_equal_one_workgroup(vns, m, layout):
     if layout == "xcd":
@@ -51,8 +51,10 @@ def test_speculative_iterations_equal_one_workgroup(vns, m, layout):
     else:
         insts, chains = [workload("batched_4096", 5)], 3
     say(f"  spec_iters m={m} layout={layout}")
+    # 16 iterations side by side: 4 wavefronts per workgroup, so that the 512 workgroups are resident at once
+    opts = {vns.OPT_SPEC_ITERS: m, **({vns.OPT_RUN_WAVES: 4} if m > 8 else {})}
     with vns.Context(insts, seed=7, chains=chains) as ref, \
-            vns.Context(insts, seed=7, chains=chains, options={vns.OPT_SPEC_ITERS: m}) as ctx:
+            vns.Context(insts, seed=7, chains=chains, options=opts) as ctx:
         for iters in (1, 40, 97):   # a chain's first iteration (a full sweep), then runs that continue it
             ref.run(iters)
             ctx.run(iters)
@@ -125,8 +127,8 @@ def test_speculative_iterations_fall_back(vns, case):
 def test_spec_iters_option_range(vns):
     with vns.Context(workload("plain_10x12"), seed=1) as ctx:
         assert ctx.get_option(vns.OPT_SPEC_ITERS) == 1
-        for bad in (0, 9, -1):
+        for bad in (0, 17, -1):
             with pytest.raises(vns.VNSError):
                 ctx.set_option(vns.OPT_SPEC_ITERS, bad)
-        ctx.set_option(vns.OPT_SPEC_ITERS, 8)
-        assert ctx.get_option(vns.OPT_SPEC_ITERS) == 8
+        ctx.set_option(vns.OPT_SPEC_ITERS, 16)
+        assert ctx.get_option(vns.OPT_SPEC_ITERS) == 16
