@@ -132,3 +132,25 @@ def test_spec_iters_option_range(vns):
                 ctx.set_option(vns.OPT_SPEC_ITERS, bad)
         ctx.set_option(vns.OPT_SPEC_ITERS, 16)
         assert ctx.get_option(vns.OPT_SPEC_ITERS) == 16
+
+
+# Degenerate instances: with zero costs or zero demand nothing ever improves, no iteration is accepted and
+# x never becomes a local optimum, so every round shares one iteration over the chain's workgroups; a single
+# product, k_max = 1 and horizons of 1 and 128 periods cover the other ends.
+@pytest.mark.parametrize("kind,K,T,kmax", [
+    ("zero_costs", 7, 12, 5), ("zero_demand", 5, 9, 3), ("uniform", 1, 20, 5), ("uniform", 6, 1, 2),
+    ("uniform", 9, 128, 5), ("sparse", 12, 30, 1), ("big_returns", 10, 24, 4), ("no_returns", 8, 40, 5)])
+def test_speculative_iterations_edge_instances(vns, kind, K, T, kmax):
+    from paper_1704_05132_amd.instances import edge_instance
+    inst = edge_instance(kind, K, T, seed=11)
+    chains, iters, m = 8, 30, 4
+    say(f"  spec_iters edge {kind} {K}x{T} kmax={kmax}")
+    with vns.Context(inst, seed=5, chains=chains, k_max=kmax) as ref, \
+            vns.Context(inst, seed=5, chains=chains, k_max=kmax, options={vns.OPT_SPEC_ITERS: m}) as ctx:
+        ref.run(iters)
+        ctx.run(iters)
+        assert ctx.stats()["last_run_spec_iters"] == m
+        same_search(ctx, ref, chains)
+        for g in (0, 3):
+            rr = oracle.Chain(inst, 5, g, (1, 2, 4), k_max=kmax).run(iters)
+            assert (ctx.trajectory(g) == rr).all(), g
