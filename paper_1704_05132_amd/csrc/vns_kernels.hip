@@ -259,14 +259,17 @@ struct RunShared {
     int32_t coop_abort;
 };
 
-// Bounded wait until *p >= v, false if the wait ran out.  The polls are relaxed (an acquire per poll would
-// invalidate the caches the other workgroups of the XCD are working from); one acquire follows success.
-__device__ __forceinline__ bool coop_wait_ge(int32_t *p, int32_t v) {
+// Bounded wait until *p >= v, false if the wait ran out (after `ticks` of the steady clock, or
+// kCoopSpinLimit polls).  The polls are relaxed (an acquire per poll would invalidate the caches the other
+// workgroups of the XCD are working from); one acquire follows success.
+__device__ __forceinline__ bool coop_wait_ge(int32_t *p, int32_t v, int64_t ticks) {
+    const int64_t t0 = wall_clock64();
     for (uint32_t n = 0; n < kCoopSpinLimit; ++n) {
         if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             return true;
         }
+        if (wall_clock64() - t0 > ticks) return false;
         __builtin_amdgcn_s_sleep(2);
     }
     return false;
@@ -724,7 +727,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 // wave-uniform arithmetic; lane 0 writes.
                 if (wave == 0) {
                     int okl = 1;
-                    if (lane == 0) okl = coop_wait_ge(&ctl->done, a.coop_m);
+                    if (lane == 0) okl = coop_wait_ge(&ctl->done, a.coop_m, a.coop_wait_ticks);
                     const bool ok = __shfl(okl, 0, 64) != 0;
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     int64_t dl = 0, ds = 0, le = 0;   // lane j: slot j's F_local - F, F_shaken - F, evaluations
@@ -809,7 +812,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     __hip_atomic_fetch_add(&ctl->round, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }
             } else if (threadIdx.x == 0) {
-                if (!coop_wait_ge(&ctl->round, coop_round + 1)) {
+                if (!coop_wait_ge(&ctl->round, coop_round + 1, a.coop_wait_ticks)) {
                     __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     atomicOr(&ctl->err, 2);
                 }

@@ -58,6 +58,7 @@ struct vns_ctx {
     int64_t run_lds_budget = 64 * 1024;   // bytes of LDS the search kernel may use for an instance's rows
     int32_t use_graph = 0;
     int64_t max_lds_per_wg = 65536;       // device limit on LDS per workgroup (queried at create)
+    int64_t coop_wait_ticks = 0;          // steady-clock ticks of kCoopWaitSeconds (clock rate queried at create)
     int32_t permille = 0;                 // learned scorer: top permille priced exactly (0 = plain search)
     int32_t speculate = 0;                // plain search: speculative VND (neighbourhoods priced side by side)
     int32_t state_lds = 1;                // search kernel: chains' solution state in LDS when it fits
@@ -392,6 +393,8 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
         int v = 0;
         VNS_CREATE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
         c->max_lds_per_wg = v;
+        VNS_CREATE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, c->device));   // kHz
+        c->coop_wait_ticks = (int64_t)((double)(v > 0 ? v : 100000) * 1000.0 * kCoopWaitSeconds);
     }
     VNS_CREATE_HIP(hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
     c->stream = c->own_stream;
@@ -777,6 +780,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         ra.coop_slot = c->d_coop_slot;
         ra.coop_res = c->d_coop_res;
         ra.coop_res_cost = c->d_coop_res_cost;
+        ra.coop_wait_ticks = c->coop_wait_ticks;
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
         VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));

@@ -105,6 +105,7 @@ struct RunArgs {
     struct CoopSlot *coop_slot; // [chains][m]
     Bits *coop_res;             // [chains][m][coop_kmax] VND results of a slot
     int64_t *coop_res_cost;     // [chains][m][coop_kmax]
+    int64_t coop_wait_ticks;    // ticks of the device's steady clock a wait for the chain may last
 };
 
 // Speculative iterations.  A rejected GVNS iteration leaves x unchanged, and its shake depends only on
@@ -127,7 +128,8 @@ struct CoopSlot {
     int32_t err;
     int32_t dp[kShakeMax];
 };
-constexpr uint32_t kCoopSpinLimit = 1u << 23;   // polls before a wait gives up (seconds, not a round's microseconds)
+constexpr double kCoopWaitSeconds = 20.0;       // a wait for the other workgroups of a chain gives up after this
+constexpr uint32_t kCoopSpinLimit = 1u << 28;   // and after this many polls (at least ~14 s), should the clock stall
 
 // Dynamic LDS of the search kernel: the rows region (int2 entries, an even number so that what follows is
 // 16-byte aligned), then per wavefront the learned-search tiles, then (optionally) the chain's solution
