@@ -115,9 +115,9 @@ typedef struct vns_record {
     int32_t iter;      /* absolute iteration index (continues across vns_run calls)                     */
     int32_t k;         /* shake size used                                                               */
     int32_t accepted;  /* 1 if the VND result replaced the current solution                             */
-    int32_t pad;
-    int64_t F_shaken;  /* objective after the shake                                                     */
-    int64_t F_local;   /* objective after the VND                                                       */
+    int32_t winner;    /* best-of-G search: the random stream whose result was selected; otherwise 0      */
+    int64_t F_shaken;  /* objective after the shake (of the winner)                                     */
+    int64_t F_local;   /* objective after the VND (of the winner)                                       */
     int64_t F_best;    /* best objective of the chain so far                                            */
 } vns_record;
 

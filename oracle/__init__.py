@@ -26,7 +26,7 @@ INF = np.iinfo(np.int64).max
 _HERE = Path(__file__).resolve().parent
 _LIB = None
 
-RECORD_DTYPE = np.dtype([("iter", np.int32), ("k", np.int32), ("accepted", np.int32), ("pad", np.int32),
+RECORD_DTYPE = np.dtype([("iter", np.int32), ("k", np.int32), ("accepted", np.int32), ("winner", np.int32),
                          ("F_shaken", np.int64), ("F_local", np.int64), ("F_best", np.int64)])
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
@@ -72,6 +72,16 @@ def lib():
                                [_u8p, _u8p, _i32p, c.c_int, c.c_int, c.c_uint64, c.c_uint64, c.c_int64,
                                 c.c_int64, c.POINTER(c.c_int32), c.POINTER(c.c_int64), _recp,
                                 c.POINTER(c.c_int64)])
+        L.orc_draw_stream.restype = c.c_int64
+        L.orc_draw_stream.argtypes = [c.c_uint64] * 6
+        L.orc_shake_stream.restype = c.c_int
+        L.orc_shake_stream.argtypes = [c.c_int, c.c_int] + inst + [_u8p, _u8p, c.c_int, c.c_uint64, c.c_uint64,
+                                                                   c.c_uint64, c.c_uint64, _i32p]
+        L.orc_gvns_best_of.restype = c.c_int64
+        L.orc_gvns_best_of.argtypes = ([c.c_int, c.c_int] + inst +
+                                       [_u8p, _u8p, _i32p, c.c_int, c.c_int, c.c_int, c.c_int, c.c_uint64,
+                                        c.c_uint64, c.c_int64, c.c_int64, c.POINTER(c.c_int32),
+                                        c.POINTER(c.c_int64), _recp, c.POINTER(c.c_int64)])
         _LIB = L
     return _LIB
 
@@ -143,16 +153,22 @@ def philox4x64_10(key, ctr):
     return out
 
 
-def draw(seed, chain, it, j, n):
+def draw(seed, chain, it, j, n, stream=0):
+    """Draw j of iteration it of random stream `stream` (Philox counter (it, j, stream, 0)), in [0, n)."""
+    if stream:
+        return int(lib().orc_draw_stream(seed, chain, it, j, stream, n))
     return int(lib().orc_draw(seed, chain, it, j, n))
 
 
-def shake(inst, zM, zR, k, seed, chain, it):
-    """Shake(x, k): returns (zM, zR, applied flags per draw)."""
+def shake(inst, zM, zR, k, seed, chain, it, stream=0):
+    """Shake(x, k) with random stream `stream`: returns (zM, zR, applied flags per draw)."""
     a = _rows(zM, inst.K, inst.T).copy()
     b = _rows(zR, inst.K, inst.T).copy()
     applied = np.zeros(max(k, 1), np.int32)
-    lib().orc_shake(inst.K, inst.T, *_inst(inst), a, b, int(k), seed, chain, it, applied)
+    if stream:
+        lib().orc_shake_stream(inst.K, inst.T, *_inst(inst), a, b, int(k), seed, chain, it, stream, applied)
+    else:
+        lib().orc_shake(inst.K, inst.T, *_inst(inst), a, b, int(k), seed, chain, it, applied)
     return a, b, applied[:k]
 
 
@@ -182,6 +198,32 @@ class Chain:
         self.F = int(lib().orc_gvns(inst.K, inst.T, *_inst(inst), self.zM, self.zR, self.nb, len(self.nb),
                                     self.k_max, self.seed, self.chain, self.it, int(iters), ctypes.byref(k),
                                     ctypes.byref(fb), rec, ctypes.byref(ev)))
+        self.k = int(k.value)
+        self.F_best = int(fb.value)
+        self.it += int(iters)
+        self.evals += int(ev.value)
+        return rec[:int(iters)]
+
+
+class BestOfChain(Chain):
+    """Best-of-G GVNS (Algorithm 2: G shakes of x with the same k, each followed by the VND, the minimum
+    selected).  literal=False keeps the GVNS rule of Section 1 (move iff strictly better, k schedule);
+    literal=True is Algorithm 2 as printed (k fixed, the minimum always replaces x)."""
+
+    def __init__(self, inst, seed, chain, nb_list=(1, 2, 4), k_max=5, G=2, literal=False):
+        super().__init__(inst, seed, chain, nb_list, k_max)
+        self.G = int(G)
+        self.literal = bool(literal)
+
+    def run(self, iters):
+        rec = np.zeros(max(int(iters), 1), RECORD_DTYPE)
+        k = ctypes.c_int32(self.k)
+        fb = ctypes.c_int64(self.F_best)
+        ev = ctypes.c_int64(0)
+        inst = self.inst
+        self.F = int(lib().orc_gvns_best_of(inst.K, inst.T, *_inst(inst), self.zM, self.zR, self.nb, len(self.nb),
+                                            self.k_max, self.G, int(self.literal), self.seed, self.chain, self.it,
+                                            int(iters), ctypes.byref(k), ctypes.byref(fb), rec, ctypes.byref(ev)))
         self.k = int(k.value)
         self.F_best = int(fb.value)
         self.it += int(iters)

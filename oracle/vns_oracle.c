@@ -15,6 +15,8 @@
  *   - VND: Algorithm 1 (per-product best move of one neighbourhood at a time, reduction of the gains,
  *     repeat until no improvement);
  *   - GVNS: Algorithm 2 and the VNS description of Section 1 (shake, VND, accept if better);
+ *   - best-of-G GVNS: Algorithm 2 with the selection Section 3 describes for its two GPUs (G shakes of x
+ *     with the same k, one VND each, the minimum kept), in the GVNS form and as printed;
  *   - Philox4x64-10: Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11.
  */
 #include <stdint.h>
@@ -281,27 +283,33 @@ static void flip_move(int T, int64_t f, int *k, int *l)
     *l = r;     /* local slot: [0,T) flip zM, [T,2T) flip zR — the same numbering as the slots */
 }
 
-/* Draw j of iteration `iter` for chain key (seed, chain): index in [0, n). */
-int64_t orc_draw(uint64_t seed, uint64_t chain, uint64_t iter, uint64_t j, uint64_t n)
+/* Draw j of iteration `iter` of random stream g for chain key (seed, chain): index in [0, n).  Stream 0 is
+ * the chain's own shake; the best-of-G search gives its G parallel shakes streams 0 .. G-1. */
+int64_t orc_draw_stream(uint64_t seed, uint64_t chain, uint64_t iter, uint64_t j, uint64_t g, uint64_t n)
 {
     uint64_t key[2] = {seed, chain};
-    uint64_t ctr[4] = {iter, j, 0, 0};
+    uint64_t ctr[4] = {iter, j, g, 0};
     uint64_t out[4];
     orc_philox4x64_10(key, ctr, out);
     return (int64_t)(((out[0] >> 32) * n) >> 32);
 }
 
-/* Shake(x, k): k random flips, each skipped if it makes its product infeasible.  Returns the number of
- * flips applied; applied[j] (may be NULL) receives 1/0 per draw. */
-int orc_shake(int K, int T, const int32_t *D, const int32_t *R,
-              const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
-              uint8_t *zM, uint8_t *zR, int kshake, uint64_t seed, uint64_t chain, uint64_t iter,
-              int32_t *applied)
+int64_t orc_draw(uint64_t seed, uint64_t chain, uint64_t iter, uint64_t j, uint64_t n)
+{
+    return orc_draw_stream(seed, chain, iter, j, 0, n);
+}
+
+/* Shake(x, k) with random stream g: k random flips, each skipped if it makes its product infeasible.
+ * Returns the number of flips applied; applied[j] (may be NULL) receives 1/0 per draw. */
+int orc_shake_stream(int K, int T, const int32_t *D, const int32_t *R,
+                     const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                     uint8_t *zM, uint8_t *zR, int kshake, uint64_t seed, uint64_t chain, uint64_t iter,
+                     uint64_t g, int32_t *applied)
 {
     int n_applied = 0;
     uint64_t n = 2 * (uint64_t)K * (uint64_t)T;
     for (int j = 0; j < kshake; ++j) {
-        int64_t f = orc_draw(seed, chain, iter, (uint64_t)j, n);
+        int64_t f = orc_draw_stream(seed, chain, iter, (uint64_t)j, g, n);
         int k, l;
         flip_move(T, f, &k, &l);
         size_t o = (size_t)k * (size_t)T;
@@ -318,12 +326,20 @@ int orc_shake(int K, int T, const int32_t *D, const int32_t *R,
     return n_applied;
 }
 
+int orc_shake(int K, int T, const int32_t *D, const int32_t *R,
+              const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+              uint8_t *zM, uint8_t *zR, int kshake, uint64_t seed, uint64_t chain, uint64_t iter,
+              int32_t *applied)
+{
+    return orc_shake_stream(K, T, D, R, kM, kR, hM, hR, zM, zR, kshake, seed, chain, iter, 0, applied);
+}
+
 /* One trajectory record per GVNS iteration. */
 typedef struct {
     int32_t iter;
     int32_t k;
     int32_t accepted;
-    int32_t pad;
+    int32_t winner;   /* best-of-G: the stream whose result was selected (0 for a plain chain) */
     int64_t F_shaken;
     int64_t F_local;
     int64_t F_best;
@@ -365,12 +381,72 @@ int64_t orc_gvns(int K, int T, const int32_t *D, const int32_t *R,
             rec[i].iter = (int32_t)it;
             rec[i].k = k;
             rec[i].accepted = accepted;
-            rec[i].pad = 0;
+            rec[i].winner = 0;
             rec[i].F_shaken = F_shaken;
             rec[i].F_local = F_local;
             rec[i].F_best = *F_best;
         }
     }
     free(sM); free(sR);
+    return F;
+}
+
+/* Best-of-G GVNS, the search of Algorithm 2: in every iteration G copies of x are shaken with the same k,
+ * each by its own random stream g, and each runs the VND; the objective values are compared and the
+ * minimum one is selected (the lowest g among equal values), as Section 3 describes for the two GPUs.
+ *   literal = 0: the selected result replaces x iff it is strictly better, and k follows the GVNS rule of
+ *                Section 1 (k = 1 after a move, else k + 1, back to 1 after k_max);
+ *   literal = 1: Algorithm 2 as printed: k never changes, and the selected result always replaces x
+ *                (accepted = 1 in every record).
+ * State, records (winner = the selected stream, F_shaken / F_local of that stream) and evaluations (all G
+ * VNDs) as in orc_gvns. */
+int64_t orc_gvns_best_of(int K, int T, const int32_t *D, const int32_t *R,
+                         const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                         uint8_t *zM, uint8_t *zR, const int32_t *nb_list, int n_nb, int k_max, int G,
+                         int literal, uint64_t seed, uint64_t chain, int64_t it0, int64_t iters,
+                         int32_t *k_state, int64_t *F_best, orc_record *rec, int64_t *evals)
+{
+    size_t n = (size_t)K * (size_t)T;
+    uint8_t *sM = (uint8_t *)malloc(n), *sR = (uint8_t *)malloc(n);
+    uint8_t *bM = (uint8_t *)malloc(n), *bR = (uint8_t *)malloc(n);
+    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, zM, zR, NULL);
+    for (int64_t i = 0; i < iters; ++i) {
+        int64_t it = it0 + i;
+        int k = *k_state;
+        int best_g = -1;
+        int64_t best_local = 0, best_shaken = 0;
+        for (int g = 0; g < G; ++g) {
+            memcpy(sM, zM, n);
+            memcpy(sR, zR, n);
+            orc_shake_stream(K, T, D, R, kM, kR, hM, hR, sM, sR, k, seed, chain, (uint64_t)it, (uint64_t)g, NULL);
+            int64_t F_shaken = orc_objective(K, T, D, R, kM, kR, hM, hR, sM, sR, NULL);
+            int64_t F_local = orc_vnd(K, T, D, R, kM, kR, hM, hR, sM, sR, nb_list, n_nb, evals);
+            if (best_g < 0 || F_local < best_local) {
+                best_g = g;
+                best_local = F_local;
+                best_shaken = F_shaken;
+                memcpy(bM, sM, n);
+                memcpy(bR, sR, n);
+            }
+        }
+        int accepted = literal ? 1 : best_local < F;
+        if (accepted) {
+            memcpy(zM, bM, n);
+            memcpy(zR, bR, n);
+            F = best_local;
+        }
+        if (!literal) *k_state = accepted ? 1 : ((k >= k_max) ? 1 : k + 1);
+        if (F < *F_best) *F_best = F;
+        if (rec) {
+            rec[i].iter = (int32_t)it;
+            rec[i].k = k;
+            rec[i].accepted = accepted;
+            rec[i].winner = best_g;
+            rec[i].F_shaken = best_shaken;
+            rec[i].F_local = best_local;
+            rec[i].F_best = *F_best;
+        }
+    }
+    free(sM); free(sR); free(bM); free(bR);
     return F;
 }

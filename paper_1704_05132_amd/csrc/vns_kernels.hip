@@ -757,7 +757,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                             r.iter = (int32_t)(it_first + done_it + j);
                             r.k = k;
                             r.accepted = accepted;
-                            r.pad = 0;
+                            r.winner = 0;
                             r.F_shaken = Fs;
                             r.F_local = Fl;
                             r.F_best = (accepted && Fl < Fb) ? Fl : Fb;
@@ -847,7 +847,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             r.iter = (int32_t)it;
             r.k = kshake;
             r.accepted = accepted;
-            r.pad = 0;
+            r.winner = 0;
             r.F_shaken = cs.F + dshake;
             r.F_local = F_local;
             r.F_best = (accepted && F_local < cs.F_best) ? F_local : cs.F_best;

@@ -66,7 +66,7 @@ struct ChainState {
 };
 
 struct Record {    // identical layout to vns_record
-    int32_t iter, k, accepted, pad;
+    int32_t iter, k, accepted, winner;
     int64_t F_shaken, F_local, F_best;
 };
 

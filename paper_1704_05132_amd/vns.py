@@ -27,7 +27,7 @@ ALL_CHAINS = -1
 PRICE_INF = np.iinfo(np.int64).max
 T_MAX = 128
 
-RECORD_DTYPE = np.dtype([("iter", np.int32), ("k", np.int32), ("accepted", np.int32), ("pad", np.int32),
+RECORD_DTYPE = np.dtype([("iter", np.int32), ("k", np.int32), ("accepted", np.int32), ("winner", np.int32),
                          ("F_shaken", np.int64), ("F_local", np.int64), ("F_best", np.int64)])
 
 # Every function the header declares, with its ctypes signature.

@@ -170,3 +170,75 @@ def test_gvns_degenerate_zero_demand():
     # with no demand every setup is removable: the first VND strips all of them
     assert ch.F == 0 and ch.zM.sum() == 0 and ch.zR.sum() == 0
     _check_records(rec, int(inst.kM.sum()) * inst.T, 5)
+
+
+# ---- best-of-G (Algorithm 2: G shakes of x with the same k, each followed by the VND, the minimum kept) ----
+
+def _numpy_draw_stream(seed, chain, it, j, g, n):
+    bg = np.random.Philox(key=np.array([seed, chain], np.uint64), counter=_counter_minus_one([it, j, g, 0]))
+    o0 = int(bg.random_raw(1)[0])
+    return ((o0 >> 32) * n) >> 32
+
+
+@pytest.mark.parametrize("g", [0, 1, 3, 15])
+def test_stream_draws_match_numpy_philox(g):
+    n = 2 * 100 * 52
+    for it, j in ((0, 0), (7, 2), (1999, 4)):
+        assert oracle.draw(5, 9, it, j, n, stream=g) == _numpy_draw_stream(5, 9, it, j, g, n)
+    if g == 0:   # stream 0 is the plain chain's shake
+        assert oracle.draw(5, 9, 7, 2, n) == oracle.draw(5, 9, 7, 2, n, stream=0)
+
+
+def _best_of_by_hand(inst, seed, chain, nb, k_max, G, literal, iters):
+    """Every iteration rebuilt from the oracle's separate steps (stream shake, VND, objective)."""
+    zM = np.ones((inst.K, inst.T), np.uint8)
+    zR = np.zeros((inst.K, inst.T), np.uint8)
+    F, k, best, out = oracle.objective(inst, zM, zR)[0], 1, None, []
+    best = F
+    for it in range(iters):
+        cand = []
+        for g in range(G):
+            a, b, _ = oracle.shake(inst, zM, zR, k, seed, chain, it, stream=g)
+            Fs = oracle.objective(inst, a, b)[0]
+            Fl, a2, b2, _ = oracle.vnd(inst, a, b, nb)
+            cand.append((Fl, g, Fs, a2, b2))
+        Fl, g, Fs, a2, b2 = min(cand, key=lambda c: (c[0], c[1]))   # lowest stream among equal values
+        acc = 1 if literal else int(Fl < F)
+        if acc:
+            zM, zR, F = a2.reshape(inst.K, inst.T), b2.reshape(inst.K, inst.T), Fl
+        best = min(best, F)
+        out.append((it, k, acc, g, Fs, Fl, best))
+        if not literal:
+            k = 1 if acc else (1 if k >= k_max else k + 1)
+    return np.array(out, dtype=oracle.RECORD_DTYPE), zM, zR
+
+
+@pytest.mark.parametrize("G,literal,k_max", [(1, False, 5), (3, False, 5), (4, False, 2), (3, True, 5)])
+def test_best_of_g_selects_the_minimum(G, literal, k_max):
+    inst = edge_instance("uniform", 5, 9, seed=3)
+    ch = oracle.BestOfChain(inst, seed=4, chain=2, nb_list=(1, 2, 4), k_max=k_max, G=G, literal=literal)
+    rec = ch.run(25)
+    ref, zM, zR = _best_of_by_hand(inst, 4, 2, (1, 2, 4), k_max, G, literal, 25)
+    assert (rec == ref).all()
+    assert (ch.zM == zM).all() and (ch.zR == zR).all()
+    if literal:   # Algorithm 2 as printed: k never changes and the minimum always replaces x
+        assert (rec["k"] == 1).all() and (rec["accepted"] == 1).all()
+    if G > 1:
+        assert (rec["winner"] > 0).any()
+
+
+def test_best_of_one_is_the_plain_chain():
+    inst = workload("plain_10x12")
+    a = oracle.BestOfChain(inst, 1, 3, (1, 2), 5, G=1).run(50)
+    b = oracle.Chain(inst, 1, 3, (1, 2)).run(50)
+    assert (a == b).all()
+
+
+def test_best_of_g_never_worse_than_its_first_stream():
+    """At the same state, stream 0 is the plain chain's candidate, so the selected VND result is at most
+    the plain one: the first iteration from the initial solution, over several chains."""
+    inst = edge_instance("uniform", 6, 12, seed=8)
+    for chain in range(4):
+        best = oracle.BestOfChain(inst, 2, chain, (1, 2, 4), 5, G=4).run(1)[0]
+        plain = oracle.Chain(inst, 2, chain).run(1)[0]
+        assert best["F_local"] <= plain["F_local"]
