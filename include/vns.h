@@ -97,7 +97,7 @@ enum vns_option {
                               the same, with fewer move-evaluations.  0 (default) = every neighbourhood
                               is priced in every pass, as Algorithm 1 states.  Not used by the
                               speculative search                                                      */
-    VNS_OPT_SPEC_ITERS = 15 /* m in 1..16 (default 1 = off): a rejected iteration leaves x unchanged and
+    VNS_OPT_SPEC_ITERS = 15, /* m in 1..16 (default 1 = off): a rejected iteration leaves x unchanged and
                               the shake of an iteration depends only on (seed, chain, iteration, k), so
                               m workgroups per chain compute the next m iterations side by side as if
                               the earlier ones were rejected; they are resolved in order and what
@@ -108,6 +108,19 @@ enum vns_option {
                               otherwise the run falls back to one workgroup per chain
                               (vns_stats.last_run_spec_iters = 1).  A chain's workgroups wait for each
                               other with bounded spins: if one runs out, vns_run returns VNS_EDEVICE */
+    VNS_OPT_BEST_OF = 16,  /* G in 0..16 (default 0 = off; 1 = the plain chain): the search of Algorithm 2,
+                              whose GPUs shake the same solution and keep the minimum (Section 3).  Every
+                              iteration shakes x G times with the same k, with random streams 0..G-1 (the
+                              third Philox counter word; stream 0 is the plain chain's shake), runs the VND
+                              on each, and selects the lowest objective (lowest stream among equals;
+                              vns_record.winner).  It moves to it iff strictly better, with the usual k
+                              schedule.  Runs as G workgroups per chain in one cooperative launch: vns_run
+                              returns VNS_EINVAL if they cannot all be resident, or with the learned
+                              scorer, speculative VND, speculative iterations, move log or graph
+                              capture.  Every stream's move-evaluations count                        */
+    VNS_OPT_BEST_OF_LITERAL = 17 /* 0/1 (default 0): best-of-G as Algorithm 2 prints it: k never changes and
+                              the selected result always replaces x (accepted = 1 in every record);
+                              with VNS_OPT_BEST_OF = 0 or 1 it runs one stream                       */
 };
 
 /* One GVNS iteration of one chain. */

@@ -13,7 +13,7 @@ SOURCES = ["vns_kernels.hip", "vns_mlp.hip", "vns_runtime.hip"]
 ARCH = os.environ.get("VNS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Werror=return-type",
     # packed FP32 instructions stay off for every HIP object of the project
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     # matrix-core results in ordinary VGPRs: with the accumulator-register form the scorer's MFMAs all went

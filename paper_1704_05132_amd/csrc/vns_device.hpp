@@ -234,10 +234,12 @@ __device__ __forceinline__ uint64_t philox_word0(uint64_t key0, uint64_t key1, u
     return c0;
 }
 
-// Index in [0, n) of draw j of iteration it for the chain keyed (seed, chain): multiply-shift of the high
-// 32 bits of Philox word 0.
-__device__ __forceinline__ uint32_t shake_draw(uint64_t seed, uint64_t chain, uint64_t it, uint64_t j, uint64_t n) {
-    const uint64_t w = philox_word0(seed, chain, it, j, 0, 0);
+// Index in [0, n) of draw j of iteration it of random stream `stream` for the chain keyed (seed, chain):
+// multiply-shift of the high 32 bits of Philox word 0, counter (it, j, stream, 0).  Stream 0 is the chain's
+// own shake; the best-of-G search shakes with streams 0 .. G-1.
+__device__ __forceinline__ uint32_t shake_draw(uint64_t seed, uint64_t chain, uint64_t it, uint64_t j, uint64_t n,
+                                               uint64_t stream = 0) {
+    const uint64_t w = philox_word0(seed, chain, it, j, stream, 0);
     return (uint32_t)(((w >> 32) * n) >> 32);
 }
 

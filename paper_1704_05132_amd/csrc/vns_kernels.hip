@@ -396,12 +396,13 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             // share that one iteration's products, which are independent (Section 3), each shaking alike
             // and writing its products' results into slot 0's region.  Otherwise each workgroup computes
             // its own iteration of the round.
-            split = !cs.lopt;
-            active = split ? 1 : (int)min<int64_t>(a.coop_m, a.iters - done_it);
-            go = split || slot < active;
-            it = it_first + done_it + (split ? 0 : slot);
+            // Best-of-G: every workgroup runs the same iteration from x, shaking with its own stream (slot).
+            split = !cs.lopt && !a.best_of;
+            active = (split || a.best_of) ? 1 : (int)min<int64_t>(a.coop_m, a.iters - done_it);
+            go = split || a.best_of || slot < active;
+            it = it_first + done_it + ((split || a.best_of) ? 0 : slot);
             kshake = cs.k;   // the shake size after this workgroup's slot rejections
-            for (int q = 0; q < slot && !split; ++q) kshake = kshake >= a.kmax ? 1 : kshake + 1;
+            for (int q = 0; q < slot && !split && !a.best_of; ++q) kshake = kshake >= a.kmax ? 1 : kshake + 1;
             const int64_t sb = ((int64_t)g * a.coop_m + (split ? 0 : slot)) * a.coop_kmax;
             s_work = a.coop_res + sb;
             s_work_cost = a.coop_res_cost + sb;
@@ -417,7 +418,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         // ---- Shake(x, k): wavefront 0 draws k flips and keeps the feasible ones in the dirty list ----
         if (wave == 0) {
             const bool draw = lane < kshake;
-            const uint32_t my = draw ? shake_draw(a.seed, (uint64_t)g, (uint64_t)it, (uint64_t)lane, nflip_all) : 0u;
+            const uint32_t my = draw ? shake_draw(a.seed, (uint64_t)g, (uint64_t)it, (uint64_t)lane, nflip_all,
+                                                  COOP && a.best_of ? (uint64_t)slot : 0u) : 0u;
             const int pd = (int)(my / (uint32_t)(2 * T));          // lane j: product and flip slot of draw j
             const int ld = (int)(my - (uint32_t)pd * (uint32_t)(2 * T));
             bool dup = false;                                        // an earlier draw hit the same product
@@ -745,30 +747,45 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         le = wave_sum_i64(le);
                         lerr = __any(lerr != 0) ? 1 : 0;
                     }
+                    int sel = 0;   // best-of-G: the stream whose result is kept
+                    if (a.best_of) {
+                        // the minimum local cost over the G streams, the lowest stream among equal values; every
+                        // stream's evaluations count
+                        const bool mine = ok && lane < a.coop_m;
+                        const uint64_t myF = mine ? (uint64_t)(cs.F + dl) : ~0ull;
+                        const uint64_t minF = wave_min_u64(myF);
+                        const unsigned long long at = __ballot(mine && myF == minF);
+                        sel = at ? (int)__builtin_ctzll(at) : 0;
+                        dl = __shfl(dl, sel, 64);
+                        ds = __shfl(ds, sel, 64);
+                        le = wave_sum_i64(le);
+                        lerr = __any(lerr != 0) ? 1 : 0;
+                    }
+                    const bool literal = a.best_of && a.best_literal;   // k fixed, the minimum always kept
                     int acc = -1, consumed = active, k = cs.k, err = ok ? 0 : 2;
                     int64_t F = cs.F, Fb = cs.F_best, ev = 0, thrown = 0;
                     for (int j = 0; j < active && ok; ++j) {
                         const int64_t Fl = cs.F + __shfl(dl, j, 64), Fs = cs.F + __shfl(ds, j, 64);
                         ev += __shfl(le, j, 64);
                         err |= __shfl(lerr, j, 64);
-                        const int accepted = Fl < F;
+                        const int accepted = literal ? 1 : Fl < F;
                         if (a.trace && lane == 0) {
                             Record r;
                             r.iter = (int32_t)(it_first + done_it + j);
                             r.k = k;
                             r.accepted = accepted;
-                            r.winner = 0;
+                            r.winner = sel;
                             r.F_shaken = Fs;
                             r.F_local = Fl;
                             r.F_best = (accepted && Fl < Fb) ? Fl : Fb;
                             a.trace[(int64_t)g * a.iters + done_it + j] = r;
                         }
                         if (accepted) {
-                            acc = j;
+                            acc = a.best_of ? sel : j;   // the slot whose VND results x takes
                             consumed = j + 1;
                             F = Fl;
                             Fb = Fl < Fb ? Fl : Fb;
-                            k = 1;
+                            k = literal ? k : 1;
                             break;
                         }
                         k = k >= a.kmax ? 1 : k + 1;

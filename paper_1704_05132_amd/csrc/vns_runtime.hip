@@ -64,6 +64,8 @@ struct vns_ctx {
     int32_t state_lds = 1;                // search kernel: chains' solution state in LDS when it fits
     int32_t vnd_memo = 0;                 // VND: skip neighbourhoods priced without improvement on this pattern
     int32_t spec_iters = 1;               // iterations speculated side by side per chain (1 = off)
+    int32_t best_of = 0;                  // best-of-G search: streams per iteration (0, 1 = the plain chain)
+    int32_t best_literal = 0;             //   as printed (k fixed, the minimum always kept)
     CoopCtl *d_coop_ctl = nullptr;        // speculative iterations: per-chain control, per-slot summaries and
     CoopSlot *d_coop_slot = nullptr;      //   VND results
     Bits *d_coop_res = nullptr;
@@ -505,6 +507,14 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v < 1 || v > 16) return fail(c, VNS_EINVAL, "spec_iters must be in 1..16");
             c->spec_iters = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_BEST_OF:
+            if (v < 0 || v > 16) return fail(c, VNS_EINVAL, "best_of must be in 0..16");
+            c->best_of = (int32_t)v;
+            return VNS_OK;
+        case VNS_OPT_BEST_OF_LITERAL:
+            if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "best_of_literal must be 0 or 1");
+            c->best_literal = (int32_t)v;
+            return VNS_OK;
         case VNS_OPT_LEARNED:
             if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
             c->permille = (int32_t)v;
@@ -545,6 +555,8 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_STATE_LDS: *v = c->state_lds; return VNS_OK;
         case VNS_OPT_VND_MEMO: *v = c->vnd_memo; return VNS_OK;
         case VNS_OPT_SPEC_ITERS: *v = c->spec_iters; return VNS_OK;
+        case VNS_OPT_BEST_OF: *v = c->best_of; return VNS_OK;
+        case VNS_OPT_BEST_OF_LITERAL: *v = c->best_literal; return VNS_OK;
         case VNS_OPT_LOG: *v = c->log_cap; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
@@ -743,12 +755,23 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     VNS_HIP(c, run_kernel_lds(kind, &static_lds, lds));
     // speculative iterations: plain search without the move log (a discarded iteration's moves must not be
     // logged), not captured, and every workgroup of the launch resident at once
-    const int m = c->spec_iters;
+    // best-of-G (Algorithm 2): the same cooperative launch with G workgroups per chain, one per random stream
+    const bool best = c->best_of >= 2 || c->best_literal;
+    const int m = best ? std::max<int>(c->best_of, 1) : c->spec_iters;
     bool coop = false;
     const size_t lds_coop = rows_bytes;   // x stays in device memory: no state region
-    if (m > 1 && kind == RunKind::kPlain && !c->use_graph && ra.log_x == nullptr)
+    if (best) {
+        if (kind != RunKind::kPlain || c->use_graph || ra.log_x != nullptr || c->spec_iters > 1)
+            return fail(c, VNS_EINVAL, "best-of-G runs the plain search alone: no learned scorer, speculative VND or "
+                                       "iterations, move log or graph capture");
         VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop));
-    c->stats.last_run_spec_iters = coop ? m : 1;
+        if (!coop)
+            return fail(c, VNS_EINVAL, "best-of-G needs its G workgroups per chain resident at once: use fewer "
+                                       "chains, wavefronts per workgroup or streams");
+    } else if (m > 1 && kind == RunKind::kPlain && !c->use_graph && ra.log_x == nullptr) {
+        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop));
+    }
+    c->stats.last_run_spec_iters = coop && !best ? m : 1;
     if (coop) {
         const size_t n_res = (size_t)G * (size_t)m * (size_t)max_K;
         if ((size_t)G > c->coop_cap_ctl) {
@@ -781,6 +804,8 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         ra.coop_res = c->d_coop_res;
         ra.coop_res_cost = c->d_coop_res_cost;
         ra.coop_wait_ticks = c->coop_wait_ticks;
+        ra.best_of = best ? 1 : 0;
+        ra.best_literal = c->best_literal;
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
         VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));

@@ -106,6 +106,9 @@ struct RunArgs {
     Bits *coop_res;             // [chains][m][coop_kmax] VND results of a slot
     int64_t *coop_res_cost;     // [chains][m][coop_kmax]
     int64_t coop_wait_ticks;    // ticks of the device's steady clock a wait for the chain may last
+    int32_t best_of;            // 1: best-of-G search (Algorithm 2): the coop_m workgroups of a chain shake the
+                                //    same x with streams 0 .. coop_m-1 and the minimum is kept
+    int32_t best_literal;       // best-of-G as printed: k fixed, the minimum always replaces x
 };
 
 // Speculative iterations.  A rejected GVNS iteration leaves x unchanged, and its shake depends only on
