@@ -12,7 +12,9 @@ the dominant kernel's roofline, the CPU oracle timed on this host on a bounded s
 `time_to_plain_best`: the device time the learned search (a scorer trained on moves logged on disjoint
 instances ranks the moves, the best-ranked tenth is priced exactly, the whole neighbourhood when none of them
 improves) needs to reach the plain search's best cost on the same instance, seeds and chains, beside the
-plain search's own time to it, with the scorer's and the training's rates.  --workload batched_4096 runs the
+plain search's own time to it, with the scorer's and the training's rates; `best_of`: the best-of-4 search
+of Algorithm 2 (4 shakes of x per iteration, the minimum kept; in the GVNS form and as printed) on the same
+chains and iterations, with its time to the plain search's best cost.  --workload batched_4096 runs the
 4096-instance batch (K ~ U{10..200}, T in {12, 24, 52}, 8 chains each) in one launch instead;
 --workload learned_batched_1024 the 1024-instance learned + batched set (K ~ U{100..1000}, T in {52, 104},
 returns U(0.1, 0.9), 16 chains each).
@@ -39,6 +41,8 @@ OPS_PER_PERIOD_STEP = 14     # operations of one period-step of the forward deco
 LANE_SLOTS_PER_STEP = 12
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9 * OPS_PER_PERIOD_STEP / LANE_SLOTS_PER_STEP
 TUNE_FILE = os.path.join(ROOT, "paper_1704_05132_amd", "tune_table.json")
+# best-of-G search (Algorithm 2) measured beside the plain one: shakes per iteration
+BEST_OF_G = 4
 # learned scorer: 2 x (16*64 + 64*64 + 64) flops per scored move; dense bfloat16 matrix-core peak of MI355X
 MLP_FLOP_PER_ROW = 2 * (16 * 64 + 64 * 64 + 64)
 BF16_PEAK_TFLOPS = 2500.0
@@ -330,6 +334,36 @@ def main():
                     "speedup_vs_every_neighbourhood": run_ms / ms_["last_run_ms"],
                     "same_best": bool((mb == [b for b, _ in bests]).all())}
 
+    # --- the best-of-G search of Algorithm 2 (G shakes of x per iteration, the minimum kept), GVNS form and as
+    #     printed, on the same chains and iterations ---
+    best_of = None
+    if name == "plain_100x52":
+        best_of = {"G": BEST_OF_G, "plain_best_F": int(min(b for b, _ in bests))}
+        for variant, literal in (("gvns", 0), ("literal", 1)):
+            with vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=False,
+                             options={vns.OPT_BEST_OF: BEST_OF_G, vns.OPT_BEST_OF_LITERAL: literal,
+                                      vns.OPT_RUN_WAVES: 4, vns.OPT_RUN_LDS: 65536}) as bctx:
+                bctx.bind_stream(stream)
+                bctx.run(args.steps)
+                bs = bctx.stats()
+                best_of[variant] = {"kernel_ms": bs["last_run_ms"], "move_evals": bs["last_run_evals"],
+                                    "move_evals_per_s": bs["last_run_evals"] / (bs["last_run_ms"] / 1e3),
+                                    "best_F": int(bctx.costs()[1].min())}
+
+            # device time until the best-of search holds the plain search's best cost (launches of --chunk)
+            def make_best(literal=literal):
+                c = vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=False,
+                                options={vns.OPT_BEST_OF: BEST_OF_G, vns.OPT_BEST_OF_LITERAL: literal,
+                                         vns.OPT_RUN_WAVES: 4, vns.OPT_RUN_LDS: 65536})
+                c.bind_stream(stream)
+                return c
+
+            import numpy as np
+            r = chunked_search(make_best, 1, chains, args.steps, args.chunk,
+                               targets=np.array([best_of["plain_best_F"]], np.int64))
+            best_of[variant]["ms_to_plain_best"] = r["ms"]
+            best_of[variant]["iters_to_plain_best"] = r["iters"] if r["ms"] is not None else None
+
     # --- full-neighbourhood sweep of all chains (pricing kernel alone) ---
     sweep_ms, sweep_ev, sweep_steps = [], 0, 0
     for _ in range(args.sweep_reps):
@@ -384,6 +418,7 @@ def main():
                        {"F_sum": int(sum(f for f, _ in bests)), "last_iteration_improved": last_it,
                         "ms": (last_it + 1) * ms_per_step}),
         "vnd_memo": memo,
+        "best_of": best_of,
         "roofline": {"kernel": run_kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(run_kernel, name),
                      "ops_per_period_step": OPS_PER_PERIOD_STEP,
