@@ -748,7 +748,11 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     int64_t state_bytes = c->state_lds ? (int64_t)(2 * sizeof(Bits) + 2 * sizeof(int64_t)) * max_K : 0;
     if (room - state_bytes < slices * (int64_t)sizeof(int2)) state_bytes = 0;
     const int64_t budget = std::min<int64_t>(c->run_lds_budget, room - state_bytes) / (int64_t)sizeof(int2);
-    ra.lds_rows = (int32_t)std::min<int64_t>(max_rows, budget);
+    // no LDS for rows when not even the smallest instance fits: the per-wave slices suffice, and the
+    // workgroups stay small enough to share a compute unit
+    int64_t min_rows = max_rows;
+    for (int32_t i = 0; i < c->n_inst; ++i) min_rows = std::min<int64_t>(min_rows, (int64_t)c->K[(size_t)i] * c->T[(size_t)i]);
+    ra.lds_rows = min_rows > budget ? 0 : (int32_t)std::min<int64_t>(max_rows, budget);
     const size_t rows_bytes = (size_t)run_rows_entries(ra.lds_rows, waves) * sizeof(int2);
     ra.state_off = state_bytes > 0 ? (int32_t)(rows_bytes + (size_t)learned) : -1;
     const size_t lds = rows_bytes + (size_t)learned + (size_t)state_bytes;

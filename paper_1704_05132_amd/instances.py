@@ -70,6 +70,8 @@ WORKLOADS = {
                          desc="Batched plain VNS, 4096 instances, K~U{10..200}, T in {12,24,52}, 8 chains x 1000"),
     "learned_100x52": dict(n_inst=17, K=100, T=52, chains=64, iters=2000, nb=(1, 2, 4), seed=4,
                            desc="Learned proposal on K=100, T=52 instances"),
+    "paper_300x52": dict(n_inst=108, K=300, T=52, chains=8, iters=2000, nb=(1, 2, 4), seed=6,
+                         desc="The paper's benchmark shape (108 instances of 300 products x 52 periods), synthetic"),
     "learned_batched_1024": dict(n_inst=1024, K=(100, 1000), T=(52, 104), chains=16, iters=5000,
                                  nb=(1, 2, 4), seed=5, ret=(0.1, 0.9),
                                  desc="Learned + batched, 1024 instances, K~U{100..1000}, T in {52,104}"),
@@ -90,7 +92,8 @@ def workload(name: str, i: int = 0) -> Instance:
 
     plain_10x12: SeedSequence(1); plain_100x52: SeedSequence(2); batched_4096: SeedSequence([3, i]) with K then
     T drawn first; learned_100x52: i = 0 is the plain_100x52 instance, i >= 1 SeedSequence([4, i - 1]),
-    training instances are i >= 100; learned_batched_1024: SeedSequence([5, i]).
+    training instances are i >= 100; learned_batched_1024: SeedSequence([5, i]); paper_300x52: SeedSequence([6, i]),
+    instances 0..107 are the set, training instances are i >= 1000.
     """
     w = WORKLOADS[name]
     if name == "plain_10x12":
@@ -101,6 +104,8 @@ def workload(name: str, i: int = 0) -> Instance:
         return _seq_instance([3, i], w["K"], w["T"], tag=f"{name}/{i}")
     if name == "learned_100x52":
         return workload("plain_100x52") if i == 0 else _seq_instance([4, i - 1], 100, 52, tag=f"{name}/{i}")
+    if name == "paper_300x52":
+        return _seq_instance([6, i], 300, 52, tag=f"{name}/{i}")
     if name == "learned_batched_1024":
         return _seq_instance([5, i], w["K"], w["T"], ret=w["ret"], tag=f"{name}/{i}")
     raise KeyError(name)
