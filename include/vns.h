@@ -118,9 +118,15 @@ enum vns_option {
                               returns VNS_EINVAL if they cannot all be resident, or with the learned
                               scorer, speculative VND, speculative iterations, move log or graph
                               capture.  Every stream's move-evaluations count                        */
-    VNS_OPT_BEST_OF_LITERAL = 17 /* 0/1 (default 0): best-of-G as Algorithm 2 prints it: k never changes and
+    VNS_OPT_BEST_OF_LITERAL = 17, /* 0/1 (default 0): best-of-G as Algorithm 2 prints it: k never changes and
                               the selected result always replaces x (accepted = 1 in every record);
                               with VNS_OPT_BEST_OF = 0 or 1 it runs one stream                       */
+    VNS_OPT_EVAL_INCREMENTAL = 18 /* 0/1 (default 0): vns_eval_neighbourhood prices every move exactly but
+                              decodes it only from its first changed period, starting from the current
+                              pattern's state there, until its state equals the current pattern's again
+                              (the rest of the cost then differs by known amounts) or it turns
+                              infeasible.  Same prices, argmins and counted evaluations;
+                              vns_stats.last_eval_decoded_steps reports the period-steps decoded      */
 };
 
 /* One GVNS iteration of one chain. */
@@ -152,6 +158,8 @@ typedef struct vns_stats {
     int64_t last_run_discarded_evals;/*   and the move-evaluations of its iterations that followed an accepted
                                         one in their round, computed and thrown away (not in
                                         last_run_evals)                                                   */
+    int64_t last_eval_decoded_steps; /* period-steps the last vns_eval_neighbourhood decoded (equal to the
+                                        evaluations' period-steps unless VNS_OPT_EVAL_INCREMENTAL)          */
 } vns_stats;
 
 /*

@@ -81,6 +81,8 @@ struct EvalShared {
     int32_t nswap[kEvalGroup];
     // the workgroup's moves, chain by chain (flips, then zM swaps, then zR swaps): chain << 9 | block << 7 | t
     uint16_t item[kEvalGroup * 4 * kTMax];
+    int32_t next;                 // incremental pricing: the next item of the workgroup's queue
+    int32_t decoded;              //   and the period-steps its lanes decoded
 };
 static_assert(kEvalGroup <= 16 && kTMax <= 128, "item packing");
 
@@ -106,10 +108,135 @@ __device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, in
     }
 }
 
-}  // namespace
+// Incremental exact pricing.  A move changes the pattern only from its first changed period t on, so its
+// decode starts from the base pattern's state before t (snapshot, per chain and period: A = (lim, XR, lsR,
+// last manufacturing setup or -1 before the first one), B = (A1, A2)).  Once every changed period is
+// decoded and the moved pattern's state A equals the base's before some period, every later step adds the
+// same amounts to both, so the cost is the base cost plus the setup-count change, -hM (dA1 + dA2) and hR dA1
+// (the forward decode's cost is linear in A1, A2 and the final XR).  A decode that turns infeasible stops there (kInf).  Lanes take items from
+// the workgroup's queue as they finish, so a wave's time follows the total decoded length, not the longest.
+__device__ __forceinline__ int32_t enc_last(const DecodeState &s) { return s.nolast ? -1 : s.lastM; }
+constexpr int kIncRefill = 4;   // steps between queue refills (a power of two): fewer refills, some idle lanes
 
-__global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restrict__ wg) {
-    __shared__ EvalShared sh;
+// The base pattern b of one chain, decoded by one lane: its state before every period 0..T.
+template <int NW>
+__device__ __forceinline__ void base_snapshot(const Bits &b, const int2 *row, int T, int4 *sa, int2 *sb) {
+    DecodeState s;
+    for (int tau = 0; tau < T; ++tau) {
+        sa[tau] = make_int4(s.lim, s.XR, s.lsR, enc_last(s));
+        sb[tau] = make_int2(s.A1, s.A2);
+        const int w = tau >> 5;
+        uint32_t m = b.m[0], r = b.r[0];
+#pragma unroll
+        for (int q = 1; q < NW; ++q) {
+            m = w == q ? b.m[q] : m;
+            r = w == q ? b.r[q] : r;
+        }
+        decode_step(s, __builtin_amdgcn_sbfe((int32_t)m, tau & 31, 1), __builtin_amdgcn_sbfe((int32_t)r, tau & 31, 1),
+                    tau, row[tau]);
+    }
+    sa[T] = make_int4(s.lim, s.XR, s.lsR, enc_last(s));
+    sb[T] = make_int2(s.A1, s.A2);
+}
+
+template <int NW>
+__device__ __forceinline__ void eval_items_inc(const EvalArgs &a, EvalShared &sh, const int4 *snapA, const int2 *snapB,
+                                               int N, int T, const ProdParams &pp) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    // per-lane item state
+    int idx = 0, j = 0, slot = 0, tau = 0, t1 = 0, dnM = 0, dnR = 0, decoded = 0;
+    bool act = false;
+    Bits mb;
+    DecodeState s;
+    auto start = [&](int i) {
+        const int e = sh.item[i];
+        j = e >> 9;
+        const int blk = (e >> 7) & 3, t = e & 127;
+        slot = blk * T + t;
+        mb = sh.bits[j];
+        const bool onm = test_bit(mb.m, t), onr = test_bit(mb.r, t);
+        dnM = blk == 0 ? (onm ? -1 : 1) : 0;   // a swap keeps the number of setups
+        dnR = blk == 1 ? (onr ? -1 : 1) : 0;
+        xor_move<NW>(mb, blk, t);
+        tau = t;
+        t1 = blk >= 2 ? t + 1 : t;                // last changed period
+        const int4 sa = snapA[j * (T + 1) + t];
+        const int2 sb = snapB[j * (T + 1) + t];
+        s.lim = sa.x;
+        s.XR = sa.y;
+        s.lsR = sa.z;
+        s.lastM = sa.w < 0 ? 0 : sa.w;
+        s.nolast = sa.w < 0 ? -1 : 0;
+        s.A1 = sb.x;
+        s.A2 = sb.y;
+        s.bad = 0;
+    };
+    auto take = [&](bool want) {   // lanes with `want` take consecutive items, one queue update per wavefront
+        const unsigned long long need = __ballot(want);
+        if (need) {
+            const int leader = __ffsll((long long)need) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&sh.next, __popcll(need));
+            base = __shfl(base, leader, 64);
+            if (want) {
+                idx = base + __popcll(need & below);
+                act = idx < N;
+                if (act) start(idx);
+            }
+        }
+    };
+    take(true);
+    bool pend = false;   // finished, waiting for the next refill
+    for (int step = 1; __any(act || pend); ++step) {
+        bool fin = false;
+        int64_t c = kInf;
+        if (act) {
+            if (tau == T) {   // decoded to the horizon
+                fin = true;
+                c = decode_finish<NW>(s, mb, T, pp);
+            } else if (tau > t1) {
+                const int4 sa = snapA[j * (T + 1) + tau];
+                if (sa.x == s.lim && sa.y == s.XR && sa.z == s.lsR && sa.w == enc_last(s)) {   // back on the base
+                    const int2 sb = snapB[j * (T + 1) + tau];
+                    const int64_t dA1 = (int64_t)s.A1 - sb.x, dA2 = (int64_t)s.A2 - sb.y;
+                    c = sh.cost[j] + (int64_t)pp.kM * dnM + (int64_t)pp.kR * dnR - (int64_t)pp.hM * (dA1 + dA2) +
+                        (int64_t)pp.hR * dA1;
+                    fin = true;
+                }
+            }
+            if (!fin) {
+                const int w = tau >> 5;
+                uint32_t m = mb.m[0], r = mb.r[0];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) {
+                    m = w == q ? mb.m[q] : m;
+                    r = w == q ? mb.r[q] : r;
+                }
+                decode_step(s, __builtin_amdgcn_sbfe((int32_t)m, tau & 31, 1),
+                            __builtin_amdgcn_sbfe((int32_t)r, tau & 31, 1), tau, sh.row[tau]);
+                ++tau;
+                ++decoded;
+                if (s.bad) fin = true;   // infeasible: kInf, nothing more to decode
+            }
+            if (fin) {
+                if (c != kInf) atomicMin(&sh.key[j], ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
+                if (a.slot_price) a.slot_price[sh.out_off[j] + slot] = c == kInf ? kInf : sh.F[j] - sh.cost[j] + c;
+                act = false;
+                pend = true;
+            }
+        }
+        if ((step & (kIncRefill - 1)) == 0 || !__any(act)) {   // refill every kIncRefill steps, or when all wait
+            take(pend);
+            pend = false;
+        }
+    }
+    atomicAdd(&sh.decoded, decoded);
+}
+
+template <bool INC>
+__device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__restrict__ wg, EvalShared &sh,
+                                          int4 *s_snap) {
     const EvalWg d = wg[blockIdx.x];
     const int g0 = d.g0, K = d.K, T = d.T, p = d.p, n = d.n;
     const ProdParams pp = a.prod[d.prod];
@@ -177,17 +304,55 @@ __global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restri
     __syncthreads();
 
     const int N = sh.off[n];
-    if (T <= 64)
-        eval_items<2>(a, sh, N, T, pp);
-    else
-        eval_items<4>(a, sh, N, T, pp);
+    if constexpr (INC) {
+        int4 *snapA = s_snap;                                              // [n][T+1]
+        int2 *snapB = reinterpret_cast<int2 *>(s_snap + (size_t)n * (T + 1));   // [n][T+1]
+        if (threadIdx.x < n) {
+            const int j = threadIdx.x;
+            if (T <= 64)
+                base_snapshot<2>(sh.bits[j], sh.row, T, snapA + j * (T + 1), snapB + j * (T + 1));
+            else
+                base_snapshot<4>(sh.bits[j], sh.row, T, snapA + j * (T + 1), snapB + j * (T + 1));
+        }
+        if (threadIdx.x == 0) {
+            sh.next = 0;
+            sh.decoded = 0;
+        }
+        __syncthreads();
+        if (T <= 64)
+            eval_items_inc<2>(a, sh, snapA, snapB, N, T, pp);
+        else
+            eval_items_inc<4>(a, sh, snapA, snapB, N, T, pp);
+    } else {
+        if (T <= 64)
+            eval_items<2>(a, sh, N, T, pp);
+        else
+            eval_items<4>(a, sh, N, T, pp);
+    }
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x) a.prod_key[d.cp + (int64_t)j * K] = sh.key[j];
     if (threadIdx.x == 0) {
         unsigned long long *ctr = a.evals + (size_t)(blockIdx.x & (kCounterSlots - 1)) * kCounterStride;
         atomicAdd(ctr, (unsigned long long)N);
         atomicAdd(ctr + 1, (unsigned long long)N * (unsigned long long)T);
+        // period-steps decoded: the base snapshots and the moves' incremental decodes, or every move in full
+        atomicAdd(ctr + 2, INC ? (unsigned long long)sh.decoded + (unsigned long long)n * T
+                               : (unsigned long long)N * (unsigned long long)T);
     }
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restrict__ wg) {
+    __shared__ EvalShared sh;
+    eval_body<false>(a, wg, sh, nullptr);
+}
+
+// The same sweep priced incrementally; dynamic LDS holds the base snapshots (24 bytes per chain and period).
+__global__ __launch_bounds__(256) void k_eval_inc(EvalArgs a, const EvalWg *__restrict__ wg) {
+    __shared__ EvalShared sh;
+    extern __shared__ __attribute__((aligned(16))) int4 s_snap[];
+    eval_body<true>(a, wg, sh, s_snap);
 }
 
 // ---------------------------------------------------------------------------------------------------
@@ -1015,6 +1180,12 @@ hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s) {
 hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s) {
     if (n_wg <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_eval, dim3((unsigned)n_wg), dim3(256), 0, s, a, wg);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_inc(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, size_t lds_bytes, hipStream_t s) {
+    if (n_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eval_inc, dim3((unsigned)n_wg), dim3(256), lds_bytes, s, a, wg);
     return hipGetLastError();
 }
 

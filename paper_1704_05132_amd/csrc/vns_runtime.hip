@@ -66,6 +66,7 @@ struct vns_ctx {
     int32_t spec_iters = 1;               // iterations speculated side by side per chain (1 = off)
     int32_t best_of = 0;                  // best-of-G search: streams per iteration (0, 1 = the plain chain)
     int32_t best_literal = 0;             //   as printed (k fixed, the minimum always kept)
+    int32_t eval_inc = 0;                 // pricing sweeps decode each move only until it rejoins the base
     CoopCtl *d_coop_ctl = nullptr;        // speculative iterations: per-chain control, per-slot summaries and
     CoopSlot *d_coop_slot = nullptr;      //   VND results
     Bits *d_coop_res = nullptr;
@@ -515,6 +516,10 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "best_of_literal must be 0 or 1");
             c->best_literal = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_EVAL_INCREMENTAL:
+            if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "eval_incremental must be 0 or 1");
+            c->eval_inc = (int32_t)v;
+            return VNS_OK;
         case VNS_OPT_LEARNED:
             if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
             c->permille = (int32_t)v;
@@ -557,6 +562,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_SPEC_ITERS: *v = c->spec_iters; return VNS_OK;
         case VNS_OPT_BEST_OF: *v = c->best_of; return VNS_OK;
         case VNS_OPT_BEST_OF_LITERAL: *v = c->best_literal; return VNS_OK;
+        case VNS_OPT_EVAL_INCREMENTAL: *v = c->eval_inc; return VNS_OK;
         case VNS_OPT_LOG: *v = c->log_cap; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
@@ -574,15 +580,16 @@ extern "C" vns_status vns_bind_stream(vns_ctx *c, void *s) {
 // pricing
 // ---------------------------------------------------------------------------------------------------
 // Sums of the spread workgroup counters (waits for the stream).
-static hipError_t read_counters(vns_ctx *c, unsigned long long (&ev)[2]) {
+static hipError_t read_counters(vns_ctx *c, unsigned long long (&ev)[3]) {
     std::vector<unsigned long long> h((size_t)counter_words());
     hipError_t e = hipMemcpyAsync(h.data(), c->d_evals, sizeof(unsigned long long) * h.size(), hipMemcpyDeviceToHost,
                                   c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    ev[0] = ev[1] = 0;
+    ev[0] = ev[1] = ev[2] = 0;
     for (int s = 0; s < kCounterSlots; ++s) {
         ev[0] += h[(size_t)s * kCounterStride];
         ev[1] += h[(size_t)s * kCounterStride + 1];
+        ev[2] += h[(size_t)s * kCounterStride + 2];
     }
     return e;
 }
@@ -614,15 +621,20 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
         c->slot_price_cap = (size_t)n_slots;
     }
     // workgroup table: for each run of up to eval_group consecutive chains of one instance, one workgroup
-    // per product
-    const int64_t key[3] = {g0, ng, c->eval_group};
+    // per product (incremental pricing: at most as many chains as the snapshots' LDS allows)
+    int32_t maxT = 1;
+    for (int32_t g = g0; g < g0 + ng; ++g) maxT = std::max<int32_t>(maxT, c->chains[(size_t)g].T);
+    const int32_t group = c->eval_inc ? std::max<int32_t>(1, std::min<int32_t>(c->eval_group,
+                                                                              kSnapLdsMax / ((maxT + 1) * kSnapBytes)))
+                                      : c->eval_group;
+    const int64_t key[3] = {g0, ng, group};
     if (!(key[0] == c->eval_wg_key[0] && key[1] == c->eval_wg_key[1] && key[2] == c->eval_wg_key[2])) {
         std::vector<EvalWg> tab;
         int32_t g = g0;
         while (g < g0 + ng) {
             const ChainInfo &ci = c->chains[(size_t)g];
             int32_t n = 1;
-            while (n < c->eval_group && g + n < g0 + ng && c->chains[(size_t)(g + n)].inst == ci.inst) ++n;
+            while (n < group && g + n < g0 + ng && c->chains[(size_t)(g + n)].inst == ci.inst) ++n;
             for (int32_t p = 0; p < ci.K; ++p) {
                 EvalWg w{};
                 w.cp = ci.cp0 + p;
@@ -660,7 +672,11 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     ea.nb_mask = nb_mask;
     VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long) * counter_words(), c->stream));
     VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-    VNS_HIP(c, launch_eval(ea, c->d_eval_wg, c->eval_wg_n, c->stream));
+    if (c->eval_inc)
+        VNS_HIP(c, launch_eval_inc(ea, c->d_eval_wg, c->eval_wg_n, (size_t)group * (size_t)(maxT + 1) * kSnapBytes,
+                                   c->stream));
+    else
+        VNS_HIP(c, launch_eval(ea, c->d_eval_wg, c->eval_wg_n, c->stream));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     ChainBestArgs cb{c->d_chains, c->d_cs, c->d_cur_cost, c->d_prod_key, c->d_prod_price, c->d_prod_slot,
                      c->d_best, c->d_best_slot, g0};
@@ -674,12 +690,13 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     if (best) VNS_HIP(c, hipMemcpyAsync(best, c->d_best, sizeof(int64_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
     if (best_slot)
         VNS_HIP(c, hipMemcpyAsync(best_slot, c->d_best_slot, sizeof(int32_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
-    unsigned long long ev[2] = {0, 0};
+    unsigned long long ev[3] = {0, 0, 0};
     VNS_HIP(c, read_counters(c, ev));
     float ms = 0.f;
     VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.last_eval_evals = (int64_t)ev[0];
     c->stats.last_eval_period_steps = (int64_t)ev[1];
+    c->stats.last_eval_decoded_steps = (int64_t)ev[2];
     c->stats.last_eval_ms = ms;
     return VNS_OK;
 }
@@ -1233,7 +1250,7 @@ extern "C" vns_status vns_eval_learned(vns_ctx *c, uint32_t nb, int32_t chain, i
     if (prod_best) VNS_HIP(c, hipMemcpyAsync(prod_best, c->d_prod_price + ci.cp0, sizeof(int64_t) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
     if (prod_best_slot) VNS_HIP(c, hipMemcpyAsync(prod_best_slot, c->d_prod_slot + ci.cp0, sizeof(int32_t) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
     if (fallback) VNS_HIP(c, hipMemcpyAsync(fallback, Fb.p, (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
-    unsigned long long ev[2] = {0, 0};
+    unsigned long long ev[3] = {0, 0, 0};
     VNS_HIP(c, read_counters(c, ev));
     c->stats.last_eval_evals = (int64_t)ev[0];
     c->stats.last_eval_period_steps = (int64_t)ev[0] * ci.T;

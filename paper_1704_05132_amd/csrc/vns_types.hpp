@@ -20,6 +20,8 @@ constexpr int kTMax = 32 * kWords;
 constexpr int kShakeMax = 64;
 constexpr int kMaxWaves = 16;     // wavefronts per search workgroup (8 for the sequential VND, 16 speculative)
 constexpr int kEvalGroup = 16;
+constexpr int kSnapBytes = 24;          // incremental pricing: base state per chain and period (int4 + int2)
+constexpr int kSnapLdsMax = 40 * 1024;  //   and the dynamic LDS a pricing workgroup may use for them
 // Workgroup counters are spread over kCounterSlots slots, kCounterStride words apart (one 64-byte line
 // each): every workgroup adding to one device-scope address serialises the launch on that address.
 constexpr int kCounterSlots = 256;
@@ -169,7 +171,8 @@ struct EvalArgs {
     int64_t *slot_price;         // optional [sum over chains of 4*K*T]
     const int64_t *price_off;    // [G] offset of each chain's slot block in slot_price
     uint64_t *prod_key;          // [sum over chains of K]: cost << 16 | slot of each product's best move
-    unsigned long long *evals;   // device counters, kCounterSlots slots: [0] move-evaluations, [1] their period-steps
+    unsigned long long *evals;   // device counters, kCounterSlots slots: [0] move-evaluations, [1] their period-steps,
+                                 // [2] period-steps decoded
     uint32_t nb_mask;
 };
 

@@ -21,7 +21,7 @@ VNS_OK, VNS_EINVAL, VNS_ENOMEM, VNS_EDEVICE, VNS_ERANGE, VNS_ESTATE = 0, -1, -2,
 NB_FLIP_M, NB_FLIP_R, NB_SHIFT = 1, 2, 4
 OPT_CHAINS, OPT_KMAX, OPT_NB_LIST, OPT_TRACE, OPT_RUN_WAVES, OPT_EVAL_GROUP, OPT_RUN_LDS, OPT_GRAPH = 1, 2, 3, 4, 5, 6, 7, 8
 OPT_LEARNED, OPT_LOG, OPT_SPECULATE, OPT_SPEC_WAVES, OPT_STATE_LDS, OPT_VND_MEMO = 9, 10, 11, 12, 13, 14
-OPT_SPEC_ITERS, OPT_BEST_OF, OPT_BEST_OF_LITERAL = 15, 16, 17
+OPT_SPEC_ITERS, OPT_BEST_OF, OPT_BEST_OF_LITERAL, OPT_EVAL_INCREMENTAL = 15, 16, 17, 18
 MLP_PARAMS, MLP_FEATURES = 5313, 16
 ALL_CHAINS = -1
 PRICE_INF = np.iinfo(np.int64).max
@@ -70,7 +70,7 @@ class VNSStats(ctypes.Structure):
                 ("last_eval_period_steps", ctypes.c_int64), ("last_run_learned_evals", ctypes.c_int64),
                 ("last_run_fallbacks", ctypes.c_int64), ("last_mlp_ms", ctypes.c_double),
                 ("last_mlp_rows", ctypes.c_int64), ("last_run_spec_iters", ctypes.c_int64),
-                ("last_run_discarded_evals", ctypes.c_int64)]
+                ("last_run_discarded_evals", ctypes.c_int64), ("last_eval_decoded_steps", ctypes.c_int64)]
 
 
 class VNSError(RuntimeError):

@@ -37,7 +37,7 @@ def test_binding_covers_the_header():
 def test_record_layout_matches_header():
     from paper_1704_05132_amd import vns
     assert vns.RECORD_DTYPE.itemsize == 40
-    assert ctypes.sizeof(vns.VNSStats) == 112
+    assert ctypes.sizeof(vns.VNSStats) == 120
 
 
 def test_create_error_path_without_device_work():
