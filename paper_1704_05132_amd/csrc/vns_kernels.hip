@@ -81,8 +81,8 @@ struct EvalShared {
     int32_t nswap[kEvalGroup];
     // the workgroup's moves, chain by chain (flips, then zM swaps, then zR swaps): chain << 9 | block << 7 | t
     uint16_t item[kEvalGroup * 4 * kTMax];
-    int32_t next;                 // incremental pricing: the next item of the workgroup's queue
-    int32_t decoded;              //   and the period-steps its lanes decoded
+    int32_t tcount[kTMax];        // incremental pricing: moves per period, then their offsets
+    int32_t decoded;              //   and the period-steps its batches ran, per lane
 };
 static_assert(kEvalGroup <= 16 && kTMax <= 128, "item packing");
 
@@ -113,10 +113,9 @@ __device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, in
 // last manufacturing setup or -1 before the first one), B = (A1, A2)).  Once every changed period is
 // decoded and the moved pattern's state A equals the base's before some period, every later step adds the
 // same amounts to both, so the cost is the base cost plus the setup-count change, -hM (dA1 + dA2) and hR dA1
-// (the forward decode's cost is linear in A1, A2 and the final XR).  A decode that turns infeasible stops there (kInf).  Lanes take items from
-// the workgroup's queue as they finish, so a wave's time follows the total decoded length, not the longest.
+// (the forward decode's cost is linear in A1, A2 and the final XR).  A decode that turns infeasible stops
+// there (kInf).
 __device__ __forceinline__ int32_t enc_last(const DecodeState &s) { return s.nolast ? -1 : s.lastM; }
-constexpr int kIncRefill = 4;   // steps between queue refills (a power of two): fewer refills, some idle lanes
 
 // The base pattern b of one chain, decoded by one lane: its state before every period 0..T.
 template <int NW>
@@ -139,96 +138,79 @@ __device__ __forceinline__ void base_snapshot(const Bits &b, const int2 *row, in
     sb[T] = make_int2(s.A1, s.A2);
 }
 
+// Moves sorted by first changed period, 64 at a time: every lane of a batch starts from the base's state
+// before the batch's first period t0 (a move changes nothing before its own first period, so its decode
+// there equals the base's) and the lanes step through the same periods, reading rows and setup bits at a
+// uniform position as the full decode does.  Every fourth period each lane checks whether it has rejoined
+// the base (or turned infeasible); the batch ends when all have, or at the horizon.
 template <int NW>
 __device__ __forceinline__ void eval_items_inc(const EvalArgs &a, EvalShared &sh, const int4 *snapA, const int2 *snapB,
                                                int N, int T, const ProdParams &pp) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long below = (1ull << lane) - 1ull;
-    // per-lane item state
-    int idx = 0, j = 0, slot = 0, tau = 0, t1 = 0, dnM = 0, dnR = 0, decoded = 0;
-    bool act = false;
-    Bits mb;
-    DecodeState s;
-    auto start = [&](int i) {
-        const int e = sh.item[i];
-        j = e >> 9;
-        const int blk = (e >> 7) & 3, t = e & 127;
-        slot = blk * T + t;
-        mb = sh.bits[j];
-        const bool onm = test_bit(mb.m, t), onr = test_bit(mb.r, t);
-        dnM = blk == 0 ? (onm ? -1 : 1) : 0;   // a swap keeps the number of setups
-        dnR = blk == 1 ? (onr ? -1 : 1) : 0;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int decoded = 0;
+    for (int basei = wave * 64; basei < N; basei += blockDim.x) {
+        const int idx = basei + lane;
+        const bool in = idx < N;
+        const int e = sh.item[in ? idx : basei];
+        const int j = e >> 9, blk = (e >> 7) & 3, t = e & 127;
+        const int slot = blk * T + t;
+        const int t0 = __builtin_amdgcn_readfirstlane(sh.item[basei] & 127);   // sorted: the batch's first period
+        Bits mb = sh.bits[j];
+        const int dnM = blk == 0 ? (test_bit(mb.m, t) ? -1 : 1) : 0;   // a swap keeps the number of setups
+        const int dnR = blk == 1 ? (test_bit(mb.r, t) ? -1 : 1) : 0;
         xor_move<NW>(mb, blk, t);
-        tau = t;
-        t1 = blk >= 2 ? t + 1 : t;                // last changed period
-        const int4 sa = snapA[j * (T + 1) + t];
-        const int2 sb = snapB[j * (T + 1) + t];
-        s.lim = sa.x;
-        s.XR = sa.y;
-        s.lsR = sa.z;
-        s.lastM = sa.w < 0 ? 0 : sa.w;
-        s.nolast = sa.w < 0 ? -1 : 0;
-        s.A1 = sb.x;
-        s.A2 = sb.y;
-        s.bad = 0;
-    };
-    auto take = [&](bool want) {   // lanes with `want` take consecutive items, one queue update per wavefront
-        const unsigned long long need = __ballot(want);
-        if (need) {
-            const int leader = __ffsll((long long)need) - 1;
-            int base = 0;
-            if (lane == leader) base = atomicAdd(&sh.next, __popcll(need));
-            base = __shfl(base, leader, 64);
-            if (want) {
-                idx = base + __popcll(need & below);
-                act = idx < N;
-                if (act) start(idx);
-            }
+        const int t1 = blk >= 2 ? t + 1 : t;                             // last changed period
+        DecodeState s;
+        {
+            const int4 sa = snapA[j * (T + 1) + t0];
+            const int2 sb = snapB[j * (T + 1) + t0];
+            s.lim = sa.x;
+            s.XR = sa.y;
+            s.lsR = sa.z;
+            s.lastM = sa.w < 0 ? 0 : sa.w;
+            s.nolast = sa.w < 0 ? -1 : 0;
+            s.A1 = sb.x;
+            s.A2 = sb.y;
         }
-    };
-    take(true);
-    bool pend = false;   // finished, waiting for the next refill
-    for (int step = 1; __any(act || pend); ++step) {
-        bool fin = false;
+        bool done = !in;
         int64_t c = kInf;
-        if (act) {
-            if (tau == T) {   // decoded to the horizon
-                fin = true;
-                c = decode_finish<NW>(s, mb, T, pp);
-            } else if (tau > t1) {
-                const int4 sa = snapA[j * (T + 1) + tau];
-                if (sa.x == s.lim && sa.y == s.XR && sa.z == s.lsR && sa.w == enc_last(s)) {   // back on the base
-                    const int2 sb = snapB[j * (T + 1) + tau];
-                    const int64_t dA1 = (int64_t)s.A1 - sb.x, dA2 = (int64_t)s.A2 - sb.y;
-                    c = sh.cost[j] + (int64_t)pp.kM * dnM + (int64_t)pp.kR * dnR - (int64_t)pp.hM * (dA1 + dA2) +
-                        (int64_t)pp.hR * dA1;
-                    fin = true;
+        int tau = t0;
+        int2 row = sh.row[t0];
+        for (; tau < T; ++tau) {
+            if (tau > t0 && ((tau - t0) & 3) == 0) {
+                if (!done) {
+                    if (s.bad) {   // infeasible: kInf
+                        done = true;
+                    } else if (tau > t1) {
+                        const int4 sa = snapA[j * (T + 1) + tau];
+                        if (sa.x == s.lim && sa.y == s.XR && sa.z == s.lsR && sa.w == enc_last(s)) {   // rejoined
+                            const int2 sb = snapB[j * (T + 1) + tau];
+                            const int64_t dA1 = (int64_t)s.A1 - sb.x, dA2 = (int64_t)s.A2 - sb.y;
+                            c = sh.cost[j] + (int64_t)pp.kM * dnM + (int64_t)pp.kR * dnR -
+                                (int64_t)pp.hM * (dA1 + dA2) + (int64_t)pp.hR * dA1;
+                            done = true;
+                        }
+                    }
                 }
+                if (!__any(!done)) break;
             }
-            if (!fin) {
-                const int w = tau >> 5;
-                uint32_t m = mb.m[0], r = mb.r[0];
+            const int2 next = sh.row[tau + 1 < T ? tau + 1 : tau];   // the next period's row, read ahead
+            const int w = tau >> 5;
+            uint32_t m = mb.m[0], r = mb.r[0];
 #pragma unroll
-                for (int q = 1; q < NW; ++q) {
-                    m = w == q ? mb.m[q] : m;
-                    r = w == q ? mb.r[q] : r;
-                }
-                decode_step(s, __builtin_amdgcn_sbfe((int32_t)m, tau & 31, 1),
-                            __builtin_amdgcn_sbfe((int32_t)r, tau & 31, 1), tau, sh.row[tau]);
-                ++tau;
-                ++decoded;
-                if (s.bad) fin = true;   // infeasible: kInf, nothing more to decode
+            for (int q = 1; q < NW; ++q) {
+                m = w == q ? mb.m[q] : m;
+                r = w == q ? mb.r[q] : r;
             }
-            if (fin) {
-                if (c != kInf) atomicMin(&sh.key[j], ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
-                if (a.slot_price) a.slot_price[sh.out_off[j] + slot] = c == kInf ? kInf : sh.F[j] - sh.cost[j] + c;
-                act = false;
-                pend = true;
-            }
+            decode_step(s, __builtin_amdgcn_sbfe((int32_t)m, tau & 31, 1), __builtin_amdgcn_sbfe((int32_t)r, tau & 31, 1),
+                        tau, row);
+            row = next;
         }
-        if ((step & (kIncRefill - 1)) == 0 || !__any(act)) {   // refill every kIncRefill steps, or when all wait
-            take(pend);
-            pend = false;
+        if (!done) c = decode_finish<NW>(s, mb, T, pp);   // decoded to the horizon (kInf when infeasible)
+        if (in) {
+            decoded += tau - t0;                           // period-steps this lane's batch ran
+            if (c != kInf) atomicMin(&sh.key[j], ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
+            if (a.slot_price) a.slot_price[sh.out_off[j] + slot] = c == kInf ? kInf : sh.F[j] - sh.cost[j] + c;
         }
     }
     atomicAdd(&sh.decoded, decoded);
@@ -279,9 +261,46 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
         sh.off[n] = o;
     }
     __syncthreads();
-    // the item table: flips (zM then zR), then each chain's valid swaps in period order
+    // the item table: flips (zM then zR), then each chain's valid swaps in period order; for incremental
+    // pricing sorted by period instead (period t: every chain's flips and valid swaps at t)
     const int fblk0 = fm ? 0 : 1;
-    for (int j = wave; j < n; j += nw) {
+    if constexpr (INC) {
+        for (int t = threadIdx.x; t < T; t += blockDim.x) {
+            int cnt = 0;
+            for (int j = 0; j < n; ++j) {
+                const Bits &b = sh.bits[j];
+                cnt += (fm ? 1 : 0) + (fr ? 1 : 0);
+                if (shift && t + 1 < T) {
+                    cnt += test_bit(b.m, t) != test_bit(b.m, t + 1);
+                    cnt += test_bit(b.r, t) != test_bit(b.r, t + 1);
+                }
+            }
+            sh.tcount[t] = cnt;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {   // exclusive prefix over the periods
+            int o = 0;
+            for (int t = 0; t < T; ++t) {
+                const int c = sh.tcount[t];
+                sh.tcount[t] = o;
+                o += c;
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < T; t += blockDim.x) {
+            int o = sh.tcount[t];
+            for (int j = 0; j < n; ++j) {
+                const Bits &b = sh.bits[j];
+                if (fm) sh.item[o++] = pack_item(j, 0, t);
+                if (fr) sh.item[o++] = pack_item(j, 1, t);
+                if (shift && t + 1 < T) {
+                    if (test_bit(b.m, t) != test_bit(b.m, t + 1)) sh.item[o++] = pack_item(j, 2, t);
+                    if (test_bit(b.r, t) != test_bit(b.r, t + 1)) sh.item[o++] = pack_item(j, 3, t);
+                }
+            }
+        }
+    }
+    for (int j = wave; j < n && !INC; j += nw) {
         uint16_t *it = sh.item + sh.off[j];
         for (int i = lane; i < nflip; i += 64) {
             const int blk = fblk0 + (i >= T ? 1 : 0);
@@ -314,10 +333,7 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
             else
                 base_snapshot<4>(sh.bits[j], sh.row, T, snapA + j * (T + 1), snapB + j * (T + 1));
         }
-        if (threadIdx.x == 0) {
-            sh.next = 0;
-            sh.decoded = 0;
-        }
+        if (threadIdx.x == 0) sh.decoded = 0;
         __syncthreads();
         if (T <= 64)
             eval_items_inc<2>(a, sh, snapA, snapB, N, T, pp);
