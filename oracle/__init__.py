@@ -46,10 +46,9 @@ def lib():
             _build.build()
         L = ctypes.CDLL(str(path))
         c = ctypes
-        inst = [_i32p, _i32p, _i32p, _i32p, _i32p, _i32p]
+        inst = [_i32p] * 8   # D, R, kM, kR, hM, hR, pM, pR
         L.orc_decode.restype = c.c_int64
-        L.orc_decode.argtypes = [c.c_int, _i32p, _i32p, c.c_int64, c.c_int64, c.c_int64, c.c_int64,
-                                 _u8p, _u8p, _i64p, _i64p, _i64p, _i64p]
+        L.orc_decode.argtypes = [c.c_int, _i32p, _i32p] + [c.c_int64] * 6 + [_u8p, _u8p, _i64p, _i64p, _i64p, _i64p]
         L.orc_objective.restype = c.c_int64
         L.orc_objective.argtypes = [c.c_int, c.c_int] + inst + [_u8p, _u8p, _i64p]
         L.orc_apply_slot.restype = c.c_int
@@ -87,7 +86,7 @@ def lib():
 
 
 def _inst(inst):
-    return inst.arrays()
+    return inst.arrays() + inst.unit_costs()
 
 
 def _rows(z, K, T):
@@ -95,11 +94,12 @@ def _rows(z, K, T):
     return a
 
 
-def decode(T, D, R, kM, kR, hM, hR, zM, zR):
-    """Decode one product: returns (cost, xM, xR, yM, yR); cost is INF when infeasible."""
+def decode(T, D, R, kM, kR, hM, hR, zM, zR, pM=0, pR=0):
+    """Decode one product: returns (cost, xM, xR, yM, yR); cost is INF when infeasible.  pM, pR: unit costs of
+    a manufactured and a remanufactured item."""
     xM, xR, yM, yR = (np.zeros(T, np.int64) for _ in range(4))
     c = lib().orc_decode(int(T), np.ascontiguousarray(D, np.int32), np.ascontiguousarray(R, np.int32),
-                         int(kM), int(kR), int(hM), int(hR), np.ascontiguousarray(zM, np.uint8),
+                         int(kM), int(kR), int(hM), int(hR), int(pM), int(pR), np.ascontiguousarray(zM, np.uint8),
                          np.ascontiguousarray(zR, np.uint8), xM, xR, yM, yR)
     return int(c), xM, xR, yM, yR
 

@@ -9,7 +9,8 @@
  *
  * Everything is int64.  Bit rows are uint8 0/1 arrays laid out [k][t].  Nothing is blocked, fused or
  * reordered beyond the steps named in each comment:
- *   - problem data and objective: Section 2 of the paper (the decode itself is not printed there; the
+ *   - problem data and objective: Section 2 of the paper, with the unit costs p_M, p_R that Algorithm 1's
+ *     signature carries (zero unless given) (the decode itself is not printed there; the
  *     rules followed are the look-ahead decode of the lot-sizing reading: a setup covers demand until the
  *     next setup of either type, remanufacture first, carry a shortfall back to the last manufacturing lot);
  *   - VND: Algorithm 1 (per-product best move of one neighbourhood at a time, reduction of the gains,
@@ -31,7 +32,7 @@
 /* per-period lots and end-of-period inventories (they may be NULL).                                  */
 /* ------------------------------------------------------------------------------------------------ */
 int64_t orc_decode(int T, const int32_t *D, const int32_t *R,
-                   int64_t kM, int64_t kR, int64_t hM, int64_t hR,
+                   int64_t kM, int64_t kR, int64_t hM, int64_t hR, int64_t pM, int64_t pR,
                    const uint8_t *zM, const uint8_t *zR,
                    int64_t *xM_out, int64_t *xR_out, int64_t *yM_out, int64_t *yR_out)
 {
@@ -79,14 +80,17 @@ int64_t orc_decode(int T, const int32_t *D, const int32_t *R,
     }
 
     if (feasible) {
-        int64_t nM = 0, nR = 0, sYM = 0, sYR = 0;
+        int64_t nM = 0, nR = 0, sYM = 0, sYR = 0, sXM = 0, sXR = 0;
         for (int t = 0; t < T; ++t) {
             nM += zM[t];
             nR += zR[t];
             sYM += yM[t];
             sYR += yR[t];
+            sXM += xM[t];
+            sXR += xR[t];
         }
-        cost = kM * nM + kR * nR + hM * sYM + hR * sYR;
+        /* setups, holding, and the unit costs of the items made (p_M, p_R of Algorithm 1's signature) */
+        cost = kM * nM + kR * nR + hM * sYM + hR * sYR + pM * sXM + pR * sXR;
     }
     for (int t = 0; t < T; ++t) {
         if (xM_out) xM_out[t] = xM[t];
@@ -101,22 +105,24 @@ int64_t orc_decode(int T, const int32_t *D, const int32_t *R,
 /* Cost of product k of an instance laid out [k][t]. */
 static int64_t product_cost(int k, int T, const int32_t *D, const int32_t *R,
                             const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                   const int32_t *pM, const int32_t *pR,
                             const uint8_t *zM, const uint8_t *zR)
 {
     size_t o = (size_t)k * (size_t)T;
-    return orc_decode(T, D + o, R + o, kM[k], kR[k], hM[k], hR[k], zM + o, zR + o,
+    return orc_decode(T, D + o, R + o, kM[k], kR[k], hM[k], hR[k], pM[k], pR[k], zM + o, zR + o,
                       NULL, NULL, NULL, NULL);
 }
 
 /* Objective F = sum of product costs (ORC_INF if any product is infeasible); cost_k may be NULL. */
 int64_t orc_objective(int K, int T, const int32_t *D, const int32_t *R,
                       const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                   const int32_t *pM, const int32_t *pR,
                       const uint8_t *zM, const uint8_t *zR, int64_t *cost_k)
 {
     int64_t F = 0;
     int inf = 0;
     for (int k = 0; k < K; ++k) {
-        int64_t c = product_cost(k, T, D, R, kM, kR, hM, hR, zM, zR);
+        int64_t c = product_cost(k, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR);
         if (cost_k) cost_k[k] = c;
         if (c == ORC_INF) inf = 1; else F += c;
     }
@@ -159,10 +165,11 @@ int orc_apply_slot(int T, uint8_t *zM, uint8_t *zR, int l)
  * Returns the number of move-evaluations (valid slots priced). */
 int64_t orc_price_all(int K, int T, const int32_t *D, const int32_t *R,
                       const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                   const int32_t *pM, const int32_t *pR,
                       const uint8_t *zM, const uint8_t *zR, uint32_t nb_mask, int64_t *price)
 {
     int64_t *cost = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
-    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, zM, zR, cost);
+    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR, cost);
     uint8_t *wM = (uint8_t *)malloc((size_t)T);
     uint8_t *wR = (uint8_t *)malloc((size_t)T);
     int64_t evals = 0;
@@ -176,7 +183,7 @@ int64_t orc_price_all(int K, int T, const int32_t *D, const int32_t *R,
             memcpy(wR, zR + o, (size_t)T);
             if (!orc_apply_slot(T, wM, wR, l)) continue;
             ++evals;
-            int64_t c = orc_decode(T, D + o, R + o, kM[k], kR[k], hM[k], hR[k], wM, wR,
+            int64_t c = orc_decode(T, D + o, R + o, kM[k], kR[k], hM[k], hR[k], pM[k], pR[k], wM, wR,
                                    NULL, NULL, NULL, NULL);
             if (c != ORC_INF && F != ORC_INF) *p = F - cost[k] + c;
         }
@@ -203,10 +210,11 @@ int64_t orc_argmin(int64_t n, const int64_t *price, int64_t *slot)
 /* ------------------------------------------------------------------------------------------------ */
 int64_t orc_vnd(int K, int T, const int32_t *D, const int32_t *R,
                 const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                   const int32_t *pM, const int32_t *pR,
                 uint8_t *zM, uint8_t *zR, const int32_t *nb_list, int n_nb, int64_t *evals)
 {
     int64_t *cost = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
-    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, zM, zR, cost);
+    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR, cost);
     uint8_t *wM = (uint8_t *)malloc((size_t)T);
     uint8_t *wR = (uint8_t *)malloc((size_t)T);
     int improvement;
@@ -224,7 +232,7 @@ int64_t orc_vnd(int K, int T, const int32_t *D, const int32_t *R,
                     memcpy(wR, zR + o, (size_t)T);
                     if (!orc_apply_slot(T, wM, wR, l)) continue;
                     if (evals) ++*evals;
-                    int64_t c = orc_decode(T, D + o, R + o, kM[k], kR[k], hM[k], hR[k], wM, wR,
+                    int64_t c = orc_decode(T, D + o, R + o, kM[k], kR[k], hM[k], hR[k], pM[k], pR[k], wM, wR,
                                            NULL, NULL, NULL, NULL);
                     if (c == ORC_INF) continue;
                     int64_t p = F - cost[k] + c;
@@ -303,6 +311,7 @@ int64_t orc_draw(uint64_t seed, uint64_t chain, uint64_t iter, uint64_t j, uint6
  * Returns the number of flips applied; applied[j] (may be NULL) receives 1/0 per draw. */
 int orc_shake_stream(int K, int T, const int32_t *D, const int32_t *R,
                      const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                   const int32_t *pM, const int32_t *pR,
                      uint8_t *zM, uint8_t *zR, int kshake, uint64_t seed, uint64_t chain, uint64_t iter,
                      uint64_t g, int32_t *applied)
 {
@@ -314,7 +323,7 @@ int orc_shake_stream(int K, int T, const int32_t *D, const int32_t *R,
         flip_move(T, f, &k, &l);
         size_t o = (size_t)k * (size_t)T;
         orc_apply_slot(T, zM + o, zR + o, l);
-        int64_t c = product_cost(k, T, D, R, kM, kR, hM, hR, zM, zR);
+        int64_t c = product_cost(k, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR);
         if (c == ORC_INF) {
             orc_apply_slot(T, zM + o, zR + o, l);   /* undo: a flip is its own inverse */
             if (applied) applied[j] = 0;
@@ -328,10 +337,11 @@ int orc_shake_stream(int K, int T, const int32_t *D, const int32_t *R,
 
 int orc_shake(int K, int T, const int32_t *D, const int32_t *R,
               const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                   const int32_t *pM, const int32_t *pR,
               uint8_t *zM, uint8_t *zR, int kshake, uint64_t seed, uint64_t chain, uint64_t iter,
               int32_t *applied)
 {
-    return orc_shake_stream(K, T, D, R, kM, kR, hM, hR, zM, zR, kshake, seed, chain, iter, 0, applied);
+    return orc_shake_stream(K, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR, kshake, seed, chain, iter, 0, applied);
 }
 
 /* One trajectory record per GVNS iteration. */
@@ -351,6 +361,7 @@ typedef struct {
  * NULL) accumulates move-evaluations. */
 int64_t orc_gvns(int K, int T, const int32_t *D, const int32_t *R,
                  const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                   const int32_t *pM, const int32_t *pR,
                  uint8_t *zM, uint8_t *zR, const int32_t *nb_list, int n_nb, int k_max,
                  uint64_t seed, uint64_t chain, int64_t it0, int64_t iters, int32_t *k_state,
                  int64_t *F_best, orc_record *rec, int64_t *evals)
@@ -358,15 +369,15 @@ int64_t orc_gvns(int K, int T, const int32_t *D, const int32_t *R,
     size_t n = (size_t)K * (size_t)T;
     uint8_t *sM = (uint8_t *)malloc(n);
     uint8_t *sR = (uint8_t *)malloc(n);
-    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, zM, zR, NULL);
+    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR, NULL);
     for (int64_t i = 0; i < iters; ++i) {
         int64_t it = it0 + i;
         int k = *k_state;
         memcpy(sM, zM, n);
         memcpy(sR, zR, n);
-        orc_shake(K, T, D, R, kM, kR, hM, hR, sM, sR, k, seed, chain, (uint64_t)it, NULL);
-        int64_t F_shaken = orc_objective(K, T, D, R, kM, kR, hM, hR, sM, sR, NULL);
-        int64_t F_local = orc_vnd(K, T, D, R, kM, kR, hM, hR, sM, sR, nb_list, n_nb, evals);
+        orc_shake(K, T, D, R, kM, kR, hM, hR, pM, pR, sM, sR, k, seed, chain, (uint64_t)it, NULL);
+        int64_t F_shaken = orc_objective(K, T, D, R, kM, kR, hM, hR, pM, pR, sM, sR, NULL);
+        int64_t F_local = orc_vnd(K, T, D, R, kM, kR, hM, hR, pM, pR, sM, sR, nb_list, n_nb, evals);
         int accepted = F_local < F;
         if (accepted) {
             memcpy(zM, sM, n);
@@ -402,6 +413,7 @@ int64_t orc_gvns(int K, int T, const int32_t *D, const int32_t *R,
  * VNDs) as in orc_gvns. */
 int64_t orc_gvns_best_of(int K, int T, const int32_t *D, const int32_t *R,
                          const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                   const int32_t *pM, const int32_t *pR,
                          uint8_t *zM, uint8_t *zR, const int32_t *nb_list, int n_nb, int k_max, int G,
                          int literal, uint64_t seed, uint64_t chain, int64_t it0, int64_t iters,
                          int32_t *k_state, int64_t *F_best, orc_record *rec, int64_t *evals)
@@ -409,7 +421,7 @@ int64_t orc_gvns_best_of(int K, int T, const int32_t *D, const int32_t *R,
     size_t n = (size_t)K * (size_t)T;
     uint8_t *sM = (uint8_t *)malloc(n), *sR = (uint8_t *)malloc(n);
     uint8_t *bM = (uint8_t *)malloc(n), *bR = (uint8_t *)malloc(n);
-    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, zM, zR, NULL);
+    int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR, NULL);
     for (int64_t i = 0; i < iters; ++i) {
         int64_t it = it0 + i;
         int k = *k_state;
@@ -418,9 +430,9 @@ int64_t orc_gvns_best_of(int K, int T, const int32_t *D, const int32_t *R,
         for (int g = 0; g < G; ++g) {
             memcpy(sM, zM, n);
             memcpy(sR, zR, n);
-            orc_shake_stream(K, T, D, R, kM, kR, hM, hR, sM, sR, k, seed, chain, (uint64_t)it, (uint64_t)g, NULL);
-            int64_t F_shaken = orc_objective(K, T, D, R, kM, kR, hM, hR, sM, sR, NULL);
-            int64_t F_local = orc_vnd(K, T, D, R, kM, kR, hM, hR, sM, sR, nb_list, n_nb, evals);
+            orc_shake_stream(K, T, D, R, kM, kR, hM, hR, pM, pR, sM, sR, k, seed, chain, (uint64_t)it, (uint64_t)g, NULL);
+            int64_t F_shaken = orc_objective(K, T, D, R, kM, kR, hM, hR, pM, pR, sM, sR, NULL);
+            int64_t F_local = orc_vnd(K, T, D, R, kM, kR, hM, hR, pM, pR, sM, sR, nb_list, n_nb, evals);
             if (best_g < 0 || F_local < best_local) {
                 best_g = g;
                 best_local = F_local;

@@ -28,17 +28,30 @@ class Instance:
     hM: np.ndarray  # int32 [K]
     hR: np.ndarray  # int32 [K]
     tag: str = field(default="")
+    pM: np.ndarray = None   # int32 [K] unit cost of a manufactured item (None: 0)
+    pR: np.ndarray = None   # int32 [K] unit cost of a remanufactured item (None: 0)
 
     def arrays(self):
         """(D, R, kM, kR, hM, hR) as C-contiguous int32 arrays."""
         return tuple(np.ascontiguousarray(a, dtype=np.int32)
                      for a in (self.D, self.R, self.kM, self.kR, self.hM, self.hR))
 
+    def unit_costs(self):
+        """(pM, pR) as C-contiguous int32 arrays (zeros when not set)."""
+        z = np.zeros(self.K, np.int32)
+        return (np.ascontiguousarray(self.pM if self.pM is not None else z, dtype=np.int32),
+                np.ascontiguousarray(self.pR if self.pR is not None else z, dtype=np.int32))
+
+    def has_unit_costs(self):
+        return any(a is not None and np.any(np.asarray(a) != 0) for a in (self.pM, self.pR))
+
     def product(self, k: int) -> "Instance":
         """The single-product instance made of product k."""
         sl = slice(k, k + 1)
+        pM, pR = self.unit_costs()
         return Instance(1, self.T, self.D[sl].copy(), self.R[sl].copy(), self.kM[sl].copy(),
-                        self.kR[sl].copy(), self.hM[sl].copy(), self.hR[sl].copy(), f"{self.tag}/p{k}")
+                        self.kR[sl].copy(), self.hM[sl].copy(), self.hR[sl].copy(), f"{self.tag}/p{k}",
+                        pM[sl].copy(), pR[sl].copy())
 
 
 def draw_instance(rng: np.random.Generator, K: int, T: int, ret_lo: float = 0.2, ret_hi: float = 0.8,

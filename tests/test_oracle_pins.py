@@ -369,3 +369,78 @@ def test_philox_matches_numpy(key0, key1, c0, c1):
     nxt = ctr.copy()
     nxt[0] += np.uint64(1)
     assert (oracle.philox4x64_10(key, nxt) == ref).all()
+
+
+# ---- unit costs p_M, p_R (the parameters Algorithm 1's signature carries) ----
+
+def _forward_remanufactured(T, D, R, zM, zR):
+    """Total remanufactured quantity by the forward recurrence of the decode (capacity closed at a
+    manufacturing setup, reopened to all returns so far at a remanufacturing setup), written out here
+    independently of the oracle's look-ahead decode."""
+    lim = XR = PR = 0
+    for t in range(T):
+        PR += int(R[t])
+        if zM[t]:
+            lim = XR
+        if zR[t]:
+            lim = PR
+        XR = min(XR + int(D[t]), lim)
+    return XR
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_unit_costs_of_the_items_made(seed):
+    rng = np.random.default_rng(1000 + seed)
+    inst = draw_instance(rng, 3, 11)
+    checked = 0
+    for _ in range(60):
+        zM = (rng.random((inst.K, inst.T)) < 0.4).astype(np.uint8)
+        zR = (rng.random((inst.K, inst.T)) < 0.4).astype(np.uint8)
+        zM[:, 0] |= rng.random(inst.K) < 0.8
+        for k in range(inst.K):
+            args = (inst.T, inst.D[k], inst.R[k], inst.kM[k], inst.kR[k], inst.hM[k], inst.hR[k], zM[k], zR[k])
+            c0 = oracle.decode(*args)[0]
+            if c0 == INF:
+                assert oracle.decode(*args, pM=5, pR=9)[0] == INF
+                continue
+            sD = int(inst.D[k].sum())
+            p = int(rng.integers(1, 60))
+            assert oracle.decode(*args, pM=p, pR=p)[0] == c0 + p * sD   # every demanded unit is made once
+            pM, pR = (int(v) for v in rng.integers(0, 60, 2))
+            X = _forward_remanufactured(inst.T, inst.D[k], inst.R[k], zM[k], zR[k])
+            assert oracle.decode(*args, pM=pM, pR=pR)[0] == c0 + pM * (sD - X) + pR * X
+            checked += 1
+    assert checked > 20
+
+
+def test_unit_costs_without_returns_shift_the_optimum():
+    """Without returns nothing is remanufactured: p_M adds p_M * sum(D) to every feasible pattern, so the
+    brute-force optimum moves by exactly that and p_R does not matter."""
+    rng = np.random.default_rng(77)
+    inst = draw_instance(rng, 1, 6)
+    inst.R[:] = 0
+    sD = int(inst.D[0].sum())
+    best0 = best1 = INF
+    for bits in range(1 << (2 * inst.T)):
+        zM = _rows(bits, inst.T)
+        zR = _rows(bits >> inst.T, inst.T)
+        args = (inst.T, inst.D[0], inst.R[0], inst.kM[0], inst.kR[0], inst.hM[0], inst.hR[0], zM, zR)
+        best0 = min(best0, oracle.decode(*args)[0])
+        best1 = min(best1, oracle.decode(*args, pM=13, pR=999)[0])
+    assert best1 == best0 + 13 * sD
+
+
+def test_unit_costs_in_the_search():
+    """The instance's unit costs reach every part of the search: the objective of the final solution, the
+    VND's local optimum and the GVNS records use them."""
+    inst = draw_instance(np.random.default_rng(5), 6, 10)
+    inst.pM = np.full(inst.K, 40, np.int32)
+    inst.pR = np.full(inst.K, 3, np.int32)   # cheap remanufacturing: the optimum keeps more zR setups
+    ch = oracle.Chain(inst, 1, 0)
+    rec = ch.run(30)
+    assert ch.F == oracle.objective(inst, ch.zM, ch.zR)[0]
+    assert rec["F_best"][-1] == ch.F_best
+    price, _ = oracle.price_all(inst, ch.zM, ch.zR, 7)
+    assert price.min() >= ch.F
+    plain = draw_instance(np.random.default_rng(5), 6, 10)
+    assert oracle.objective(inst, ch.zM, ch.zR)[0] != oracle.objective(plain, ch.zM, ch.zR)[0]
