@@ -189,6 +189,16 @@ vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const int32_t *T, 
 /* vns_destroy — frees every device and host resource of the context; NULL is accepted. */
 void vns_destroy(vns_ctx *ctx);
 
+/*
+ * vns_set_unit_costs — unit costs of a manufactured item (pM) and of a remanufactured item (pR) per product,
+ * the p_M, p_R of Algorithm 1's signature: the objective adds pM * sum x_M + pR * sum x_R (every demanded item
+ * is made once, so this is pM * (sum D - X) + pR * X with X the remanufactured total).  pM, pR: [sum of K over
+ * the instances] int32 in [0, 2^16), products in instance order, host memory, copied.  Zero at creation.
+ * Every chain keeps its solution; its costs are recomputed and its search state restarts as at creation
+ * (F = best = the new objective, k = 1).  VNS_ERANGE if a product's worst-case cost would reach 2^47.
+ */
+vns_status vns_set_unit_costs(vns_ctx *ctx, const int32_t *pM, const int32_t *pR);
+
 /* vns_set_option / vns_get_option — see enum vns_option.  VNS_EINVAL for an unknown key or a value out of
  * range. */
 vns_status vns_set_option(vns_ctx *ctx, int32_t key, int64_t value);

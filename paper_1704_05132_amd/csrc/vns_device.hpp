@@ -101,8 +101,10 @@ __device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bit
         nM += __popc(b.m[j]);
         nR += __popc(b.r[j]);
     }
+    // unit costs: every demanded item is made once, XR of them remanufactured
     return (int64_t)pp.kM * nM + (int64_t)pp.kR * nR + (int64_t)pp.hM * (pp.S_tD - (int64_t)s.A1 - (int64_t)s.A2) +
-           (int64_t)pp.hR * (pp.S_PR - (int64_t)T * s.XR + (int64_t)s.A1);
+           (int64_t)pp.hR * (pp.S_PR - (int64_t)T * s.XR + (int64_t)s.A1) + (int64_t)pp.pM * (pp.SD - (int64_t)s.XR) +
+           (int64_t)pp.pR * s.XR;
 }
 
 template <class RowPtr>

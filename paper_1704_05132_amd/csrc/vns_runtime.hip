@@ -43,6 +43,8 @@ struct vns_ctx {
     int32_t n_inst = 0;
     std::vector<int32_t> K, T, prod0;
     std::vector<int32_t> prod_row;        // row offset of every product (as in the device product table)
+    std::vector<ProdParams> prod_host;    // the device product table
+    std::vector<int64_t> cost_bound;      // each product's worst-case cost without unit costs (< 2^47)
     int64_t n_prod = 0;
     uint64_t seed = 0;
     int device = 0;
@@ -326,6 +328,7 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
 
     std::vector<int2> rows((size_t)n_rows);
     std::vector<ProdParams> prod((size_t)n_prod);
+    std::vector<int64_t> bounds((size_t)n_prod);   // worst-case cost of each product without unit costs
     std::vector<int32_t> prod0((size_t)n_inst);
     int64_t p = 0, r = 0;
     for (int32_t i = 0; i < n_inst; ++i) {
@@ -364,6 +367,9 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
             pp.S_PR = S_PR;
             pp.T = Ti;
             pp.row = (int32_t)r;
+            pp.pM = pp.pR = 0;
+            pp.SD = sumD;
+            bounds[(size_t)p] = (int64_t)bound;
             r += Ti;
         }
         if (F_bound >= ((__int128)1 << 62)) return fail(nullptr, VNS_ERANGE, "an instance's objective could reach 2^62");
@@ -378,6 +384,8 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
     c->n_prod = n_prod;
     c->prod_row.resize((size_t)n_prod);
     for (int64_t q = 0; q < n_prod; ++q) c->prod_row[(size_t)q] = prod[(size_t)q].row;
+    c->prod_host = prod;
+    c->cost_bound = bounds;
     c->seed = seed;
     vns_status st = VNS_OK;
     auto bail = [&](vns_status s) {
@@ -927,6 +935,34 @@ extern "C" vns_status vns_get_solution(vns_ctx *c, int32_t chain, uint8_t *zM, u
             zM[(size_t)k * ci.T + t] = (uint8_t)((b[(size_t)k].m[t >> 5] >> (t & 31)) & 1u);
             zR[(size_t)k * ci.T + t] = (uint8_t)((b[(size_t)k].r[t >> 5] >> (t & 31)) & 1u);
         }
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_set_unit_costs(vns_ctx *c, const int32_t *pM, const int32_t *pR) {
+    VNS_LIVE(c);
+    if (!pM || !pR) return fail(c, VNS_EINVAL, "NULL input");
+    std::vector<ProdParams> prod = c->prod_host;
+    size_t p = 0;
+    for (int32_t i = 0; i < c->n_inst; ++i) {
+        __int128 F_bound = 0;
+        for (int32_t k = 0; k < c->K[(size_t)i]; ++k, ++p) {
+            if (pM[p] < 0 || pR[p] < 0 || pM[p] >= (1 << 16) || pR[p] >= (1 << 16))
+                return fail(c, VNS_EINVAL, "unit costs must be in [0, 2^16)");
+            const __int128 bound = (__int128)c->cost_bound[p] + (__int128)std::max(pM[p], pR[p]) * prod[p].SD;
+            if (bound >= ((__int128)1 << 47)) return fail(c, VNS_ERANGE, "a product's cost could reach 2^47");
+            F_bound += bound;
+            prod[p].pM = pM[p];
+            prod[p].pR = pR[p];
+        }
+        if (F_bound >= ((__int128)1 << 62)) return fail(c, VNS_ERANGE, "an instance's objective could reach 2^62");
+    }
+    drop_graph(c);
+    VNS_HIP(c, hipMemcpyAsync(c->d_prod, prod.data(), sizeof(ProdParams) * prod.size(), hipMemcpyHostToDevice, c->stream));
+    // every chain's costs from its current solution, as at creation: F = best = the new objective, k = 1
+    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs, 0};
+    VNS_HIP(c, launch_init(ia, (int)c->chains.size(), c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    c->prod_host = prod;
     return VNS_OK;
 }
 

@@ -44,6 +44,8 @@ struct ProdParams {
     int64_t S_PR;   // sum_t PR(t)
     int32_t T;
     int32_t row;    // offset of the product's first period in rows
+    int32_t pM, pR; // unit costs of a manufactured and a remanufactured item (0 unless set)
+    int64_t SD;     // sum_t D(t): the items made, sum x_M + sum x_R
 };
 
 struct ChainInfo {

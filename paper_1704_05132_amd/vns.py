@@ -38,6 +38,7 @@ SIGNATURES = {
     "vns_create_batch": (_c.c_int, [_c.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _c.c_uint64, _c.POINTER(_P)]),
     "vns_destroy": (None, [_P]),
     "vns_set_option": (_c.c_int, [_P, _c.c_int32, _c.c_int64]),
+    "vns_set_unit_costs": (_c.c_int, [_P, _P, _P]),
     "vns_get_option": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int64)]),
     "vns_bind_stream": (_c.c_int, [_P, _P]),
     "vns_eval_neighbourhood": (_c.c_int, [_P, _c.c_uint32, _c.c_int32, _P, _P, _P, _P, _P]),
@@ -146,6 +147,9 @@ class Context:
         for key, val in (options or {}).items():
             self.set_option(key, val)
         self.chains_per_inst = int(chains)
+        if any(i.has_unit_costs() for i in insts):
+            u = [i.unit_costs() for i in insts]
+            self.set_unit_costs(np.concatenate([a for a, _ in u]), np.concatenate([b for _, b in u]))
 
     # -- plumbing ------------------------------------------------------------------------------------
     def _check(self, st):
@@ -168,6 +172,12 @@ class Context:
 
     def __exit__(self, *a):
         self.close()
+
+    def set_unit_costs(self, pM, pR):
+        """Unit costs of a manufactured / remanufactured item per product (all instances, in order)."""
+        a = np.ascontiguousarray(pM, np.int32)
+        b = np.ascontiguousarray(pR, np.int32)
+        self._check(lib().vns_set_unit_costs(self.h, _ptr(a), _ptr(b)))
 
     def set_option(self, key, value):
         self._check(lib().vns_set_option(self.h, int(key), int(value)))
