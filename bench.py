@@ -87,6 +87,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--print-source-hash", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain time-to-best half")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the side measurements (neighbourhood skip, best-of-G, incremental sweep), so that the "
+                         "timed search launch is the only one of its kernel (for a profiler's per-kernel average)")
     ap.add_argument("--chunk", type=int, default=50, help="iterations per launch in the time-to-best runs")
     ap.add_argument("--learned-permille", type=int, default=100, help="share of moves priced exactly (1/1000)")
     ap.add_argument("--learned-train-instances", type=int, default=16)
@@ -382,7 +385,7 @@ def main():
 
     # --- the same search with neighbourhoods not re-priced on an unchanged pattern (same moves applied) ---
     memo = None
-    if name != "learned_batched_1024":
+    if name != "learned_batched_1024" and not args.no_extras:
         with vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=False,
                          options={vns.OPT_VND_MEMO: 1}) as mctx:
             mctx.bind_stream(stream)
@@ -399,7 +402,7 @@ def main():
     # --- the best-of-G search of Algorithm 2 (G shakes of x per iteration, the minimum kept), GVNS form and as
     #     printed, on the same chains and iterations ---
     best_of = None
-    if name == "plain_100x52":
+    if name == "plain_100x52" and not args.no_extras:
         best_of = {"G": BEST_OF_G, "plain_best_F": int(min(b for b, _ in bests))}
         for variant, literal in (("gvns", 0), ("literal", 1)):
             with vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=False,
@@ -436,14 +439,15 @@ def main():
     sweep_med = statistics.median(sweep_ms)
     # the same sweeps priced incrementally (each move decoded only until it rejoins the current pattern)
     inc_ms, inc_dec = [], 0
-    ctx.set_option(vns.OPT_EVAL_INCREMENTAL, 1)
-    for _ in range(args.sweep_reps):
-        ctx.eval_neighbourhood(7, vns.ALL_CHAINS, slot_prices=False)
-        s = ctx.stats()
-        inc_ms.append(s["last_eval_ms"])
-        inc_dec = s["last_eval_decoded_steps"]
-    ctx.set_option(vns.OPT_EVAL_INCREMENTAL, 0)
-    inc_med = statistics.median(inc_ms)
+    if not args.no_extras:
+        ctx.set_option(vns.OPT_EVAL_INCREMENTAL, 1)
+        for _ in range(args.sweep_reps):
+            ctx.eval_neighbourhood(7, vns.ALL_CHAINS, slot_prices=False)
+            s = ctx.stats()
+            inc_ms.append(s["last_eval_ms"])
+            inc_dec = s["last_eval_decoded_steps"]
+        ctx.set_option(vns.OPT_EVAL_INCREMENTAL, 0)
+    inc_med = statistics.median(inc_ms) if inc_ms else None
 
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -500,7 +504,7 @@ def main():
         "sweep": {"kernel": "k_eval", "move_evals": sweep_ev, "median_ms": sweep_med,
                   "value": sweep_ev / (sweep_med / 1e3), "unit": "move-evals/s", "achieved": sweep_achieved,
                   "peak": peak, "frac": sweep_achieved / peak, "traffic": measured_traffic("k_eval", name)},
-        "sweep_incremental": {"kernel": "k_eval_inc", "move_evals": sweep_ev, "median_ms": inc_med,
+        "sweep_incremental": None if inc_med is None else {"kernel": "k_eval_inc", "move_evals": sweep_ev, "median_ms": inc_med,
                               "value": sweep_ev / (inc_med / 1e3), "unit": "move-evals/s",
                               "speedup_vs_full_decode": sweep_med / inc_med,
                               "decoded_period_steps": inc_dec, "full_decode_period_steps": sweep_steps,
