@@ -101,10 +101,10 @@ __device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bit
         nM += __popc(b.m[j]);
         nR += __popc(b.r[j]);
     }
-    // unit costs: every demanded item is made once, XR of them remanufactured
-    return (int64_t)pp.kM * nM + (int64_t)pp.kR * nR + (int64_t)pp.hM * (pp.S_tD - (int64_t)s.A1 - (int64_t)s.A2) +
-           (int64_t)pp.hR * (pp.S_PR - (int64_t)T * s.XR + (int64_t)s.A1) + (int64_t)pp.pM * (pp.SD - (int64_t)s.XR) +
-           (int64_t)pp.pR * s.XR;
+    // kM nM + kR nR + hM (S_tD - A1 - A2) + hR (S_PR - T XR + A1) + pM (SD - XR) + pR XR, the constant and
+    // the XR terms folded into C and cXR (every demanded item is made once, XR of them remanufactured)
+    return (int64_t)pp.kM * nM + (int64_t)pp.kR * nR - (int64_t)pp.hM * ((int64_t)s.A1 + (int64_t)s.A2) +
+           (int64_t)pp.hR * s.A1 + pp.cXR * s.XR + pp.C;
 }
 
 template <class RowPtr>

@@ -438,6 +438,8 @@ struct RunShared {
     int32_t coop_stop;
     int32_t coop_acc;
     int32_t coop_abort;
+    int64_t nbr[kMaxWaves];   // a round's learned counters per wavefront
+    int64_t fbr[kMaxWaves];
 };
 
 // Bounded wait until *p >= v, false if the wait ran out (after `ticks` of the steady clock, or
@@ -481,7 +483,7 @@ struct SpecShared {
 template <bool SPEC, bool LEARNED, bool COOP = false>
 __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecShared &sp, int2 *s_rows) {
     static_assert(!(SPEC && LEARNED), "the speculative VND prices whole neighbourhoods");
-    static_assert(!(COOP && (SPEC || LEARNED)), "speculative iterations run the plain sequential VND");
+    static_assert(!(COOP && SPEC), "speculative iterations run the sequential VND");
     int g = blockIdx.x, slot = 0;   // chain, and (speculative iterations) the iteration of a round it computes
     if constexpr (COOP) {
         const int m = a.coop_m;
@@ -559,7 +561,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         int active = 1;           // iterations computed in this round
         bool split = false;       // one iteration whose products are shared out over the chain's workgroups
         int vfirst = wave, vstep = W;   // this wavefront's products in the VND loop
-        const int64_t ev_round = evals;
+        const int64_t ev_round = evals, nb_round = nb_evals, fb_round = fallbacks;
         if constexpr (COOP) {
             // the chain's state as the leader left it (acquired at the end of the previous round)
             if (threadIdx.x == 0) {
@@ -875,6 +877,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             if constexpr (COOP) {
                 sh.ev[wave] = evals - ev_round;
                 sh.verr[wave] = vnd_err;
+                sh.nbr[wave] = nb_evals - nb_round;
+                sh.fbr[wave] = fallbacks - fb_round;
             }
         }
         __syncthreads();
@@ -883,17 +887,21 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             CoopCtl *ctl = a.coop_ctl + g;
             CoopSlot *mine = a.coop_slot + (int64_t)g * a.coop_m + slot;
             if (go && threadIdx.x == 0) {   // this iteration's summary
-                int64_t delta = 0, dshake = 0, ev = 0;
+                int64_t delta = 0, dshake = 0, ev = 0, nbe = 0, fbe = 0;
                 int err = 0;
                 for (int w = 0; w < W; ++w) {
                     delta += sh.part[w];
                     dshake += sh.shk[w];
                     ev += sh.ev[w];
                     err |= sh.verr[w];
+                    nbe += sh.nbr[w];
+                    fbe += sh.fbr[w];
                 }
                 mine->F_local = cs.F + delta;
                 mine->F_shaken = cs.F + dshake;
                 mine->evals = ev;
+                mine->nb_evals = nbe;
+                mine->fallbacks = fbe;
                 mine->err = err;
                 mine->n_touch = cs.lopt ? nd : -1;   // -1: every product
                 for (int q = 0; q < nd; ++q) mine->dp[q] = sh.dp[q];
@@ -914,6 +922,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     const bool ok = __shfl(okl, 0, 64) != 0;
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                     int64_t dl = 0, ds = 0, le = 0;   // lane j: slot j's F_local - F, F_shaken - F, evaluations
+                    int64_t lnb = 0, lfb = 0;          //   and its learned counters
                     int lerr = 0;
                     if (ok && lane < a.coop_m) {
                         const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + lane;
@@ -921,11 +930,15 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         ds = sj->F_shaken - cs.F;
                         le = sj->evals;
                         lerr = sj->err;
+                        lnb = sj->nb_evals;
+                        lfb = sj->fallbacks;
                     }
                     if (split) {   // the one iteration is the sum of every slot's share
                         dl = wave_sum_i64(dl);
                         ds = wave_sum_i64(ds);
                         le = wave_sum_i64(le);
+                        lnb = wave_sum_i64(lnb);
+                        lfb = wave_sum_i64(lfb);
                         lerr = __any(lerr != 0) ? 1 : 0;
                     }
                     int sel = 0;   // best-of-G: the stream whose result is kept
@@ -940,14 +953,18 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         dl = __shfl(dl, sel, 64);
                         ds = __shfl(ds, sel, 64);
                         le = wave_sum_i64(le);
+                        lnb = wave_sum_i64(lnb);
+                        lfb = wave_sum_i64(lfb);
                         lerr = __any(lerr != 0) ? 1 : 0;
                     }
                     const bool literal = a.best_of && a.best_literal;   // k fixed, the minimum always kept
                     int acc = -1, consumed = active, k = cs.k, err = ok ? 0 : 2;
-                    int64_t F = cs.F, Fb = cs.F_best, ev = 0, thrown = 0;
+                    int64_t F = cs.F, Fb = cs.F_best, ev = 0, thrown = 0, nbe = 0, fbe = 0;
                     for (int j = 0; j < active && ok; ++j) {
                         const int64_t Fl = cs.F + __shfl(dl, j, 64), Fs = cs.F + __shfl(ds, j, 64);
                         ev += __shfl(le, j, 64);
+                        nbe += __shfl(lnb, j, 64);
+                        fbe += __shfl(lfb, j, 64);
                         err |= __shfl(lerr, j, 64);
                         const int accepted = literal ? 1 : Fl < F;
                         if (a.trace && lane == 0) {
@@ -984,6 +1001,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                             ctl->iters_done = done_it + consumed;
                             ctl->evals += ev;
                             ctl->discarded += thrown;
+                            ctl->nb_evals += nbe;
+                            ctl->fallbacks += fbe;
                         }
                         if (err) atomicOr(&ctl->err, err);
                     }
@@ -1073,8 +1092,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 cs.evals = a.coop_ctl[g].evals;
                 cs.discarded = a.coop_ctl[g].discarded;
                 cs.err |= a.coop_ctl[g].err;
-                cs.nb_evals = 0;
-                cs.fallbacks = 0;
+                cs.nb_evals = a.coop_ctl[g].nb_evals;
+                cs.fallbacks = a.coop_ctl[g].fallbacks;
                 a.cstate[g] = cs;
             }
         }
@@ -1139,6 +1158,14 @@ __global__ __launch_bounds__(512) void k_run_coop(RunArgs a) {
 }
 
 // learned VND: the scorer's weight fragments stay in registers for the whole launch
+// speculative iterations of the learned search
+__global__ __launch_bounds__(512) void k_run_learned_coop(RunArgs a) {
+    __shared__ RunShared sh;
+    __shared__ SpecShared sp;
+    extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
+    run_chain<false, true, true>(a, sh, sp, s_rows);
+}
+
 __global__ __launch_bounds__(512) void k_run_learned(RunArgs a) {
     __shared__ RunShared sh;
     __shared__ SpecShared sp;
@@ -1234,14 +1261,17 @@ hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_byt
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes);
 }
 
-hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits) {
+static const void *coop_kernel(bool learned) {
+    return learned ? reinterpret_cast<const void *>(&k_run_learned_coop) : reinterpret_cast<const void *>(&k_run_coop);
+}
+
+hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bool learned) {
     *fits = false;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_run_coop),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const void *fn = coop_kernel(learned);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     int per_cu = 0, dev = 0, cus = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_run_coop), 64 * waves,
-                                                     lds_bytes);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * waves, lds_bytes);
     if (e != hipSuccess) return e;
     e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
@@ -1252,11 +1282,11 @@ hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits) {
 }
 
 hipError_t launch_run_coop(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
-                           hipStream_t s) {
+                           hipStream_t s, bool learned) {
     if (n_chains <= 0 || a.iters <= 0) return hipSuccess;
     RunArgs args = a;
     void *params[] = {&args};
-    hipError_t e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_run_coop),
+    hipError_t e = hipLaunchCooperativeKernel(coop_kernel(learned),
                                               dim3((unsigned)(n_chains * a.coop_m)), dim3(64 * waves), params,
                                               (unsigned)lds_bytes, s);
     if (e != hipSuccess) return e;

@@ -74,10 +74,10 @@ hipError_t launch_eval_inc(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, si
 hipError_t launch_chain_best(const ChainBestArgs &a, int n_chains, hipStream_t s);
 // Speculative iterations (a.coop_m workgroups per chain, cooperative launch): whether blocks workgroups of
 // `waves` wavefronts and lds_bytes of dynamic LDS are all resident at once, and the launch itself (then the
-// device iteration counter advances by a.iters).
-hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits);
+// device iteration counter advances by a.iters).  learned: the learned search's kernel.
+hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bool learned);
 hipError_t launch_run_coop(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
-                           hipStream_t s);
+                           hipStream_t s, bool learned);
 // The search kernel variant `kind` over n_chains workgroups, then the device iteration counter advances by a.iters (two kernels on s;
 // both can be captured in a graph).
 hipError_t launch_run(const RunArgs &a, RunKind kind, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,

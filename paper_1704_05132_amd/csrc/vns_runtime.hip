@@ -369,6 +369,7 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
             pp.row = (int32_t)r;
             pp.pM = pp.pR = 0;
             pp.SD = sumD;
+            set_cost_terms(pp);
             bounds[(size_t)p] = (int64_t)bound;
             r += Ti;
         }
@@ -788,17 +789,19 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     const bool best = c->best_of >= 2 || c->best_literal;
     const int m = best ? std::max<int>(c->best_of, 1) : c->spec_iters;
     bool coop = false;
-    const size_t lds_coop = rows_bytes;   // x stays in device memory: no state region
+    // x stays in device memory: no state region; the learned search keeps its per-wavefront tiles
+    const size_t lds_coop = rows_bytes + (size_t)learned;
+    const bool coop_learned = kind == RunKind::kLearned;
     if (best) {
         if (kind != RunKind::kPlain || c->use_graph || ra.log_x != nullptr || c->spec_iters > 1)
             return fail(c, VNS_EINVAL, "best-of-G runs the plain search alone: no learned scorer, speculative VND or "
                                        "iterations, move log or graph capture");
-        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop));
+        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, false));
         if (!coop)
             return fail(c, VNS_EINVAL, "best-of-G needs its G workgroups per chain resident at once: use fewer "
                                        "chains, wavefronts per workgroup or streams");
-    } else if (m > 1 && kind == RunKind::kPlain && !c->use_graph && ra.log_x == nullptr) {
-        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop));
+    } else if (m > 1 && kind != RunKind::kSpec && !c->use_graph && ra.log_x == nullptr) {
+        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, coop_learned));
     }
     c->stats.last_run_spec_iters = coop && !best ? m : 1;
     if (coop) {
@@ -836,7 +839,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         ra.best_of = best ? 1 : 0;
         ra.best_literal = c->best_literal;
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-        VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream));
+        VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream, coop_learned));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     } else if (c->use_graph) {
         const int64_t key[5] = {iters, G, waves * 4 + (int64_t)kind, (int64_t)lds, (int64_t)(intptr_t)ra.trace};
@@ -953,6 +956,7 @@ extern "C" vns_status vns_set_unit_costs(vns_ctx *c, const int32_t *pM, const in
             F_bound += bound;
             prod[p].pM = pM[p];
             prod[p].pR = pR[p];
+            set_cost_terms(prod[p]);
         }
         if (F_bound >= ((__int128)1 << 62)) return fail(c, VNS_ERANGE, "an instance's objective could reach 2^62");
     }

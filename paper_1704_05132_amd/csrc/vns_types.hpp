@@ -40,13 +40,22 @@ struct Bits {
 
 struct ProdParams {
     int32_t kM, kR, hM, hR;
-    int64_t S_tD;   // sum_t t * D(t)
-    int64_t S_PR;   // sum_t PR(t)
+    // the cost's constant part and the coefficient of the remanufactured total XR (the decode reads these):
+    //   C = hM * S_tD + hR * S_PR + pM * SD,  cXR = pR - pM - hR * T
+    int64_t C;
+    int64_t cXR;
     int32_t T;
     int32_t row;    // offset of the product's first period in rows
-    int32_t pM, pR; // unit costs of a manufactured and a remanufactured item (0 unless set)
+    int64_t S_tD;   // sum_t t * D(t)
+    int64_t S_PR;   // sum_t PR(t)
     int64_t SD;     // sum_t D(t): the items made, sum x_M + sum x_R
+    int32_t pM, pR; // unit costs of a manufactured and a remanufactured item (0 unless set)
 };
+// The two derived fields of a product.
+inline void set_cost_terms(ProdParams &pp) {
+    pp.C = (int64_t)pp.hM * pp.S_tD + (int64_t)pp.hR * pp.S_PR + (int64_t)pp.pM * pp.SD;
+    pp.cXR = (int64_t)pp.pR - pp.pM - (int64_t)pp.hR * pp.T;
+}
 
 struct ChainInfo {
     int32_t inst;
@@ -126,11 +135,14 @@ struct alignas(128) CoopCtl {   // one cache line per chain
     int64_t iters_done;   // iterations of this launch resolved so far
     int64_t evals;        // move-evaluations of the resolved iterations
     int64_t discarded;    //   and of the iterations computed after an accepted one, thrown away
+    int64_t nb_evals;     // learned search: neighbourhood evaluations of the resolved iterations
+    int64_t fallbacks;    //   and how many of them priced the whole neighbourhood
     int32_t abort;        // a bounded wait ran out: every workgroup of the chain leaves
     int32_t err;
 };
 struct CoopSlot {
     int64_t F_local, F_shaken, evals;
+    int64_t nb_evals, fallbacks;   // learned search: the iteration's neighbourhood evaluations and fallbacks
     int32_t n_touch;      // products in dp (K = every product: the VND of a state not yet a local optimum)
     int32_t err;
     int32_t dp[kShakeMax];

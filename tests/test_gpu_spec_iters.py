@@ -3,9 +3,9 @@
 A rejected iteration leaves x unchanged, so iterations i+1..i+m-1 can be computed beside iteration i as if
 it were rejected; what follows the first accepted one is thrown away (Section 3, the shake-VND-move-or-not
 loop).  The search must not notice: every record, solution and counted move-evaluation equals the
-one-workgroup search's, and sampled chains equal the oracle.  A run that cannot use the cooperative launch
-(learned scorer, move log, graph capture, too many workgroups to be resident) falls back to one workgroup
-per chain and says so in its statistics.
+one-workgroup search's, and sampled chains equal the oracle; for the learned search the neighbourhood and
+fallback counts too.  A run that cannot use the cooperative launch (move log, graph capture, too many
+workgroups to be resident) falls back to one workgroup per chain and says so in its statistics.
 """
 import sys
 
@@ -98,7 +98,7 @@ def test_speculative_iterations_headline_shape(vns):
         same_search(ctx, ref, 64)
 
 
-@pytest.mark.parametrize("case", ["log", "graph", "learned", "too_many"])
+@pytest.mark.parametrize("case", ["log", "graph", "too_many"])
 def test_speculative_iterations_fall_back(vns, case):
     insts = [workload("batched_4096", i) for i in range(4)]
     chains, opts = 2, {vns.OPT_SPEC_ITERS: 4}
@@ -106,17 +106,12 @@ def test_speculative_iterations_fall_back(vns, case):
         opts[vns.OPT_LOG] = 4096
     elif case == "graph":
         opts[vns.OPT_GRAPH] = 1
-    elif case == "learned":
-        opts[vns.OPT_LEARNED] = 100
     else:   # more workgroups than the device holds at once
         insts, chains = [workload("batched_4096", i) for i in range(1024)], 8
     say(f"  spec_iters fallback: {case}")
     base = {k: v for k, v in opts.items() if k != vns.OPT_SPEC_ITERS}
     with vns.Context(insts, seed=5, chains=chains, options=base) as ref, \
             vns.Context(insts, seed=5, chains=chains, options=opts) as ctx:
-        if case == "learned":
-            ctx.mlp_init(9)
-            ref.mlp_init(9)
         ref.run(6)
         ctx.run(6)
         assert ctx.stats()["last_run_spec_iters"] == 1
@@ -154,3 +149,26 @@ def test_speculative_iterations_edge_instances(vns, kind, K, T, kmax):
         for g in (0, 3):
             rr = oracle.Chain(inst, 5, g, (1, 2, 4), k_max=kmax).run(iters)
             assert (ctx.trajectory(g) == rr).all(), g
+
+
+@pytest.mark.parametrize("m", [2, 4, 8])
+def test_speculative_iterations_learned_search(vns, m):
+    """The learned search (scorer-ranked selection, exact pricing, fallback) with m iterations side by side
+    equals the one-workgroup learned search: records, solutions, costs, and the evaluation, neighbourhood
+    and fallback counts."""
+    inst = workload("plain_100x52")
+    chains, iters = 8, 40
+    say(f"  learned search, spec_iters m={m}, 100x52 x {chains} chains")
+    base = {vns.OPT_LEARNED: 100, vns.OPT_RUN_WAVES: 4}
+    with vns.Context(inst, seed=2, chains=chains, options=base) as ref, \
+            vns.Context(inst, seed=2, chains=chains, options={**base, vns.OPT_SPEC_ITERS: m}) as ctx:
+        for c in (ref, ctx):
+            c.mlp_init(21)
+        for n in (1, iters):
+            ref.run(n)
+            ctx.run(n)
+            st, rst = ctx.stats(), ref.stats()
+            assert st["last_run_spec_iters"] == m and rst["last_run_spec_iters"] == 1
+            same_search(ctx, ref, chains)
+            for key in ("last_run_learned_evals", "last_run_fallbacks"):
+                assert st[key] == rst[key], key
