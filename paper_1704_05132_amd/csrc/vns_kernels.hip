@@ -435,12 +435,21 @@ struct RunShared {
     // workgroup decides alike), the round's accepted slot (-1: none) and abort flag
     ChainState coop_cs;
     int64_t coop_done_it;
+    int32_t coop_round;   // the round this workgroup computes
+    int32_t next_prod;    // VND: the next product index to hand to a wavefront that has finished its own
     int32_t coop_stop;
     int32_t coop_acc;
     int32_t coop_abort;
     int64_t nbr[kMaxWaves];   // a round's learned counters per wavefront
     int64_t fbr[kMaxWaves];
 };
+
+// The next VND product index of a wavefront: one LDS add by lane 0, the value in lane 0.
+__device__ __forceinline__ int next_index(int32_t &counter, int lane) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(&counter, 1);
+    return __shfl(v, 0, 64);
+}
 
 // Bounded wait until *p >= v, false if the wait ran out (after `ticks` of the steady clock, or
 // kCoopSpinLimit polls).  The polls are relaxed (an acquire per poll would invalidate the caches the other
@@ -552,8 +561,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     if constexpr (LEARNED) mlp::load_frags(a.mlp, fr);
     const uint64_t nflip_all = 2ull * (uint64_t)K * (uint64_t)T;
 
-    int32_t coop_round = 0;   // rounds this workgroup has seen completed
-    int64_t done_it = 0;      // speculative iterations: iterations resolved before this round
+    int32_t coop_round = 0;   // speculative iterations: the round this workgroup computes
+    int64_t done_it = 0;      //   and the iterations resolved before it
+    int64_t executed = 0;     //   move-evaluations this workgroup computed (thread 0)
     for (int i = 0; COOP || i < a.iters; ++i) {
         int64_t it = it_first + i;
         int kshake = cs.k;
@@ -561,10 +571,15 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         int active = 1;           // iterations computed in this round
         bool split = false;       // one iteration whose products are shared out over the chain's workgroups
         int vfirst = wave, vstep = W;   // this wavefront's products in the VND loop
+        bool may_abandon = false;       // the iteration is dropped once the leader resolves the round without it
         const int64_t ev_round = evals, nb_round = nb_evals, fb_round = fallbacks;
         if constexpr (COOP) {
-            // the chain's state as the leader left it (acquired at the end of the previous round)
+            // the chain's state as the leader left it.  The round counter comes first: a workgroup that
+            // computed an abandoned iteration may join a round the leader has already moved past, and
+            // then reads a newer state than that round's; its summary carries the older round and is
+            // never used.
             if (threadIdx.x == 0) {
+                sh.coop_round = __hip_atomic_load(&a.coop_ctl[g].round, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                 sh.coop_cs = a.cstate[g];
                 sh.coop_done_it = a.coop_ctl[g].iters_done;
                 sh.coop_stop = sh.coop_done_it >= a.iters ||
@@ -573,6 +588,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             __syncthreads();
             cs = sh.coop_cs;
             done_it = sh.coop_done_it;
+            coop_round = sh.coop_round;
             if (sh.coop_stop) break;
             // Until x is known to be a local optimum an iteration runs the VND of every product (the first
             // iteration from the initial solution is most of a short run's time): then the m workgroups
@@ -584,6 +600,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             active = (split || a.best_of) ? 1 : (int)min<int64_t>(a.coop_m, a.iters - done_it);
             go = split || a.best_of || slot < active;
             it = it_first + done_it + ((split || a.best_of) ? 0 : slot);
+            may_abandon = !split && !a.best_of && slot > 0;
             kshake = cs.k;   // the shake size after this workgroup's slot rejections
             for (int q = 0; q < slot && !split && !a.best_of; ++q) kshake = kshake >= a.kmax ? 1 : kshake + 1;
             const int64_t sb = ((int64_t)g * a.coop_m + (split ? 0 : slot)) * a.coop_kmax;
@@ -650,7 +667,10 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     wave_sync_lds();
                 }
             }
-            if (lane == 0) sh.nd = nd;
+            if (lane == 0) {
+                sh.nd = nd;
+                sh.next_prod = W;   // wavefront w starts with product index w
+            }
         }
         __syncthreads();
         nd = sh.nd;
@@ -780,7 +800,13 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             // ---- VND (Algorithm 1) per product: the shaken products, or every product until x is known to
             //      be a local optimum ----
             const int nprod = cs.lopt ? nd : K;
-            for (int idx = vfirst; idx < nprod; idx += vstep) {
+            bool stale = false;   // the round moved on without this iteration (uniform)
+            // Products go to wavefronts as they finish (a product's VND length varies, and a shake of more
+            // products than wavefronts would otherwise put two on one wavefront however short the others
+            // are); the products of a split round are shared out over the chain's workgroups in fixed order.
+            const bool dyn = vstep == W;
+            for (int idx = vfirst; idx < nprod && !stale;
+                 idx = dyn ? __builtin_amdgcn_readfirstlane(next_index(sh.next_prod, lane)) : idx + vstep) {
                 int p, e = -1;
                 if (cs.lopt) {
                     p = sh.dp[idx];
@@ -806,7 +832,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 bool improved = true;
                 int passes = 0;
                 uint32_t clean = 0;   // neighbourhoods priced without improvement since the last applied move
-                while (improved) {
+                while (improved && !stale) {
                     if (++passes > kMaxPasses) {
                         vnd_err = 1;
                         break;
@@ -814,6 +840,13 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     improved = false;
                     for (int q = 0; q < a.n_nb; ++q) {
                         if (a.memo && ((clean >> q) & 1u)) continue;   // same pattern: nothing to find
+                        // the round counter, read before the evaluation and looked at after it, so that the
+                        // load's latency is hidden behind the pricing
+                        int32_t rnow = coop_round;
+                        if constexpr (COOP) {
+                            if (may_abandon)
+                                rnow = __hip_atomic_load(&a.coop_ctl[g].round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
                         bool applied = false;
                         const uint32_t nb = (a.nb_list >> (4 * q)) & 0xFu;
                         uint64_t key, ckey = kInfKey;
@@ -861,8 +894,13 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         // a move changes the pattern: every earlier pricing is stale
                         clean = applied ? 0u : (clean | (1u << q));
                         wave_sync_lds();
+                        if (__builtin_amdgcn_readfirstlane(rnow) != coop_round) {
+                            stale = true;
+                            break;
+                        }
                     }
                 }
+                if (stale) break;
                 if (lane == 0) {
                     s_work[p] = b;
                     s_work_cost[p] = cost;
@@ -897,6 +935,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     nbe += sh.nbr[w];
                     fbe += sh.fbr[w];
                 }
+                executed += ev;
                 mine->F_local = cs.F + delta;
                 mine->F_shaken = cs.F + dshake;
                 mine->evals = ev;
@@ -906,32 +945,52 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 mine->n_touch = cs.lopt ? nd : -1;   // -1: every product
                 for (int q = 0; q < nd; ++q) mine->dp[q] = sh.dp[q];
             }
-            // the VND results (written by every wavefront) and the summary, before the count
+            // the VND results (written by every wavefront) and the summary, before the stamp
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
-            // every workgroup of the chain checks in, idle or not, so that none can still be reading this
-            // round's starting state when the leader replaces it
-            if (threadIdx.x == 0) __hip_atomic_fetch_add(&ctl->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (go && threadIdx.x == 0)
+                __hip_atomic_store(&mine->stamp, coop_round + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             if (slot == 0) {
-                // the leader resolves the round in iteration order: the first accepted iteration ends it.
-                // Wavefront 0 loads the m summaries side by side (lane j: slot j) and resolves them with
-                // wave-uniform arithmetic; lane 0 writes.
+                // the leader resolves the round in iteration order: the first accepted iteration ends it, so
+                // it waits only for the slots up to that one (a split or best-of round needs all of them).
+                // Wavefront 0 polls the m stamps side by side (lane j: slot j), loads each summary once its
+                // slot and every earlier one have reported, and resolves them with wave-uniform arithmetic;
+                // lane 0 writes.
                 if (wave == 0) {
-                    int okl = 1;
-                    if (lane == 0) okl = coop_wait_ge(&ctl->done, a.coop_m, a.coop_wait_ticks);
-                    const bool ok = __shfl(okl, 0, 64) != 0;
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    const int need = (split || a.best_of) ? a.coop_m : active;   // slots holding this round
+                    const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + min(lane, a.coop_m - 1);
                     int64_t dl = 0, ds = 0, le = 0;   // lane j: slot j's F_local - F, F_shaken - F, evaluations
                     int64_t lnb = 0, lfb = 0;          //   and its learned counters
                     int lerr = 0;
-                    if (ok && lane < a.coop_m) {
-                        const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + lane;
-                        dl = sj->F_local - cs.F;
-                        ds = sj->F_shaken - cs.F;
-                        le = sj->evals;
-                        lerr = sj->err;
-                        lnb = sj->nb_evals;
-                        lfb = sj->fallbacks;
+                    int have = 0;                      // leading slots whose summaries are loaded (uniform)
+                    bool ok = true;
+                    const int64_t t0 = wall_clock64();
+                    for (uint32_t n = 0;; ++n) {
+                        const int32_t st =
+                            lane < need ? __hip_atomic_load(&sj->stamp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+                        const unsigned long long rdy = __ballot(lane < need && st == coop_round + 1);
+                        const int r = (int)__builtin_ctzll(~rdy);   // need <= 16, so ~rdy has a zero bit
+                        if (r > have) {
+                            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the summaries behind the stamps
+                            if (lane >= have && lane < r) {
+                                dl = sj->F_local - cs.F;
+                                ds = sj->F_shaken - cs.F;
+                                le = sj->evals;
+                                lerr = sj->err;
+                                lnb = sj->nb_evals;
+                                lfb = sj->fallbacks;
+                            }
+                            have = r;
+                        }
+                        if (have >= need) break;
+                        // no earlier iteration of the round is accepted, so iteration j is accepted when its
+                        // local cost is below F
+                        if (!(split || a.best_of) && __ballot(lane < have && dl < 0)) break;
+                        if (n >= kCoopSpinLimit || wall_clock64() - t0 > a.coop_wait_ticks) {
+                            ok = false;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
                     }
                     if (split) {   // the one iteration is the sum of every slot's share
                         dl = wave_sum_i64(dl);
@@ -959,7 +1018,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     }
                     const bool literal = a.best_of && a.best_literal;   // k fixed, the minimum always kept
                     int acc = -1, consumed = active, k = cs.k, err = ok ? 0 : 2;
-                    int64_t F = cs.F, Fb = cs.F_best, ev = 0, thrown = 0, nbe = 0, fbe = 0;
+                    int64_t F = cs.F, Fb = cs.F_best, ev = 0, nbe = 0, fbe = 0;
                     for (int j = 0; j < active && ok; ++j) {
                         const int64_t Fl = cs.F + __shfl(dl, j, 64), Fs = cs.F + __shfl(ds, j, 64);
                         ev += __shfl(le, j, 64);
@@ -988,8 +1047,6 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         }
                         k = k >= a.kmax ? 1 : k + 1;
                     }
-                    // iterations after the accepted one are thrown away (none in a split round: active = 1)
-                    for (int j = consumed; j < active && ok; ++j) thrown += __shfl(le, j, 64);
                     if (lane == 0) {
                         sh.coop_acc = ok ? acc : -1;
                         sh.coop_abort = !ok;
@@ -1000,7 +1057,6 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                             if (acc >= 0) cs.lopt = 1;
                             ctl->iters_done = done_it + consumed;
                             ctl->evals += ev;
-                            ctl->discarded += thrown;
                             ctl->nb_evals += nbe;
                             ctl->fallbacks += fbe;
                         }
@@ -1025,7 +1081,6 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 if (threadIdx.x == 0) {
                     a.cstate[g] = cs;
                     if (sh.coop_abort) ctl->abort = 1;
-                    ctl->done = 0;
                     __hip_atomic_fetch_add(&ctl->round, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
                 }
             } else if (threadIdx.x == 0) {
@@ -1034,7 +1089,6 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     atomicOr(&ctl->err, 2);
                 }
             }
-            ++coop_round;
             __syncthreads();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the leader's writes, for every thread
             continue;
@@ -1082,6 +1136,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     }
 
     if constexpr (COOP) {
+        CoopCtl *ctl = a.coop_ctl + g;
         if (slot == 0) {   // the leader: this launch's counters, and work == cur for the other search kernels
             __syncthreads();
             for (int q = threadIdx.x; q < K; q += blockDim.x) {
@@ -1089,12 +1144,23 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 a.work_cost[cp0 + q] = a.cur_cost[cp0 + q];
             }
             if (threadIdx.x == 0) {
-                cs.evals = a.coop_ctl[g].evals;
-                cs.discarded = a.coop_ctl[g].discarded;
-                cs.err |= a.coop_ctl[g].err;
-                cs.nb_evals = a.coop_ctl[g].nb_evals;
-                cs.fallbacks = a.coop_ctl[g].fallbacks;
+                cs.evals = ctl->evals;
+                cs.discarded = 0;
+                cs.err |= ctl->err;
+                cs.nb_evals = ctl->nb_evals;
+                cs.fallbacks = ctl->fallbacks;
                 a.cstate[g] = cs;
+            }
+        }
+        // the last workgroup of the chain to leave records the move-evaluations computed and not consumed
+        // (the iterations after an accepted one, finished or abandoned), and any error a slot raised
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(&ctl->executed, executed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t n = __hip_atomic_fetch_add(&ctl->exited, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if (n == a.coop_m - 1) {
+                const int64_t ex = __hip_atomic_load(&ctl->executed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                a.cstate[g].discarded = ex - ctl->evals;
+                a.cstate[g].err |= __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         return;

@@ -827,6 +827,8 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
             c->coop_cap_res = n_res;
         }
         VNS_HIP(c, hipMemsetAsync(c->d_coop_ctl, 0, sizeof(CoopCtl) * (size_t)G, c->stream));
+        // the slots' round stamps: one left by an earlier launch must not match a round of this one
+        VNS_HIP(c, hipMemsetAsync(c->d_coop_slot, 0, sizeof(CoopSlot) * (size_t)(G * m), c->stream));
         ra.state_off = -1;
         ra.coop_m = m;
         ra.coop_xcd = G % 8 == 0;

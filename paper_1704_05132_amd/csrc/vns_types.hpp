@@ -128,13 +128,15 @@ struct RunArgs {
 // (seed, chain, iteration, k), so the m iterations that follow a state are computed side by side, each by
 // its own workgroup, as if the earlier ones were rejected; they are then resolved in order and everything
 // after the first accepted one is discarded.  Records, moves and counted evaluations are those of the
-// sequential search.  Per chain, in device memory (set up by the host before each launch):
+// sequential search.  The leader resolves a round as soon as the slots up to its first accepted iteration
+// have reported; the workgroups still computing later iterations see the round counter move and abandon
+// them.  Per chain, in device memory (set up by the host before each launch):
 struct alignas(128) CoopCtl {   // one cache line per chain
     int32_t round;        // rounds completed (the leader increments it to start the next round)
-    int32_t done;         // workgroups of the chain done with the current round
+    int32_t exited;       // workgroups of the chain that have left the launch
     int64_t iters_done;   // iterations of this launch resolved so far
     int64_t evals;        // move-evaluations of the resolved iterations
-    int64_t discarded;    //   and of the iterations computed after an accepted one, thrown away
+    int64_t executed;     // move-evaluations every workgroup of the chain computed, abandoned ones included
     int64_t nb_evals;     // learned search: neighbourhood evaluations of the resolved iterations
     int64_t fallbacks;    //   and how many of them priced the whole neighbourhood
     int32_t abort;        // a bounded wait ran out: every workgroup of the chain leaves
@@ -145,6 +147,7 @@ struct CoopSlot {
     int64_t nb_evals, fallbacks;   // learned search: the iteration's neighbourhood evaluations and fallbacks
     int32_t n_touch;      // products in dp (K = every product: the VND of a state not yet a local optimum)
     int32_t err;
+    int32_t stamp;        // 1 + the round this summary belongs to (0: none in this launch)
     int32_t dp[kShakeMax];
 };
 constexpr double kCoopWaitSeconds = 20.0;       // a wait for the other workgroups of a chain gives up after this
