@@ -43,6 +43,7 @@ VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9 * OPS_PER_PERIOD_STEP / LANE_SLOTS_PER_STEP
 TUNE_FILE = os.path.join(ROOT, "paper_1704_05132_amd", "tune_table.json")
 # best-of-G search (Algorithm 2) measured beside the plain one: shakes per iteration
 BEST_OF_G = 4
+LEARNED_SPEC_M = 8   # speculative iterations of the learned search (4 wavefronts per workgroup)
 # learned scorer: 2 x (16*64 + 64*64 + 64) flops per scored move; dense bfloat16 matrix-core peak of MI355X
 MLP_FLOP_PER_ROW = 2 * (16 * 64 + 64 * 64 + 64)
 BF16_PEAK_TFLOPS = 2500.0
@@ -233,10 +234,12 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, seed, chains, n
     target = insts[0] if len(insts) == 1 else insts
     n_inst, chunk = len(insts), args.chunk
 
-    def make(options=None):
-        c = vns.Context(target, seed=seed, chains=chains, nb_list=nb, trace=False, options=options)
+    def make(options=None):   # the tuned launch shape, then the given options over it
+        c = vns.Context(target, seed=seed, chains=chains, nb_list=nb, trace=False)
         c.bind_stream(stream)
         table.apply(c, key)
+        for opt, v in (options or {}).items():
+            c.set_option(opt, v)
         return c
 
     # plain: per-instance best after the workload's iterations, and the device time to first reach all
@@ -276,6 +279,11 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, seed, chains, n
 
     def make_learned():
         c = make({vns.OPT_LEARNED: args.learned_permille})
+        if c.get_option(vns.OPT_SPEC_ITERS) > 1:
+            # the learned kernel keeps the scorer's weights in registers (about 250 VGPRs, two wavefronts per
+            # SIMD), so its speculative launch takes two 4-wavefront workgroups per compute unit
+            c.set_option(vns.OPT_RUN_WAVES, 4)
+            c.set_option(vns.OPT_SPEC_ITERS, LEARNED_SPEC_M)
         c.mlp_set(params)
         return c
 

@@ -19,7 +19,8 @@ from typing import Callable, Iterable, Sequence
 SEARCH_CANDIDATES = ([dict(waves=w, lds=l, spec=0, state=st) for w in (2, 4, 8) for l in (0, 65536) for st in (0, 1)] +
                      [dict(spec=1, spec_waves=s, lds=l) for s in (6, 9, 15) for l in (0, 65536)] +
                      [dict(waves=w, lds=65536, spec=0, iters=m) for w, m in
-                      ((8, 2), (8, 3), (8, 4), (4, 3), (4, 4), (4, 6), (4, 8), (2, 6), (2, 8))])
+                      ((8, 2), (8, 3), (8, 4), (4, 3), (4, 4), (4, 6), (4, 8), (4, 12), (3, 8), (3, 12), (2, 6),
+                       (2, 8))])
 EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 3, 4, 5, 6, 8, 12, 16)]
 
 

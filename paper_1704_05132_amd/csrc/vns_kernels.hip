@@ -1216,7 +1216,7 @@ __global__ __launch_bounds__(1024) void k_run_spec(RunArgs a) {
 
 // speculative iterations: m workgroups per chain compute the next m iterations side by side (cooperative
 // launch: every workgroup of a chain is resident while it waits for the others)
-__global__ __launch_bounds__(512) void k_run_coop(RunArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_run_coop(RunArgs a) {
     __shared__ RunShared sh;
     __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
