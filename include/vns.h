@@ -102,8 +102,10 @@ enum vns_option {
                               m workgroups per chain compute the next m iterations side by side as if
                               the earlier ones were rejected; they are resolved in order and what
                               follows the first accepted one is discarded.  Records, solutions and
-                              counted move-evaluations equal those of the one-workgroup search.  Used
-                              for the plain search when every workgroup of the launch can be resident
+                              counted move-evaluations equal those of the one-workgroup search.  A round
+                              is resolved once the iterations up to its first accepted one are done; the
+                              workgroups computing later ones abandon them.  Used for the plain and the
+                              learned search when every workgroup of the launch can be resident
                               at once, the move log is off and the run is not captured in a graph;
                               otherwise the run falls back to one workgroup per chain
                               (vns_stats.last_run_spec_iters = 1).  A chain's workgroups wait for each
@@ -157,7 +159,8 @@ typedef struct vns_stats {
                                         VNS_OPT_SPEC_ITERS)                                               */
     int64_t last_run_discarded_evals;/*   and the move-evaluations of its iterations that followed an accepted
                                         one in their round, computed and thrown away (not in
-                                        last_run_evals)                                                   */
+                                        last_run_evals); abandoned iterations count what they computed
+                                        before they stopped, so this figure varies from run to run        */
     int64_t last_eval_decoded_steps; /* period-steps the last vns_eval_neighbourhood decoded (equal to the
                                         evaluations' period-steps unless VNS_OPT_EVAL_INCREMENTAL)          */
 } vns_stats;
