@@ -92,7 +92,7 @@ def parse():
                     help="skip the side measurements (neighbourhood skip, best-of-G, incremental sweep), so that the "
                          "timed search launch is the only one of its kernel (for a profiler's per-kernel average)")
     ap.add_argument("--chunk", type=int, default=50, help="iterations per launch in the time-to-best runs")
-    ap.add_argument("--learned-permille", type=int, default=100, help="share of moves priced exactly (1/1000)")
+    ap.add_argument("--learned-permille", type=int, default=50, help="share of moves priced exactly (1/1000)")
     ap.add_argument("--learned-train-instances", type=int, default=16)
     ap.add_argument("--learned-log-iters", type=int, default=200)
     ap.add_argument("--learned-epochs", type=int, default=8)
