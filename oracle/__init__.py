@@ -9,7 +9,11 @@ Parity status per function (what pins it, see tests/test_oracle_pins.py):
                  and MILP <= min decode when R > 0; closed forms; hand-worked golden examples; flow-balance
                  invariants on random instances.
   price_all      brute-force table of all 2^(2T) patterns (K = 1, T <= 6): every slot's price.
-  vnd            local optimality of the result, monotone objective, per-product independence.
+  vnd            move by move against a VND written in the tests over brute-force cost tables of every
+                 pattern (the per-product best move of each neighbourhood in list order, applied only when
+                 strictly better, lowest slot on ties, no reset within a pass); a hand-worked example
+                 (tests/golden/vnd_hand.json); local optimality, monotone objective, per-product
+                 independence.
   philox         numpy.random.Philox (the library's Philox4x64-10).
   shake          slots derived from numpy.random.Philox outputs; feasibility of every applied flip.
   gvns           acceptance rule, k schedule, best tracking, resume equivalence, objective recomputation.
@@ -59,6 +63,9 @@ def lib():
         L.orc_argmin.argtypes = [c.c_int64, _i64p, c.POINTER(c.c_int64)]
         L.orc_vnd.restype = c.c_int64
         L.orc_vnd.argtypes = [c.c_int, c.c_int] + inst + [_u8p, _u8p, _i32p, c.c_int, c.POINTER(c.c_int64)]
+        L.orc_vnd_trace.restype = c.c_int64
+        L.orc_vnd_trace.argtypes = ([c.c_int, c.c_int] + inst + [_u8p, _u8p, _i32p, c.c_int, c.POINTER(c.c_int64),
+                                                                  _i64p, c.c_int64, c.POINTER(c.c_int64)])
         L.orc_philox4x64_10.restype = None
         L.orc_philox4x64_10.argtypes = [_u64p, _u64p, _u64p]
         L.orc_draw.restype = c.c_int64
@@ -136,14 +143,28 @@ def argmin(price):
     return int(v), int(s.value)
 
 
-def vnd(inst, zM, zR, nb_list=(1, 2, 4)):
-    """VND (Algorithm 1) from the given solution; returns (F, zM, zR, move-evaluations)."""
+def vnd(inst, zM, zR, nb_list=(1, 2, 4), trace=False):
+    """VND (Algorithm 1) from the given solution; returns (F, zM, zR, move-evaluations), and with `trace`
+    also the applied moves as an int64 array of rows (pass, neighbourhood id, product, local slot, F after)."""
     a = _rows(zM, inst.K, inst.T).copy()
     b = _rows(zR, inst.K, inst.T).copy()
     ev = ctypes.c_int64(0)
     nb = np.ascontiguousarray(nb_list, np.int32)
-    F = lib().orc_vnd(inst.K, inst.T, *_inst(inst), a, b, nb, len(nb), ctypes.byref(ev))
-    return int(F), a, b, int(ev.value)
+    if not trace:
+        F = lib().orc_vnd(inst.K, inst.T, *_inst(inst), a, b, nb, len(nb), ctypes.byref(ev))
+        return int(F), a, b, int(ev.value)
+    cap = 1 << 12
+    while True:
+        rec = np.zeros(5 * cap, np.int64)
+        n = ctypes.c_int64(0)
+        a = _rows(zM, inst.K, inst.T).copy()
+        b = _rows(zR, inst.K, inst.T).copy()
+        ev = ctypes.c_int64(0)
+        F = lib().orc_vnd_trace(inst.K, inst.T, *_inst(inst), a, b, nb, len(nb), ctypes.byref(ev), rec, cap,
+                                ctypes.byref(n))
+        if n.value <= cap:
+            return int(F), a, b, int(ev.value), rec[:5 * n.value].reshape(-1, 5)
+        cap = int(n.value)
 
 
 def philox4x64_10(key, ctr):

@@ -206,18 +206,22 @@ int64_t orc_argmin(int64_t n, const int64_t *price, int64_t *slot)
 /* VND, Algorithm 1.  nb_list holds n_nb neighbourhood ids in order.  For each neighbourhood, every   */
 /* product's best move (lowest slot on ties) is applied when it strictly lowers F; passes repeat until */
 /* one changes nothing.  zM/zR are updated in place; returns the final F (the input must be feasible). */
-/* *evals (may be NULL) accumulates the number of move-evaluations.                                   */
+/* *evals (may be NULL) accumulates the number of move-evaluations.  With trace non-NULL, every applied */
+/* move appends (pass, neighbourhood id, product, local slot, F after the move), five int64 each, up   */
+/* to trace_cap moves; *n_trace receives the number of moves applied.                                  */
 /* ------------------------------------------------------------------------------------------------ */
-int64_t orc_vnd(int K, int T, const int32_t *D, const int32_t *R,
-                const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
-                   const int32_t *pM, const int32_t *pR,
-                uint8_t *zM, uint8_t *zR, const int32_t *nb_list, int n_nb, int64_t *evals)
+int64_t orc_vnd_trace(int K, int T, const int32_t *D, const int32_t *R,
+                      const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                      const int32_t *pM, const int32_t *pR,
+                      uint8_t *zM, uint8_t *zR, const int32_t *nb_list, int n_nb, int64_t *evals,
+                      int64_t *trace, int64_t trace_cap, int64_t *n_trace)
 {
     int64_t *cost = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
     int64_t F = orc_objective(K, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR, cost);
     uint8_t *wM = (uint8_t *)malloc((size_t)T);
     uint8_t *wR = (uint8_t *)malloc((size_t)T);
     int improvement;
+    int64_t pass = 0, n_moves = 0;
     do {
         improvement = 0;
         for (int q = 0; q < n_nb; ++q) {
@@ -243,12 +247,27 @@ int64_t orc_vnd(int K, int T, const int32_t *D, const int32_t *R,
                     cost[k] = cost[k] + (best_price - F);
                     F = best_price;
                     improvement = 1;
+                    if (trace && n_moves < trace_cap) {
+                        int64_t *r = trace + 5 * n_moves;
+                        r[0] = pass; r[1] = nb_list[q]; r[2] = k; r[3] = best_l; r[4] = F;
+                    }
+                    ++n_moves;
                 }
             }
         }
+        ++pass;
     } while (improvement);
+    if (n_trace) *n_trace = n_moves;
     free(wM); free(wR); free(cost);
     return F;
+}
+
+int64_t orc_vnd(int K, int T, const int32_t *D, const int32_t *R,
+                const int32_t *kM, const int32_t *kR, const int32_t *hM, const int32_t *hR,
+                const int32_t *pM, const int32_t *pR,
+                uint8_t *zM, uint8_t *zR, const int32_t *nb_list, int n_nb, int64_t *evals)
+{
+    return orc_vnd_trace(K, T, D, R, kM, kR, hM, hR, pM, pR, zM, zR, nb_list, n_nb, evals, NULL, 0, NULL);
 }
 
 /* ------------------------------------------------------------------------------------------------ */
