@@ -145,7 +145,8 @@ struct LearnedLds {
 // Learned best move of one neighbourhood (one wavefront).  The scorer ranks the moves (lowest score first,
 // ties to the lower slot), the best-ranked ceil(permille * n / 1000) (at least one) are priced exactly and
 // the best of them is returned if it is cheaper than `cost`; otherwise the whole neighbourhood is priced
-// exactly (fallback) and its best move is returned.  With `ident` the unchanged pattern is priced with the
+// exactly (fallback) and its best move is returned.  A neighbourhood without moves returns kInfKey with no
+// evaluation and no fallback.  With `ident` the unchanged pattern is priced with the
 // selected moves and *cost is set to it first.  score_out / sel_out (indexed by slot, may be null) receive
 // the scores and the selection.
 __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 *row, int T, const ProdParams &pp,
@@ -157,6 +158,13 @@ __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 
     int nflip;
     bool fm;
     const int nitems = move_list(b, T, nb, list, nflip, fm);
+    fallback = 0;
+    if (nitems == 0) {
+        // an empty neighbourhood (every adjacent pair equal in a shift, or T = 1): nothing is scored,
+        // selected or priced; with `ident` the unchanged pattern is still priced, by every lane alike
+        if (ident) cost = decode_cost(b, row, T, pp);
+        return kInfKey;
+    }
     // 1. scores of every move, kept as (sortable score << 32 | slot) keys, up to four per lane
     uint64_t sk[4] = {kInfKey, kInfKey, kInfKey, kInfKey};
 #pragma unroll
@@ -181,7 +189,7 @@ __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 
         }
     }
     // 2. the best-ranked moves, by repeated wavefront minima
-    int n_sel = (permille * nitems + 999) / 1000;
+    int n_sel = (permille * nitems + 999) / 1000;   // nitems >= 1 here
     n_sel = n_sel < 1 ? 1 : (n_sel > nitems ? nitems : n_sel);
     for (int r = 0; r < n_sel; ++r) {
         uint64_t my = sk[0];
@@ -191,7 +199,7 @@ __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) sk[ch] = sk[ch] == m ? kInfKey : sk[ch];
         if (lane == 0) L.sel[r] = (uint16_t)(m & 0xFFFFu);
-        if (sel_out && lane == 0) sel_out[m & 0xFFFFu] = 1;
+        if (sel_out && lane == 0 && m != kInfKey) sel_out[m & 0xFFFFu] = 1;
     }
     wave_sync_lds();
     // 3. exact prices of the selection (and of the unchanged pattern)

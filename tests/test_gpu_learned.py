@@ -113,6 +113,7 @@ def _check_learned_eval(vns, ctx, inst, chain, nb, permille):
           params[5248:5312].reshape(64, 1), params[5312:5313]]
     T = inst.T
     n_fallback = 0
+    n_priced = 0   # exact evaluations the rule makes: the selection, plus the whole neighbourhood on fallback
     for k in range(inst.K):
         base = 4 * T * k
         slots = [l for l in range(4 * T) if oracle.apply_slot(T, zM[k], zR[k], l)[0] and
@@ -122,6 +123,7 @@ def _check_learned_eval(vns, ctx, inst, chain, nb, permille):
         if not slots:                     # no move in this neighbourhood (e.g. no differing adjacent bits)
             assert not out["selected"][base:base + 4 * T].any()
             assert (int(out["prod_best"][k]), int(out["prod_best_slot"][k])) == (INF, -1)
+            assert out["fallback"][k] == 0   # nothing scored, selected or priced
             continue
         feats = np.array([L.move_features(inst, k, zM[k], zR[k], l) for l in slots])
         ref, _ = L.forward(feats, ps, quantize=True)
@@ -132,6 +134,7 @@ def _check_learned_eval(vns, ctx, inst, chain, nb, permille):
         order = sorted(slots, key=lambda l: (sortable(sc[l]), l))
         sel = set(order[:n_sel])
         assert set(np.flatnonzero(out["selected"][base:base + 4 * T])) == sel, k
+        n_priced += n_sel
         prices = price[base:base + 4 * T]
         best_sel = min(((prices[l], l) for l in sel), default=(INF, -1))
         if best_sel[0] < F:
@@ -140,9 +143,16 @@ def _check_learned_eval(vns, ctx, inst, chain, nb, permille):
         else:
             assert out["fallback"][k] == 1
             n_fallback += 1
+            n_priced += len(slots)
             fin = [(prices[l], l) for l in slots if prices[l] != INF]
             expect = min(fin) if fin else (INF, -1)
         assert (int(out["prod_best"][k]), int(out["prod_best_slot"][k])) == expect, k
+    # the selections from all products of the chain, nothing unselected besides
+    assert int(out["selected"].sum()) == sum(
+        min(n, max(1, -(-permille * n // 1000))) for n in
+        (len([l for l in range(4 * T) if oracle.apply_slot(T, zM[k], zR[k], l)[0] and
+              oracle.learned.move_type(T, l) in {1: (0,), 2: (1,), 4: (2, 3)}[nb]]) for k in range(inst.K)) if n)
+    assert ctx.stats()["last_eval_evals"] == n_priced
     return n_fallback
 
 
@@ -231,3 +241,37 @@ def test_mlp_init_is_he_uniform(vns):
     for off, n, fan_in in ((0, 1024, 16), (1088, 4096, 64)):
         w = p1[off:off + n]
         assert np.abs(w).max() <= np.sqrt(6.0 / fan_in) and abs(w.mean()) < 0.1 * np.sqrt(6.0 / fan_in)
+
+
+@pytest.mark.parametrize("T", [65, 104, 128])
+def test_learned_eval_rules_long_horizon(vns, T):
+    """The four-word setup rows (T > 64): every rule of the learned choice in each neighbourhood, from the
+    initial solution (the shift neighbourhood is empty there) and after a few iterations."""
+    inst = draw_instance(np.random.default_rng([61, T]), 3, T)
+    with vns.Context(inst, seed=6) as ctx:
+        ctx.mlp_set(random_params(62))
+        for nb in (1, 2, 4):
+            say(f"  learned eval T={T} nb={nb} (initial solution)")
+            _check_learned_eval(vns, ctx, inst, 0, nb, 100)
+        ctx.run(4)
+        for nb, permille in ((1, 100), (2, 250), (4, 100), (4, 1000)):
+            say(f"  learned eval T={T} nb={nb} permille={permille} (after 4 iterations)")
+            _check_learned_eval(vns, ctx, inst, 0, nb, permille)
+
+
+@pytest.mark.parametrize("T", [65, 104, 128])
+def test_learned_search_local_optima_long_horizon(vns, T):
+    inst = draw_instance(np.random.default_rng([63, T]), 4, T)
+    say(f"  learned search T={T}")
+    with vns.Context(inst, seed=7, chains=2, options={vns.OPT_LEARNED: 100}) as ctx:
+        ctx.mlp_set(random_params(64))
+        ctx.run(6)
+        for g in range(2):
+            zM, zR = ctx.solution(g)
+            F, Fb = ctx.cost(g)
+            assert F == oracle.objective(inst, zM, zR)[0] and F == Fb
+            price, _ = oracle.price_all(inst, zM, zR, 7)
+            assert price.min() >= F
+            rec = ctx.trajectory(g)
+            assert (rec["F_local"] <= rec["F_shaken"]).all()
+            assert ((rec["accepted"][1:] == 1) == (rec["F_local"][1:] < rec["F_best"][:-1])).all()
