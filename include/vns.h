@@ -212,6 +212,30 @@ vns_status vns_get_option(const vns_ctx *ctx, int32_t key, int64_t *value);
 vns_status vns_bind_stream(vns_ctx *ctx, void *hip_stream);
 
 /*
+ * Workspace: device memory that a call's kernels use only while the call runs.  By default the context
+ * allocates it itself (hipMalloc, kept for later calls).  A caller that manages device memory (a framework's
+ * caching allocator) can bind a buffer it owns instead; the flags say which calls take their scratch from it:
+ *   VNS_WS_RUN          vns_run's speculative-iteration and best-of-G buffers (per chain a 128-byte control
+ *                       line, per chain and slot a summary and 40 bytes per product), sized for the current
+ *                       VNS_OPT_SPEC_ITERS / VNS_OPT_BEST_OF; nothing when neither is on;
+ *   VNS_WS_EVAL         vns_eval_neighbourhood's table of pricing workgroups (40 bytes per (chain, product),
+ *                       the most any chain range or VNS_OPT_EVAL_GROUP needs);
+ *   VNS_WS_EVAL_PRICES  as VNS_WS_EVAL, plus the staging of slot prices for every chain (8 bytes per slot).
+ * vns_workspace_bytes — bytes a workspace bound with `flags` must have under the current options (0 for no
+ * flags).  vns_bind_workspace — bind `dev_ptr` (device memory of the context's device, 256-byte aligned,
+ * `bytes` long) for the calls in `flags`; VNS_EINVAL if it is smaller than vns_workspace_bytes(flags), badly
+ * aligned, or flags has unknown bits.  dev_ptr = NULL (or flags = 0) unbinds: the context allocates again.
+ * The caller keeps ownership, must keep the buffer alive while it is bound, and must not touch it while a
+ * call of this context runs.  A call whose scratch outgrows the bound buffer (options changed after the bind)
+ * returns VNS_EINVAL without running; query the size again and rebind.
+ */
+#define VNS_WS_RUN 1u
+#define VNS_WS_EVAL 2u
+#define VNS_WS_EVAL_PRICES 4u
+vns_status vns_workspace_bytes(const vns_ctx *ctx, uint32_t flags, size_t *bytes);
+vns_status vns_bind_workspace(vns_ctx *ctx, void *dev_ptr, size_t bytes, uint32_t flags);
+
+/*
  * vns_eval_neighbourhood — exact pricing of every move of the neighbourhoods in nb_mask (an OR of VNS_NB_*)
  * for the current solution of one chain, or of every chain (chain = VNS_ALL_CHAINS).  For a move of product
  * k, price = F - cost_k + cost_k(after the move), the objective the move would give (Section 3: the new
@@ -243,12 +267,22 @@ vns_status vns_get_cost(vns_ctx *ctx, int32_t chain, int64_t *F, int64_t *F_best
  * NULL): one device-to-host copy instead of one call per chain. */
 vns_status vns_get_costs(vns_ctx *ctx, int64_t *F, int64_t *F_best);
 
-/* vns_get_solution — current setup rows of one chain, [K*T] uint8 0/1 each, row-major [k][t]. */
-vns_status vns_get_solution(vns_ctx *ctx, int32_t chain, uint8_t *zM, uint8_t *zR);
+/*
+ * vns_get_solution — setup rows of one chain, [K*T] uint8 0/1 each, row-major [k][t]:
+ *   which = VNS_SOLUTION_CURRENT: the current solution x;
+ *   which = VNS_SOLUTION_BEST: the cheapest solution the chain has held (objective F_best of vns_get_cost),
+ *   tracked on the device at every acceptance.  Under Algorithm 2's accept-if-better rule it is x itself;
+ *   it differs from x only after best-of-G as printed (VNS_OPT_BEST_OF_LITERAL), whose selected result
+ *   replaces x even when it is worse.  VNS_EINVAL for any other `which`.
+ */
+#define VNS_SOLUTION_CURRENT 0
+#define VNS_SOLUTION_BEST 1
+vns_status vns_get_solution(vns_ctx *ctx, int32_t chain, int32_t which, uint8_t *zM, uint8_t *zR);
 
 /* vns_set_solution — replace the current solution of one chain ([K*T] uint8, nonzero = setup).  The
- * chain's best objective is reset to the new F and its shake size to 1.  VNS_ERANGE (nothing changed) if
- * a product would be infeasible. */
+ * chain's search state restarts from it: best solution = x, best objective = the new F, shake size 1.
+ * VNS_ERANGE if a product would be infeasible: x is then left unchanged and the search state restarts from
+ * it in the same way. */
 vns_status vns_set_solution(vns_ctx *ctx, int32_t chain, const uint8_t *zM, const uint8_t *zR);
 
 /* vns_get_trajectory — records of the last vns_run for one chain: up to `cap` records into `rec`, the
@@ -304,6 +338,18 @@ int64_t vns_num_chains(const vns_ctx *ctx);
 /* vns_last_error — text of the last error of the context (or of the last failed create when ctx is NULL);
  * valid until the next call on the same context. */
 const char *vns_last_error(const vns_ctx *ctx);
+
+/*
+ * vns_test_inject_failure — for tests of the error paths, without a real device fault (per calling thread):
+ *   kind = VNS_INJECT_ALLOC:  the `countdown`-th device allocation from now (1 = the next) fails as out of
+ *                             memory, so the call making it returns VNS_ENOMEM;
+ *   kind = VNS_INJECT_DEVICE: the `countdown`-th call on a live context from now reports a HIP failure, so it
+ *                             returns VNS_EDEVICE and the context is dead (later calls: VNS_ESTATE);
+ *   countdown = 0 clears the injection of that kind.  VNS_EINVAL for another kind or a negative countdown.
+ */
+#define VNS_INJECT_ALLOC 1
+#define VNS_INJECT_DEVICE 2
+vns_status vns_test_inject_failure(int32_t kind, int32_t countdown);
 
 #ifdef __cplusplus
 }

@@ -37,6 +37,7 @@ __global__ __launch_bounds__(256) void k_init_costs(InitArgs a) {
         a.cur_cost[cp] = c;
         a.work[cp] = b;
         a.work_cost[cp] = c;
+        a.best[cp] = b;
         if (c == kInf) inf = 1; else sum += c;
     }
     __shared__ int64_t s_sum[4];
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(256) void k_init_costs(InitArgs a) {
         cs.k = 1;
         cs.lopt = 0;
         cs.err = 0;
-        cs.pad = 0;
+        cs.bsync = 1;
         cs.nb_evals = 0;
         cs.fallbacks = 0;
         cs.discarded = 0;
@@ -440,6 +441,7 @@ struct RunShared {
     int32_t coop_stop;
     int32_t coop_acc;
     int32_t coop_abort;
+    int32_t coop_bmode;   // the round's update of the best solution: 0 none, 1 the accepted products, 2 all of x
     int64_t nbr[kMaxWaves];   // a round's learned counters per wavefront
     int64_t fbr[kMaxWaves];
 };
@@ -1047,13 +1049,18 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         }
                         k = k >= a.kmax ? 1 : k + 1;
                     }
+                    // the best solution follows x when x becomes the cheapest so far: the accepted products
+                    // when it held x before, all of x otherwise (x had moved to a worse solution)
+                    const int bmode = (ok && acc >= 0 && F < cs.F_best) ? (cs.bsync ? 1 : 2) : 0;
                     if (lane == 0) {
                         sh.coop_acc = ok ? acc : -1;
                         sh.coop_abort = !ok;
+                        sh.coop_bmode = bmode;
                         if (ok) {
                             cs.F = F;
                             cs.F_best = Fb;
                             cs.k = k;
+                            cs.bsync = bmode ? 1 : (acc >= 0 ? 0 : cs.bsync);
                             if (acc >= 0) cs.lopt = 1;
                             ctl->iters_done = done_it + consumed;
                             ctl->evals += ev;
@@ -1065,16 +1072,22 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 }
                 __syncthreads();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the slots' results, for every thread
-                const int acc = sh.coop_acc;
+                const int acc = sh.coop_acc, bmode = sh.coop_bmode;
                 if (acc >= 0) {   // x takes the accepted iteration's VND results
                     const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + acc;
                     const int64_t sb = ((int64_t)g * a.coop_m + acc) * a.coop_kmax;
                     const int n = sj->n_touch < 0 ? K : sj->n_touch;
                     for (int q = threadIdx.x; q < n; q += blockDim.x) {
                         const int p = sj->n_touch < 0 ? q : sj->dp[q];
-                        a.cur[cp0 + p] = a.coop_res[sb + p];
+                        const Bits b = a.coop_res[sb + p];
+                        a.cur[cp0 + p] = b;
                         a.cur_cost[cp0 + p] = a.coop_res_cost[sb + p];
+                        if (bmode == 1) a.best[cp0 + p] = b;
                     }
+                }
+                if (bmode == 2) {
+                    __syncthreads();
+                    for (int q = threadIdx.x; q < K; q += blockDim.x) a.best[cp0 + q] = a.cur[cp0 + q];
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // x, before the round count
                 __syncthreads();
@@ -1102,12 +1115,16 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
         }
         const int64_t F_local = cs.F + delta;
         const int accepted = F_local < cs.F;
+        // the best solution follows x when x becomes the cheapest so far: the touched products when it held
+        // x before, all of x otherwise
+        const int bmode = (accepted && F_local < cs.F_best) ? (cs.bsync ? 1 : 2) : 0;
         const int ntouch = cs.lopt ? nd : K;
         for (int idx = threadIdx.x; idx < ntouch; idx += blockDim.x) {
             const int p = cs.lopt ? sh.dp[idx] : idx;
             if (accepted) {
                 s_cur[p] = s_work[p];
                 s_cur_cost[p] = s_work_cost[p];
+                if (bmode == 1) a.best[cp0 + p] = s_work[p];
             } else {
                 s_work[p] = s_cur[p];
                 s_work_cost[p] = s_cur_cost[p];
@@ -1124,10 +1141,15 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             r.F_best = (accepted && F_local < cs.F_best) ? F_local : cs.F_best;
             a.trace[(int64_t)g * a.iters + i] = r;
         }
+        if (bmode == 2) {
+            __syncthreads();
+            for (int q = threadIdx.x; q < K; q += blockDim.x) a.best[cp0 + q] = s_cur[q];
+        }
         if (accepted) {
             cs.F = F_local;
             cs.k = 1;
             cs.lopt = 1;
+            cs.bsync = bmode ? 1 : 0;
         } else {
             cs.k = cs.k >= a.kmax ? 1 : cs.k + 1;
         }

@@ -16,6 +16,7 @@ struct InitArgs {
     Bits *work;
     int64_t *work_cost;
     ChainState *cstate;
+    Bits *best;          // the best solution starts as the current one
     int32_t chain0;
 };
 

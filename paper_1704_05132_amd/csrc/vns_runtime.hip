@@ -29,6 +29,9 @@ static void mlp_he_uniform(uint64_t seed, std::vector<float> &p);
 namespace {
 
 thread_local std::string g_create_error;
+// vns_test_inject_failure: countdowns to a simulated allocation failure / HIP failure (0 = off)
+thread_local int32_t g_inject_alloc = 0;
+thread_local int32_t g_inject_device = 0;
 
 template <class T>
 struct DevBuf {
@@ -90,6 +93,7 @@ struct vns_ctx {
     int32_t *d_cp_chain = nullptr;
     int64_t *d_price_off = nullptr;
     Bits *d_cur = nullptr, *d_work = nullptr;
+    Bits *d_bestx = nullptr;              // each chain's best solution so far
     int64_t *d_cur_cost = nullptr, *d_work_cost = nullptr;
     ChainState *d_cs = nullptr;
     uint64_t *d_prod_key = nullptr;
@@ -115,6 +119,10 @@ struct vns_ctx {
     EvalWg *d_eval_wg = nullptr;          // k_eval workgroup table of the last chain range priced
     int64_t eval_wg_n = 0;
     int64_t eval_wg_key[3] = {-1, -1, -1};  // (first chain, number of chains, group size) of that table
+
+    char *ws = nullptr;                   // caller-owned workspace (vns_bind_workspace), its size and flags
+    size_t ws_bytes = 0;
+    uint32_t ws_flags = 0;
 
     hipStream_t own_stream = nullptr, stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -156,6 +164,8 @@ static vns_status hip_fail(vns_ctx *c, hipError_t e, const char *what) {
     do {                                                                                       \
         if (!(ctx)) return fail(nullptr, VNS_EINVAL, "null context");                          \
         if ((ctx)->dead) return fail((ctx), VNS_ESTATE, "context is dead after a device error"); \
+        if (g_inject_device > 0 && --g_inject_device == 0)                                     \
+            return hip_fail((ctx), hipErrorLaunchFailure, "injected failure (vns_test_inject_failure)"); \
         VNS_HIP((ctx), hipSetDevice((ctx)->device));                                          \
     } while (0)
 
@@ -163,6 +173,7 @@ template <class T>
 static hipError_t dmalloc(T **p, size_t n) {
     *p = nullptr;
     if (n == 0) n = 1;
+    if (g_inject_alloc > 0 && --g_inject_alloc == 0) return hipErrorOutOfMemory;
     return hipMalloc((void **)p, n * sizeof(T));
 }
 
@@ -188,6 +199,7 @@ static void free_chains(vns_ctx *c) {
     dfree(c->d_price_off);
     dfree(c->d_cur);
     dfree(c->d_work);
+    dfree(c->d_bestx);
     dfree(c->d_cur_cost);
     dfree(c->d_work_cost);
     dfree(c->d_cs);
@@ -278,6 +290,7 @@ static vns_status setup_chains(vns_ctx *c) {
     VNS_HIP(c, dmalloc(&c->d_price_off, (size_t)G));
     VNS_HIP(c, dmalloc(&c->d_cur, (size_t)cp));
     VNS_HIP(c, dmalloc(&c->d_work, (size_t)cp));
+    VNS_HIP(c, dmalloc(&c->d_bestx, (size_t)cp));
     VNS_HIP(c, dmalloc(&c->d_cur_cost, (size_t)cp));
     VNS_HIP(c, dmalloc(&c->d_work_cost, (size_t)cp));
     VNS_HIP(c, dmalloc(&c->d_cs, (size_t)G));
@@ -293,7 +306,8 @@ static vns_status setup_chains(vns_ctx *c) {
     VNS_HIP(c, hipMemcpyAsync(c->d_cp_chain, cp_chain.data(), sizeof(int32_t) * (size_t)cp, hipMemcpyHostToDevice, c->stream));
     VNS_HIP(c, hipMemcpyAsync(c->d_price_off, c->price_off.data(), sizeof(int64_t) * (size_t)G, hipMemcpyHostToDevice, c->stream));
     VNS_HIP(c, hipMemcpyAsync(c->d_cur, bits.data(), sizeof(Bits) * (size_t)cp, hipMemcpyHostToDevice, c->stream));
-    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs, 0};
+    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs,
+                c->d_bestx, 0};
     VNS_HIP(c, launch_init(ia, (int)G, c->stream));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     c->iteration = 0;
@@ -586,6 +600,98 @@ extern "C" vns_status vns_bind_stream(vns_ctx *c, void *s) {
 }
 
 // ---------------------------------------------------------------------------------------------------
+// workspace
+// ---------------------------------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Layout of a workspace bound with `flags` under the current options: the pricing workgroup table at 0, then
+// the slot-price staging, then vns_run's buffers (the only part whose size depends on options, so last).
+struct WsLayout {
+    size_t eval_off = 0, eval_bytes = 0;
+    size_t price_off = 0, price_bytes = 0;
+    size_t run_off = 0, ctl_bytes = 0, slot_bytes = 0, res_bytes = 0, res_cost_bytes = 0;
+    size_t total = 0;
+};
+
+static int64_t max_products(const vns_ctx *c) {
+    int64_t m = 0;
+    for (int32_t i = 0; i < c->n_inst; ++i) m = std::max<int64_t>(m, c->K[(size_t)i]);
+    return m;
+}
+
+// Slots per chain of vns_run's cooperative launch under the current options (0: no cooperative launch).
+static int32_t coop_slots(const vns_ctx *c) {
+    const bool best = c->best_of >= 2 || c->best_literal;
+    if (best) return std::max<int32_t>(c->best_of, 1);
+    return c->spec_iters > 1 ? c->spec_iters : 0;
+}
+
+static WsLayout ws_layout(const vns_ctx *c, uint32_t flags) {
+    WsLayout L;
+    size_t off = 0;
+    if (flags & (VNS_WS_EVAL | VNS_WS_EVAL_PRICES)) {
+        L.eval_off = off;
+        L.eval_bytes = align256(sizeof(EvalWg) * (size_t)std::max<int64_t>(c->total_cp, 1));
+        off += L.eval_bytes;
+    }
+    if (flags & VNS_WS_EVAL_PRICES) {
+        L.price_off = off;
+        L.price_bytes = align256(sizeof(int64_t) * (size_t)std::max<int64_t>(c->total_slots, 1));
+        off += L.price_bytes;
+    }
+    if (flags & VNS_WS_RUN) {
+        const size_t G = c->chains.size(), m = (size_t)coop_slots(c), n_res = G * m * (size_t)max_products(c);
+        L.run_off = off;
+        if (m > 0) {
+            L.ctl_bytes = align256(sizeof(CoopCtl) * G);
+            L.slot_bytes = align256(sizeof(CoopSlot) * G * m);
+            L.res_bytes = align256(sizeof(Bits) * n_res);
+            L.res_cost_bytes = align256(sizeof(int64_t) * n_res);
+        }
+        off += L.ctl_bytes + L.slot_bytes + L.res_bytes + L.res_cost_bytes;
+    }
+    L.total = off;
+    return L;
+}
+
+extern "C" vns_status vns_workspace_bytes(const vns_ctx *c, uint32_t flags, size_t *bytes) {
+    if (!c || !bytes) return fail(nullptr, VNS_EINVAL, "null argument");
+    if (flags & ~(VNS_WS_RUN | VNS_WS_EVAL | VNS_WS_EVAL_PRICES))
+        return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown workspace flags");
+    *bytes = ws_layout(c, flags).total;
+    return VNS_OK;
+}
+
+extern "C" vns_status vns_bind_workspace(vns_ctx *c, void *p, size_t bytes, uint32_t flags) {
+    VNS_LIVE(c);
+    if (flags & ~(VNS_WS_RUN | VNS_WS_EVAL | VNS_WS_EVAL_PRICES)) return fail(c, VNS_EINVAL, "unknown workspace flags");
+    VNS_HIP(c, hipStreamSynchronize(c->stream));   // no running call still uses the previous buffer
+    drop_graph(c);
+    c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = -1;   // the cached table lives in one of them
+    if (!p || flags == 0) {
+        c->ws = nullptr;
+        c->ws_bytes = 0;
+        c->ws_flags = 0;
+        return VNS_OK;
+    }
+    if (((uintptr_t)p & 255u) != 0) return fail(c, VNS_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < ws_layout(c, flags).total) return fail(c, VNS_EINVAL, "workspace smaller than vns_workspace_bytes");
+    c->ws = (char *)p;
+    c->ws_bytes = bytes;
+    c->ws_flags = flags;
+    return VNS_OK;
+}
+
+// The bound workspace's layout for its flags, or an error when the current options outgrew it.
+static vns_status ws_check(vns_ctx *c, WsLayout *L) {
+    *L = ws_layout(c, c->ws_flags);
+    if (L->total > c->ws_bytes)
+        return fail(c, VNS_EINVAL, "the bound workspace is smaller than this call needs under the current options: "
+                                   "query vns_workspace_bytes and rebind");
+    return VNS_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------
 // pricing
 // ---------------------------------------------------------------------------------------------------
 // Sums of the spread workgroup counters (waits for the stream).
@@ -623,11 +729,20 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     const int64_t cp_begin = first.cp0, n_cp = last.cp0 + last.K - first.cp0;
     const int64_t slot_begin = c->price_off[(size_t)g0];
     const int64_t n_slots = c->price_off[(size_t)(g0 + ng - 1)] + 4LL * last.K * last.T - slot_begin;
-    if (slot_price && (size_t)n_slots > c->slot_price_cap) {
+    const bool ws_tab = c->ws && (c->ws_flags & (VNS_WS_EVAL | VNS_WS_EVAL_PRICES));
+    const bool ws_price = c->ws && (c->ws_flags & VNS_WS_EVAL_PRICES);
+    WsLayout wl;
+    if (ws_tab) {
+        vns_status s = ws_check(c, &wl);
+        if (s != VNS_OK) return s;
+    }
+    int64_t *d_sp = ws_price ? reinterpret_cast<int64_t *>(c->ws + wl.price_off) : c->d_slot_price;
+    if (slot_price && !ws_price && (size_t)n_slots > c->slot_price_cap) {
         dfree(c->d_slot_price);
         c->slot_price_cap = 0;
         VNS_HIP(c, dmalloc(&c->d_slot_price, (size_t)n_slots));
         c->slot_price_cap = (size_t)n_slots;
+        d_sp = c->d_slot_price;
     }
     // workgroup table: for each run of up to eval_group consecutive chains of one instance, one workgroup
     // per product (incremental pricing: at most as many chains as the snapshots' LDS allows)
@@ -637,6 +752,7 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
                                                                               kSnapLdsMax / ((maxT + 1) * kSnapBytes)))
                                       : c->eval_group;
     const int64_t key[3] = {g0, ng, group};
+    EvalWg *d_tab = ws_tab ? reinterpret_cast<EvalWg *>(c->ws + wl.eval_off) : c->d_eval_wg;
     if (!(key[0] == c->eval_wg_key[0] && key[1] == c->eval_wg_key[1] && key[2] == c->eval_wg_key[2])) {
         std::vector<EvalWg> tab;
         int32_t g = g0;
@@ -658,11 +774,14 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
             }
             g += n;
         }
-        dfree(c->d_eval_wg);
         c->eval_wg_n = 0;
         c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = -1;
-        VNS_HIP(c, dmalloc(&c->d_eval_wg, tab.size()));
-        VNS_HIP(c, hipMemcpyAsync(c->d_eval_wg, tab.data(), sizeof(EvalWg) * tab.size(), hipMemcpyHostToDevice, c->stream));
+        if (!ws_tab) {
+            dfree(c->d_eval_wg);
+            VNS_HIP(c, dmalloc(&c->d_eval_wg, tab.size()));
+            d_tab = c->d_eval_wg;
+        }
+        VNS_HIP(c, hipMemcpyAsync(d_tab, tab.data(), sizeof(EvalWg) * tab.size(), hipMemcpyHostToDevice, c->stream));
         c->eval_wg_n = (int64_t)tab.size();
         for (int i = 0; i < 3; ++i) c->eval_wg_key[i] = key[i];
     }
@@ -674,7 +793,7 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     ea.cur = c->d_cur;
     ea.cur_cost = c->d_cur_cost;
     ea.cstate = c->d_cs;
-    ea.slot_price = slot_price ? c->d_slot_price - slot_begin : nullptr;
+    ea.slot_price = slot_price ? d_sp - slot_begin : nullptr;
     ea.price_off = c->d_price_off;
     ea.prod_key = c->d_prod_key;
     ea.evals = c->d_evals;
@@ -682,16 +801,16 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     VNS_HIP(c, hipMemsetAsync(c->d_evals, 0, sizeof(unsigned long long) * counter_words(), c->stream));
     VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
     if (c->eval_inc)
-        VNS_HIP(c, launch_eval_inc(ea, c->d_eval_wg, c->eval_wg_n, (size_t)group * (size_t)(maxT + 1) * kSnapBytes,
+        VNS_HIP(c, launch_eval_inc(ea, d_tab, c->eval_wg_n, (size_t)group * (size_t)(maxT + 1) * kSnapBytes,
                                    c->stream));
     else
-        VNS_HIP(c, launch_eval(ea, c->d_eval_wg, c->eval_wg_n, c->stream));
+        VNS_HIP(c, launch_eval(ea, d_tab, c->eval_wg_n, c->stream));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     ChainBestArgs cb{c->d_chains, c->d_cs, c->d_cur_cost, c->d_prod_key, c->d_prod_price, c->d_prod_slot,
                      c->d_best, c->d_best_slot, g0};
     VNS_HIP(c, launch_chain_best(cb, ng, c->stream));
     if (slot_price)
-        VNS_HIP(c, hipMemcpyAsync(slot_price, c->d_slot_price, sizeof(int64_t) * (size_t)n_slots, hipMemcpyDeviceToHost, c->stream));
+        VNS_HIP(c, hipMemcpyAsync(slot_price, d_sp, sizeof(int64_t) * (size_t)n_slots, hipMemcpyDeviceToHost, c->stream));
     if (prod_best)
         VNS_HIP(c, hipMemcpyAsync(prod_best, c->d_prod_price + cp_begin, sizeof(int64_t) * (size_t)n_cp, hipMemcpyDeviceToHost, c->stream));
     if (prod_best_slot)
@@ -740,6 +859,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     ra.work = c->d_work;
     ra.work_cost = c->d_work_cost;
     ra.cstate = c->d_cs;
+    ra.best = c->d_bestx;
     ra.trace = c->trace ? c->d_trace : nullptr;
     ra.it0 = c->d_iter;
     ra.seed = c->seed;
@@ -804,7 +924,20 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, coop_learned));
     }
     c->stats.last_run_spec_iters = coop && !best ? m : 1;
-    if (coop) {
+    CoopCtl *d_ctl = c->d_coop_ctl;
+    CoopSlot *d_slot = c->d_coop_slot;
+    Bits *d_res = c->d_coop_res;
+    int64_t *d_res_cost = c->d_coop_res_cost;
+    if (coop && c->ws && (c->ws_flags & VNS_WS_RUN)) {   // from the caller's workspace
+        WsLayout wl;
+        vns_status s = ws_check(c, &wl);
+        if (s != VNS_OK) return s;
+        char *base = c->ws + wl.run_off;
+        d_ctl = reinterpret_cast<CoopCtl *>(base);
+        d_slot = reinterpret_cast<CoopSlot *>(base + wl.ctl_bytes);
+        d_res = reinterpret_cast<Bits *>(base + wl.ctl_bytes + wl.slot_bytes);
+        d_res_cost = reinterpret_cast<int64_t *>(base + wl.ctl_bytes + wl.slot_bytes + wl.res_bytes);
+    } else if (coop) {
         const size_t n_res = (size_t)G * (size_t)m * (size_t)max_K;
         if ((size_t)G > c->coop_cap_ctl) {
             dfree(c->d_coop_ctl);
@@ -826,17 +959,23 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
             VNS_HIP(c, dmalloc(&c->d_coop_res_cost, n_res));
             c->coop_cap_res = n_res;
         }
-        VNS_HIP(c, hipMemsetAsync(c->d_coop_ctl, 0, sizeof(CoopCtl) * (size_t)G, c->stream));
+        d_ctl = c->d_coop_ctl;
+        d_slot = c->d_coop_slot;
+        d_res = c->d_coop_res;
+        d_res_cost = c->d_coop_res_cost;
+    }
+    if (coop) {
+        VNS_HIP(c, hipMemsetAsync(d_ctl, 0, sizeof(CoopCtl) * (size_t)G, c->stream));
         // the slots' round stamps: one left by an earlier launch must not match a round of this one
-        VNS_HIP(c, hipMemsetAsync(c->d_coop_slot, 0, sizeof(CoopSlot) * (size_t)(G * m), c->stream));
+        VNS_HIP(c, hipMemsetAsync(d_slot, 0, sizeof(CoopSlot) * (size_t)(G * m), c->stream));
         ra.state_off = -1;
         ra.coop_m = m;
         ra.coop_xcd = G % 8 == 0;
         ra.coop_kmax = (int32_t)max_K;
-        ra.coop_ctl = c->d_coop_ctl;
-        ra.coop_slot = c->d_coop_slot;
-        ra.coop_res = c->d_coop_res;
-        ra.coop_res_cost = c->d_coop_res_cost;
+        ra.coop_ctl = d_ctl;
+        ra.coop_slot = d_slot;
+        ra.coop_res = d_res;
+        ra.coop_res_cost = d_res_cost;
         ra.coop_wait_ticks = c->coop_wait_ticks;
         ra.best_of = best ? 1 : 0;
         ra.best_literal = c->best_literal;
@@ -926,14 +1065,16 @@ extern "C" vns_status vns_get_costs(vns_ctx *c, int64_t *F, int64_t *F_best) {
     return VNS_OK;
 }
 
-extern "C" vns_status vns_get_solution(vns_ctx *c, int32_t chain, uint8_t *zM, uint8_t *zR) {
+extern "C" vns_status vns_get_solution(vns_ctx *c, int32_t chain, int32_t which, uint8_t *zM, uint8_t *zR) {
     VNS_LIVE(c);
     vns_status s = check_chain(c, chain);
     if (s != VNS_OK) return s;
+    if (which != VNS_SOLUTION_CURRENT && which != VNS_SOLUTION_BEST) return fail(c, VNS_EINVAL, "which must be 0 or 1");
     if (!zM || !zR) return fail(c, VNS_EINVAL, "NULL output");
     const ChainInfo &ci = c->chains[(size_t)chain];
     std::vector<Bits> b((size_t)ci.K);
-    VNS_HIP(c, hipMemcpyAsync(b.data(), c->d_cur + ci.cp0, sizeof(Bits) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
+    const Bits *src = (which == VNS_SOLUTION_BEST ? c->d_bestx : c->d_cur) + ci.cp0;
+    VNS_HIP(c, hipMemcpyAsync(b.data(), src, sizeof(Bits) * (size_t)ci.K, hipMemcpyDeviceToHost, c->stream));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     for (int32_t k = 0; k < ci.K; ++k)
         for (int32_t t = 0; t < ci.T; ++t) {
@@ -965,7 +1106,8 @@ extern "C" vns_status vns_set_unit_costs(vns_ctx *c, const int32_t *pM, const in
     drop_graph(c);
     VNS_HIP(c, hipMemcpyAsync(c->d_prod, prod.data(), sizeof(ProdParams) * prod.size(), hipMemcpyHostToDevice, c->stream));
     // every chain's costs from its current solution, as at creation: F = best = the new objective, k = 1
-    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs, 0};
+    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs,
+                c->d_bestx, 0};
     VNS_HIP(c, launch_init(ia, (int)c->chains.size(), c->stream));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     c->prod_host = prod;
@@ -973,7 +1115,8 @@ extern "C" vns_status vns_set_unit_costs(vns_ctx *c, const int32_t *pM, const in
 }
 
 static vns_status reinit_chain(vns_ctx *c, int32_t chain) {
-    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs, chain};
+    InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs,
+                c->d_bestx, chain};
     VNS_HIP(c, launch_init(ia, 1, c->stream));
     return VNS_OK;
 }
@@ -1044,6 +1187,14 @@ extern "C" int64_t vns_num_chains(const vns_ctx *c) { return c ? (int64_t)c->cha
 
 extern "C" const char *vns_last_error(const vns_ctx *c) {
     return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" vns_status vns_test_inject_failure(int32_t kind, int32_t countdown) {
+    if (countdown < 0) return fail(nullptr, VNS_EINVAL, "negative countdown");
+    if (kind == VNS_INJECT_ALLOC) g_inject_alloc = countdown;
+    else if (kind == VNS_INJECT_DEVICE) g_inject_device = countdown;
+    else return fail(nullptr, VNS_EINVAL, "unknown injection kind");
+    return VNS_OK;
 }
 
 // ---------------------------------------------------------------------------------------------------

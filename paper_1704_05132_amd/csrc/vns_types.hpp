@@ -72,7 +72,8 @@ struct ChainState {
     int32_t k;      // shake size for the next iteration
     int32_t lopt;   // 1 when every product of x is known to be a VND local optimum
     int32_t err;    // nonzero if a VND exceeded kMaxPasses (cannot happen with a consistent decode)
-    int32_t pad;
+    int32_t bsync;  // 1 when the chain's best-solution rows hold x itself (so a cheaper x updates them
+                    // product by product); 0 after x moved to a worse solution (best-of-G as printed)
     int64_t nb_evals;   // learned mode: neighbourhood evaluations during the last run
     int64_t fallbacks;  //   and how many of them priced the whole neighbourhood
     int64_t discarded;  // speculative iterations: move-evaluations of iterations computed and thrown away
@@ -92,6 +93,7 @@ struct RunArgs {
     Bits *work;
     int64_t *work_cost;
     ChainState *cstate;
+    Bits *best;             // [sum over chains of K] the chain's best solution so far (objective F_best)
     Record *trace;          // [G][iters] or nullptr
     const int64_t *it0;     // device iteration counter: the first iteration of this launch
     uint64_t seed;

@@ -24,6 +24,9 @@ OPT_LEARNED, OPT_LOG, OPT_SPECULATE, OPT_SPEC_WAVES, OPT_STATE_LDS, OPT_VND_MEMO
 OPT_SPEC_ITERS, OPT_BEST_OF, OPT_BEST_OF_LITERAL, OPT_EVAL_INCREMENTAL = 15, 16, 17, 18
 MLP_PARAMS, MLP_FEATURES = 5313, 16
 ALL_CHAINS = -1
+SOLUTION_CURRENT, SOLUTION_BEST = 0, 1
+WS_RUN, WS_EVAL, WS_EVAL_PRICES = 1, 2, 4
+INJECT_ALLOC, INJECT_DEVICE = 1, 2
 PRICE_INF = np.iinfo(np.int64).max
 T_MAX = 128
 
@@ -41,11 +44,13 @@ SIGNATURES = {
     "vns_set_unit_costs": (_c.c_int, [_P, _P, _P]),
     "vns_get_option": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int64)]),
     "vns_bind_stream": (_c.c_int, [_P, _P]),
+    "vns_workspace_bytes": (_c.c_int, [_P, _c.c_uint32, _c.POINTER(_c.c_size_t)]),
+    "vns_bind_workspace": (_c.c_int, [_P, _P, _c.c_size_t, _c.c_uint32]),
     "vns_eval_neighbourhood": (_c.c_int, [_P, _c.c_uint32, _c.c_int32, _P, _P, _P, _P, _P]),
     "vns_run": (_c.c_int, [_P, _c.c_int32]),
     "vns_get_cost": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64)]),
     "vns_get_costs": (_c.c_int, [_P, _P, _P]),
-    "vns_get_solution": (_c.c_int, [_P, _c.c_int32, _P, _P]),
+    "vns_get_solution": (_c.c_int, [_P, _c.c_int32, _c.c_int32, _P, _P]),
     "vns_set_solution": (_c.c_int, [_P, _c.c_int32, _P, _P]),
     "vns_get_trajectory": (_c.c_int, [_P, _c.c_int32, _P, _c.c_int64, _c.POINTER(_c.c_int64)]),
     "vns_get_stats": (_c.c_int, [_P, _P]),
@@ -61,6 +66,7 @@ SIGNATURES = {
     "vns_eval_learned": (_c.c_int, [_P, _c.c_uint32, _c.c_int32, _c.c_int32, _P, _P, _P, _P, _P]),
     "vns_num_chains": (_c.c_int64, [_P]),
     "vns_last_error": (_c.c_char_p, [_P]),
+    "vns_test_inject_failure": (_c.c_int, [_c.c_int32, _c.c_int32]),
 }
 
 
@@ -100,6 +106,14 @@ def lib() -> ctypes.CDLL:
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def inject_failure(kind: int, countdown: int):
+    """vns_test_inject_failure: make the countdown-th device allocation (INJECT_ALLOC) or call on a live
+    context (INJECT_DEVICE) from now fail, on this thread; 0 clears."""
+    st = lib().vns_test_inject_failure(int(kind), int(countdown))
+    if st != VNS_OK:
+        raise VNSError(st, lib().vns_last_error(None).decode())
 
 
 def _i32(a):
@@ -194,6 +208,22 @@ class Context:
         raw = None if stream is None else (stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
         self._check(lib().vns_bind_stream(self.h, ctypes.c_void_p(raw)))
 
+    def workspace_bytes(self, flags: int) -> int:
+        n = ctypes.c_size_t()
+        self._check(lib().vns_workspace_bytes(self.h, int(flags), ctypes.byref(n)))
+        return int(n.value)
+
+    def bind_workspace(self, buf, flags: int):
+        """Bind caller-owned device memory (a torch tensor on the context's device, or None to unbind) as the
+        workspace of the calls in `flags`; the tensor must stay alive while bound."""
+        if buf is None:
+            self._check(lib().vns_bind_workspace(self.h, None, 0, 0))
+            self._ws = None
+            return
+        nbytes = buf.numel() * buf.element_size()
+        self._check(lib().vns_bind_workspace(self.h, ctypes.c_void_p(buf.data_ptr()), nbytes, int(flags)))
+        self._ws = buf
+
     @property
     def n_chains(self) -> int:
         return int(lib().vns_num_chains(self.h))
@@ -202,18 +232,20 @@ class Context:
         return self.instances[chain // self.chains_per_inst]
 
     # -- API -----------------------------------------------------------------------------------------
-    def eval_neighbourhood(self, nb_mask: int = 7, chain: int = ALL_CHAINS, slot_prices: bool = True):
-        """Exact prices of every move; returns dict(slot_price, prod_best, prod_best_slot, best, best_slot)."""
+    def eval_neighbourhood(self, nb_mask: int = 7, chain: int = ALL_CHAINS, slot_prices: bool = True,
+                           prod_best: bool = True):
+        """Exact prices of every move; returns dict(slot_price, prod_best, prod_best_slot, best, best_slot).
+        slot_prices / prod_best = False pass NULL for those outputs (their entries are then None)."""
         chains = range(self.n_chains) if chain == ALL_CHAINS else [chain]
-        n_slots = sum(4 * self.chain_instance(g).K * self.chain_instance(g).T for g in chains)
-        n_prod = sum(self.chain_instance(g).K for g in chains)
+        n_slots = sum(4 * self.chain_instance(g).K * self.chain_instance(g).T for g in chains) if slot_prices else 0
+        n_prod = sum(self.chain_instance(g).K for g in chains) if prod_best else 0
         sp = np.empty(n_slots, np.int64) if slot_prices else None
-        pb = np.empty(n_prod, np.int64)
-        ps = np.empty(n_prod, np.int32)
+        pb = np.empty(n_prod, np.int64) if prod_best else None
+        ps = np.empty(n_prod, np.int32) if prod_best else None
         b = np.empty(len(chains), np.int64)
         bs = np.empty(len(chains), np.int32)
-        self._check(lib().vns_eval_neighbourhood(self.h, int(nb_mask), int(chain),
-                                                 _ptr(sp) if sp is not None else None, _ptr(pb), _ptr(ps), _ptr(b),
+        opt = lambda a: _ptr(a) if a is not None else None
+        self._check(lib().vns_eval_neighbourhood(self.h, int(nb_mask), int(chain), opt(sp), opt(pb), opt(ps), _ptr(b),
                                                  _ptr(bs)))
         return dict(slot_price=sp, prod_best=pb, prod_best_slot=ps, best=b, best_slot=bs)
 
@@ -232,11 +264,12 @@ class Context:
         self._check(lib().vns_get_costs(self.h, _ptr(F), _ptr(Fb)))
         return F, Fb
 
-    def solution(self, chain: int):
+    def solution(self, chain: int, which: int = SOLUTION_CURRENT):
+        """(zM, zR) [K, T] uint8 of the current solution, or of the best one so far (which = SOLUTION_BEST)."""
         inst = self.chain_instance(chain)
         zM = np.empty((inst.K, inst.T), np.uint8)
         zR = np.empty((inst.K, inst.T), np.uint8)
-        self._check(lib().vns_get_solution(self.h, int(chain), _ptr(zM), _ptr(zR)))
+        self._check(lib().vns_get_solution(self.h, int(chain), int(which), _ptr(zM), _ptr(zR)))
         return zM, zR
 
     def set_solution(self, chain: int, zM, zR):
