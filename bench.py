@@ -1,29 +1,41 @@
 #!/usr/bin/env python3
-"""Benchmark of the MI355X lot-sizing VNS: exact move-evaluations per second.
+"""Benchmark of the MI355X lot-sizing VNS: exact move-evaluations per second, and time to the plain
+method's best cost, learned vs plain.
 
-Workload: one synthetic instance of 100 products x 52 periods (demand U{0..200}, returns floor(D*U(0.2,0.8)),
-setup costs U{200..2000}, holding hM U{2..6}, hR U{1..hM}; seed 2), 64 independent Philox chains, neighbourhoods
-flip zM, flip zR, shift; shake sizes 1..5.  One step = one GVNS iteration (shake, VND, acceptance) of all 64
-chains; the K timed steps are one vns_run(K) launch on a fresh context starting from the initial solution,
-so the timed region is exactly the workload's first K iterations.  Inputs are resident in HBM before timing.
+Workload (default): the learned + batched set, 1024 synthetic instances with K ~ U{100..1000} products and
+T in {52, 104} periods (demand U{0..200}, returns floor(D * U(0.1, 0.9)), setup costs U{200..2000}, holding
+hM U{2..6}, hR U{1..hM}; instance i drawn from SeedSequence([5, i])), 16 Philox chains each: 16,384 chains,
+~2.8e9 move slots per full sweep, all resident in HBM.  It is the largest workload that fits one GPU.
 
-Prints one JSON line.  Extra fields: the full-neighbourhood sweep of all chains (the pricing kernel alone),
-the dominant kernel's roofline, the CPU oracle timed on this host on a bounded sample, and
-`time_to_plain_best`: the device time the learned search (a scorer trained on moves logged on disjoint
-instances ranks the moves, the best-ranked tenth is priced exactly, the whole neighbourhood when none of them
-improves) needs to reach the plain search's best cost on the same instance, seeds and chains, beside the
-plain search's own time to it, with the scorer's and the training's rates; `best_of`: the best-of-4 search
-of Algorithm 2 (4 shakes of x per iteration, the minimum kept; in the GVNS form and as printed) on the same
-chains and iterations, with its time to the plain search's best cost.  --workload batched_4096 runs the
-4096-instance batch (K ~ U{10..200}, T in {12, 24, 52}, 8 chains each) in one launch instead;
---workload learned_batched_1024 the 1024-instance learned + batched set (K ~ U{100..1000}, T in {52, 104},
-returns U(0.1, 0.9), 16 chains each).
+One step = one exact sweep: every move of the neighbourhoods flip zM, flip zR and shift for every chain
+(the pricing kernel k_eval), followed by each chain's lexicographic (price, slot) argmin (k_chain_best),
+whose results are copied to the host.  The sweeps run on the states the plain GVNS search reached after the
+workload's 5000 iterations (local optima, as in the VND's last passes).  `value` = move-evaluations of the
+K timed steps / their device time (HIP events on the stream the kernels run on); inputs are resident before
+the timed region starts.
+
+Beside it, on the same GPU in the same run:
+  * `time_to_plain_best`: the plain search runs the workload's 5000 iterations (launches of --chunk); per
+    instance its best cost over the chains is the target.  The learned search (a scorer trained on moves the
+    search logged on 16 disjoint instances ranks each neighbourhood's moves, the best-ranked 10% are priced
+    exactly, the whole neighbourhood when none of them improves) runs on the same instances, seeds and chains
+    until every instance reaches its target.  Device times of both, the scorer's and the training's rates.
+  * `search`: the plain GVNS search's exact move-evaluations/s over the configured iterations: the 100 x 52
+    instance with 64 chains x 2000 iterations in one launch (with its kernel's roofline), the 4096-instance
+    batch with 8 chains x 1000 iterations in one launch, and the 1024-instance set's 5000 iterations.
+  * `sweeps`: the same step on the 4096-instance batch (8 chains, after its 1000 iterations) and on the
+    100 x 52 instance (64 chains, after its 2000 iterations).
+  * `time_to_plain_best_100x52`: the same comparison on the 100 x 52 instance (64 chains, 2000 iterations).
+  * `cpu_baseline`: the CPU oracle's exact sweep (every move of the three neighbourhoods priced by its
+    look-ahead decode) on a sample of the workload's instances, one thread and every host thread.
+--workload paper_300x52 adds the Table-1-shaped comparison of the searches on 108 instances of 300 x 52.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import statistics
 import sys
 import time
@@ -32,21 +44,24 @@ from concurrent.futures import ThreadPoolExecutor
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# int32 VALU peak of MI355X for the decode's own operation mix.  256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz give
-# 39.3e12 lane-slots/s.  Of the 14 operations of a period-step, 10 (bfe x2, bfi x4, min, mad x2, and_or) take a
-# lane-slot each and 4 (add, sub x2, the bitop3 of the no-setup mask) take half of one: gfx950 issues that
-# class at twice the rate (measured on the device: ~114-119 against ~62.5 lane-ops per CU per clock).
+# int32 VALU peak of MI355X for the decode's own operation mix, from unit counts and clock: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz = 39.3e12 lane-slots/s.  Of the 14 operations of a period-step, 10 (bfe x2, bfi x4, min,
+# mad x2, and_or) take a lane-slot each and 4 (add, sub x2, the bitop3 of the no-setup mask) take half of one:
+# gfx950 issues that class at twice the rate (the probe in csrc/valu_probe.hip, `bench.py --valu-probe`).
 # 12 lane-slots per period-step make the peak 3.28e12 period-steps/s, 45.9e12 of these operations per second.
 OPS_PER_PERIOD_STEP = 14     # operations of one period-step of the forward decode
 LANE_SLOTS_PER_STEP = 12
-VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9 * OPS_PER_PERIOD_STEP / LANE_SLOTS_PER_STEP
+CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
+VALU_PEAK_OPS = CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ * OPS_PER_PERIOD_STEP / LANE_SLOTS_PER_STEP
 TUNE_FILE = os.path.join(ROOT, "paper_1704_05132_amd", "tune_table.json")
-# best-of-G search (Algorithm 2) measured beside the plain one: shakes per iteration
-BEST_OF_G = 4
-LEARNED_SPEC_M = 8   # speculative iterations of the learned search (4 wavefronts per workgroup)
+BEST_OF_G = 4                # best-of-G search (Algorithm 2) measured beside the plain one: shakes per iteration
+LEARNED_SPEC_M = 8           # speculative iterations of the learned search (4 wavefronts per workgroup)
 # learned scorer: 2 x (16*64 + 64*64 + 64) flops per scored move; dense bfloat16 matrix-core peak of MI355X
 MLP_FLOP_PER_ROW = 2 * (16 * 64 + 64 * 64 + 64)
 BF16_PEAK_TFLOPS = 2500.0
+METRIC = "exact move-evals/s (int64 cost) + time-to-plain-best-cost, learned vs plain"
+SWEEP_LAUNCH = "k_eval: every chain, neighbourhoods flip zM + flip zR + shift, tuned chains per workgroup"
+SEARCH_LAUNCH = "search: every chain, the workload's iterations in one launch, tuned launch shape"
 
 
 def kernel_source_hash():
@@ -61,112 +76,334 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it is current."""
+def measured_traffic(kernel, workload, launch):
+    """HBM bytes per launch of `kernel` in `launch` on `workload`, from the committed rocprofv3 counter summary
+    (profiles/traffic_<workload>.json), if it was taken on the current kernels."""
     try:
         with open(os.path.join(ROOT, "profiles", f"traffic_{workload}.json")) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha256") != kernel_source_hash() or kernel not in t.get("kernels", {}):
+    if t.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    return t["kernels"][kernel]["bytes_per_launch"]
+    e = t.get("launches", {}).get(launch, {}).get(kernel)
+    return None if e is None else e["bytes_per_launch"]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="plain_100x52", choices=["plain_100x52", "plain_10x12", "batched_4096",
-                                                                   "learned_batched_1024", "paper_300x52"])
-    ap.add_argument("--quality-ms", type=float, default=2000.0,
-                    help="paper_300x52: device time each search arm of the quality table gets")
-    ap.add_argument("--graph", action="store_true", help="run the search through a captured HIP graph")
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--sweep-reps", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--workload", default="learned_batched_1024",
+                    choices=["learned_batched_1024", "batched_4096", "plain_100x52", "paper_300x52"])
+    ap.add_argument("--steps", type=int, default=20, help="timed sweeps")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed sweeps before them")
+    ap.add_argument("--search-iters", type=int, default=None,
+                    help="iterations of the searches (default: the workload's own, 5000 / 1000 / 2000)")
+    ap.add_argument("--only-sweep", action="store_true",
+                    help="only the workload's search, as one launch, and the timed sweeps (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--print-source-hash", action="store_true")
-    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain time-to-best half")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the side measurements (neighbourhood skip, best-of-G, incremental sweep), so that the "
-                         "timed search launch is the only one of its kernel (for a profiler's per-kernel average)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain time-to-best halves")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0, help="target time of each oracle sample")
     ap.add_argument("--chunk", type=int, default=50, help="iterations per launch in the time-to-best runs")
-    ap.add_argument("--learned-permille", type=int, default=50, help="share of moves priced exactly (1/1000)")
-    ap.add_argument("--learned-train-instances", type=int, default=16)
+    ap.add_argument("--learned-permille", type=int, default=100, help="share of moves priced exactly (1/1000)")
     ap.add_argument("--learned-log-iters", type=int, default=200)
     ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--quality-ms", type=float, default=2000.0,
+                    help="paper_300x52: device time each search arm of the quality table gets")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration for profiling runs)")
+    ap.add_argument("--valu-probe", action="store_true", help="run the VALU issue-rate probe and print its JSON")
+    ap.add_argument("--print-source-hash", action="store_true")
     return ap.parse_args()
 
 
-def cpu_baseline(pairs, nb, target_s, label):
-    """The oracle, as it is, on this host: independent (instance, seed, chain) runs from iteration 0, one per
-    thread, each sized so that the sample takes about target_s."""
-    import oracle
-    threads = max(1, min(16, os.cpu_count() or 1, len(pairs)))
-    pairs = pairs[:threads]
-    inst, seed, chain = pairs[0]
-    probe = oracle.Chain(inst, seed, chain, nb)
+# ---------------------------------------------------------------------------------------------------------
+# helpers
+# ---------------------------------------------------------------------------------------------------------
+def host_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def new_ctx(vns, insts, w, stream, table, key, chains=None, trace=False, options=None):
+    """A context on the workload's instances with the tuned launch shape, then `options` over it."""
+    target = insts[0] if len(insts) == 1 else insts
+    c = vns.Context(target, seed=w["seed"], chains=chains or w["chains"], nb_list=w["nb"], trace=trace)
+    c.bind_stream(stream)
+    table.apply(c, key)
+    for opt, v in (options or {}).items():
+        c.set_option(opt, v)
+    return c
+
+
+def sweep_steps(torch, vns, ctx, stream, steps, warmup):
+    """`warmup` untimed, then `steps` timed exact sweeps of every chain (one step: pricing kernel, per-chain
+    argmin, results to the host).  Device time of the steps from HIP events on the stream, the pricing
+    kernel's own time per step from the library's events around it."""
+    for _ in range(warmup):
+        ctx.eval_neighbourhood(7, vns.ALL_CHAINS, slot_prices=False, prod_best=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    k_ms, evals, psteps = [], 0, 0
     t0 = time.perf_counter()
-    probe.run(4)
-    per_first4 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    probe.run(8)
-    per_iter = (time.perf_counter() - t0) / 8
-    iters = int(max(5, 4 + (target_s - per_first4) / max(per_iter, 1e-6)))
-
-    def one(p):
-        ch = oracle.Chain(p[0], p[1], p[2], nb)
-        ch.run(iters)
-        return ch.evals
-
-    t0 = time.perf_counter()
-    with ThreadPoolExecutor(threads) as ex:
-        evals = sum(ex.map(one, pairs))
-    dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "move-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{threads} chains x {iters} GVNS iterations of {label} from iteration 0, one chain per "
-                      f"thread ({evals} move-evaluations in {dt:.1f} s)"}
+    e0.record(stream)
+    for _ in range(steps):
+        ctx.eval_neighbourhood(7, vns.ALL_CHAINS, slot_prices=False, prod_best=False)
+        s = ctx.stats()
+        k_ms.append(s["last_eval_ms"])
+        evals += s["last_eval_evals"]
+        psteps += s["last_eval_period_steps"]
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    achieved = psteps * OPS_PER_PERIOD_STEP / (sum(k_ms) / 1e3) / 1e12
+    return {"steps": steps, "move_evals_per_step": evals // max(steps, 1), "device_ms": ms, "wall_s": wall,
+            "value": evals / (ms / 1e3), "unit": "move-evals/s", "kernel": "k_eval",
+            "kernel_ms_mean": sum(k_ms) / len(k_ms), "kernel_ms_median": statistics.median(k_ms),
+            "kernel_share": sum(k_ms) / ms, "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12,
+            "frac": achieved / (VALU_PEAK_OPS / 1e12)}
 
 
-def chunked_search(make_ctx, n_inst, chains, max_iters, chunk, targets=None, horizon_ms=None):
+def search_once(vns, ctx, iters):
+    """One launch of `iters` GVNS iterations of every chain; the search kernel's rate and roofline (the
+    evaluations the search consumed; speculative iterations thrown away are counted apart)."""
+    ctx.run(iters)
+    st = ctx.stats()
+    ms, evals = st["last_run_ms"], st["last_run_evals"]
+    spec_m, discarded = st["last_run_spec_iters"], st["last_run_discarded_evals"]
+    achieved = st["last_run_period_steps"] * OPS_PER_PERIOD_STEP / (ms / 1e3) / 1e12
+    executed = (evals + discarded) / evals if evals else 1.0
+    best = ctx.get_option(vns.OPT_BEST_OF)
+    return {"iters": iters, "kernel": "k_run_coop" if spec_m > 1 or best > 1 else "k_run", "kernel_ms": ms,
+            "move_evals": evals, "value": evals / (ms / 1e3), "unit": "move-evals/s",
+            "iterations_per_s": iters / (ms / 1e3), "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12,
+            "unit_achieved": "TOP/s", "frac": achieved / (VALU_PEAK_OPS / 1e12),
+            "speculative_iterations": spec_m, "discarded_move_evals": discarded,
+            "executed_over_consumed": executed, "executed_frac": achieved * executed / (VALU_PEAK_OPS / 1e12)}
+
+
+def chunked_search(make_ctx, n_inst, chains, max_iters, chunk, targets=None, horizon_ms=None, keep=False):
     """Run a fresh context in launches of `chunk` iterations.  Per instance, the best cost over its chains
     is tracked after every launch.  Stops once every instance is at or below `targets` (when given).
-    Returns a dict with the device ms and iterations at which all targets were reached (None if not), the
-    final per-instance bests, the total device ms, the per-launch history (ms, bests), and the share of
-    instances at their target when the device time first reached `horizon_ms`."""
+    Returns the device ms and iterations at which all targets were reached (None if not), the final
+    per-instance bests, the total device ms and evaluations, the per-launch history (ms, iterations, bests),
+    and the share of instances at their target when the device time first reached `horizon_ms`.  With `keep`
+    the context is returned open under "ctx"."""
     import numpy as np
     ctx = make_ctx()
-    ms, it, reached, hist, share_at = 0.0, 0, None, [], None
+    ms, it, evals, reached, hist, share_at = 0.0, 0, 0, None, [], None
     best = ctx.costs()[1].reshape(n_inst, chains).min(1)
     while it < max_iters:
         n = min(chunk, max_iters - it)
         ctx.run(n)
-        ms += ctx.stats()["last_run_ms"]
+        st = ctx.stats()
+        ms += st["last_run_ms"]
+        evals += st["last_run_evals"]
         it += n
         best = ctx.costs()[1].reshape(n_inst, chains).min(1)
-        hist.append((ms, best.copy()))
+        hist.append((ms, it, best.copy()))
         if targets is not None:
             if horizon_ms is not None and share_at is None and ms >= horizon_ms:
                 share_at = float(np.mean(best <= targets))
             if (best <= targets).all():
                 reached = (ms, it)
                 break
-    ctx.close()
-    return {"ms": reached[0] if reached else None, "iters": reached[1] if reached else it, "best": best,
-            "total_ms": ms, "hist": hist, "share_at_horizon": share_at}
+    out = {"ms": reached[0] if reached else None, "iters": reached[1] if reached else it, "best": best,
+           "total_ms": ms, "total_iters": it, "evals": evals, "hist": hist, "share_at_horizon": share_at}
+    if keep:
+        out["ctx"] = ctx
+    else:
+        ctx.close()
+    return out
 
 
-def paper_quality(args, vns, stream, insts, seed, nb):
-    """A table shaped like the paper's Table 1 on its benchmark shape (synthetic: 108 instances of 300
-    products x 52 periods): every search gets the same device time on all instances at once, with 8
-    workgroups per instance, and the best cost per instance is compared across searches.  The paper's serial
-    VND arm is not reproduced (its code is not available)."""
+LEARNED_SETUP = {
+    # evaluation workload -> (training workload, first training index, training instances, chains while logging)
+    "plain_100x52": ("learned_100x52", 100, 16, 16),
+    "learned_batched_1024": ("learned_batched_1024", 4096, 16, 4),
+}
+
+
+def learned_vs_plain(args, vns, stream, table, key, name, insts, w, plain):
+    """Time to the plain method's best cost, per instance: the plain search (`plain`, a chunked_search run over
+    the workload's iterations) vs the learned search (scorer trained on moves the search logged on disjoint
+    training instances), same instances, seeds and chains, this GPU."""
     import numpy as np
     from paper_1704_05132_amd.instances import workload
-    n = len(insts)
+    n_inst, chains, chunk, iters = len(insts), w["chains"], args.chunk, plain["total_iters"]
+
+    def make(options=None):
+        return new_ctx(vns, insts, w, stream, table, key, options=options)
+
+    B = plain["best"]
+    first = next(h for h in plain["hist"] if (h[2] <= B).all())
+    plain_ms, plain_it = first[0], first[1]
+
+    # training set: moves logged by the search on disjoint instances
+    tw, t0i, n_train, log_chains = LEARNED_SETUP[name]
+    train = [workload(tw, t0i + j) for j in range(n_train)]
+    t0 = time.perf_counter()
+    with vns.Context(train, seed=w["seed"], chains=log_chains, nb_list=w["nb"], trace=False,
+                     options={vns.OPT_LOG: 2_000_000}) as lg:
+        lg.bind_stream(stream)
+        lg.run(args.learned_log_iters)
+        log_ms = lg.stats()["last_run_ms"]
+        X, y = lg.move_log()
+    with make() as tr:
+        tr.mlp_init(7)
+        t1 = time.perf_counter()
+        loss = tr.mlp_train(X, y, epochs=args.learned_epochs, batch=4096, lr=2e-3, seed=11)
+        train_s = time.perf_counter() - t1
+        st = tr.stats()
+        train_dev_ms, train_rows = st["last_mlp_ms"], st["last_mlp_rows"]
+        params = tr.mlp_get()
+        # scorer alone: one launch over 2^20 feature rows (the logged moves, repeated)
+        Xs = np.resize(X, (1 << 20, X.shape[1])) if len(X) else np.zeros((1 << 20, 16), np.float32)
+        for _ in range(3):
+            tr.mlp_score(Xs)
+        st = tr.stats()
+        score_ms, score_rows = st["last_mlp_ms"], st["last_mlp_rows"]
+    collect_s = time.perf_counter() - t0 - train_s
+
+    def make_learned():
+        c = make({vns.OPT_LEARNED: args.learned_permille})
+        if c.get_option(vns.OPT_SPEC_ITERS) > 1:
+            # the learned kernel keeps the scorer's weights in registers (about 250 VGPRs, two wavefronts per
+            # SIMD), so its speculative launch takes two 4-wavefront workgroups per compute unit
+            c.set_option(vns.OPT_RUN_WAVES, 4)
+            c.set_option(vns.OPT_SPEC_ITERS, LEARNED_SPEC_M)
+        c.mlp_set(params)
+        return c
+
+    lrn = chunked_search(make_learned, n_inst, chains, 2 * iters, chunk, targets=B, horizon_ms=plain["total_ms"])
+    if lrn["share_at_horizon"] is None:   # reached (or stopped) before the plain run's total time
+        lrn["share_at_horizon"] = float(np.mean(lrn["best"] <= B))
+    out = {
+        "instances": n_inst, "chains": chains, "iters": iters, "chunk_iters": chunk,
+        "plain_ms_to_best": plain_ms, "plain_iters_to_best": plain_it, "plain_total_ms": plain["total_ms"],
+        "learned_ms_to_plain_best": lrn["ms"], "learned_iters": lrn["iters"], "learned_reached": lrn["ms"] is not None,
+        "learned_share_at_plain_total_ms": lrn["share_at_horizon"],
+        "speedup": (plain_ms / lrn["ms"]) if lrn["ms"] else None,
+        "permille_priced": args.learned_permille,
+        "training": {"instances": len(train), "logged_moves": int(len(y)),
+                     "improving_share": float(np.mean(y < 0)) if len(y) else 0.0,
+                     "log_search_ms": log_ms, "collect_s": collect_s, "epochs": args.learned_epochs,
+                     "train_s": train_s, "final_loss": loss, "device_ms": train_dev_ms,
+                     "rows_per_s": train_rows / (train_dev_ms / 1e3) if train_dev_ms else None,
+                     "tflops": (train_rows * 3 * MLP_FLOP_PER_ROW / (train_dev_ms / 1e3) / 1e12
+                                if train_dev_ms else None)},
+        "scorer": {"kernel": "k_mlp_score", "rows": score_rows, "ms": score_ms,
+                   "rows_per_s": score_rows / (score_ms / 1e3), "bound": "mfma",
+                   "achieved": score_rows * MLP_FLOP_PER_ROW / (score_ms / 1e3) / 1e12, "peak": BF16_PEAK_TFLOPS,
+                   "unit": "TFLOP/s",
+                   "frac": score_rows * MLP_FLOP_PER_ROW / (score_ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
+                   "flop_per_row": MLP_FLOP_PER_ROW},
+        "note": "device time of the search launches only; scorer training is reported separately",
+    }
+    if n_inst == 1:
+        out["plain_best_F"] = int(B[0])
+        out["learned_best_F"] = int(lrn["best"][0])
+    else:
+        out["plain_best_F_sum"] = int(B.sum())
+        out["learned_best_F_sum"] = int(lrn["best"].sum())
+    return out
+
+
+def cpu_baseline(insts, w, name, target_s):
+    """The oracle as it is, on this host: its exact sweep (orc_price_all, every move of the three
+    neighbourhoods) of random feasible setup patterns of the workload's instances, first on one thread, then
+    one instance per thread on every host thread (up to 16).  Each sample is sized to about target_s."""
+    import numpy as np
+    import oracle
+    from paper_1704_05132_amd.instances import random_pattern
+    rng = np.random.default_rng(12345)
+    order = rng.permutation(len(insts))
+    nthreads = host_threads()
+
+    def one(i, reps, seed):
+        inst = insts[i]
+        zM, zR = random_pattern(inst, np.random.default_rng(seed))
+        n = 0
+        for _ in range(reps):
+            n += oracle.price_all(inst, zM, zR, 7)[1]
+        return n
+
+    # one thread: instances in the sampled order until target_s has passed
+    t0, n1, used = time.perf_counter(), 0, 0
+    while time.perf_counter() - t0 < target_s and used < len(order):
+        n1 += one(int(order[used]), 1, used)
+        used += 1
+    dt1 = time.perf_counter() - t0
+    rate1 = n1 / dt1
+    # every thread: one instance each, repeated so that each thread runs about target_s
+    per_sweep = dt1 / max(used, 1)
+    reps = max(1, int(target_s / max(per_sweep, 1e-6)))
+    picks = [int(order[j % len(order)]) for j in range(nthreads)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nthreads) as ex:
+        nN = sum(ex.map(lambda a: one(a[1], reps, 1000 + a[0]), enumerate(picks)))
+    dtN = time.perf_counter() - t0
+    Ks = [insts[i].K for i in picks]
+    return {"value": nN / dtN, "unit": "move-evals/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"oracle exact sweeps (flip zM, flip zR, shift) of random feasible patterns of {name} "
+                      f"instances: {nthreads} threads x {reps} sweeps of one instance each (K {min(Ks)}..{max(Ks)}), "
+                      f"{nN} move-evaluations in {dtN:.1f} s",
+            "single_thread": {"value": rate1, "instances": used, "move_evals": n1, "seconds": dt1},
+            "nproc": os.cpu_count(), "threads_available": nthreads, "cpu_model": cpu_model()}
+
+
+def valu_probe():
+    """Issue rates of the decode's integer operations (csrc/valu_probe.hip), as lane-operations per CU per
+    nominal 2.4 GHz clock, and the decode step's rate as period-steps and operations per second."""
+    import ctypes
+    import torch  # noqa: F401  (one HIP runtime in the process)
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_1704_05132_amd", "libvaluprobe.so"))
+    L.valu_probe_name.restype = ctypes.c_char_p
+    L.valu_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)]
+    grid, iters = 8192, 4096     # 4-wave workgroups: 32 waves per SIMD over the run, 8 resident at a time
+    out = {"grid_workgroups": grid, "workgroup": 256, "iters": iters, "clock_hz": CLOCK_HZ, "cu": CU, "ops": {}}
+    for op in range(L.valu_probe_count()):
+        best = None
+        for _ in range(3):
+            ms, n = ctypes.c_double(), ctypes.c_double()
+            rc = L.valu_probe_run(op, grid, iters, ctypes.byref(ms), ctypes.byref(n))
+            if rc != 0:
+                raise RuntimeError(f"valu probe {op} failed: hip error {rc}")
+            best = ms.value if best is None else min(best, ms.value)
+        per_cu_clk = n.value / (best / 1e3) / CU / CLOCK_HZ
+        nm = L.valu_probe_name(op).decode()
+        out["ops"][nm] = {"ms": best, "lane_ops": n.value, "lane_ops_per_cu_per_clock": per_cu_clk}
+        if nm == "decode_step":
+            out["ops"][nm]["period_steps_per_s"] = n.value / (best / 1e3)
+            out["ops"][nm]["ops_per_s"] = n.value / (best / 1e3) * OPS_PER_PERIOD_STEP
+            out["ops"][nm]["frac_of_derived_peak"] = n.value / (best / 1e3) * OPS_PER_PERIOD_STEP / VALU_PEAK_OPS
+    out["derived_peak_ops_per_s"] = VALU_PEAK_OPS
+    return out
+
+
+def paper_quality(args, vns, stream, insts, w):
+    """A table shaped like the paper's Table 1 on its benchmark shape (synthetic: 108 instances of 300
+    products x 52 periods): every search gets the same device time on all instances at once, with 8
+    workgroups per instance, and the best cost per instance is compared across searches."""
+    import numpy as np
+    from paper_1704_05132_amd.instances import workload
+    n, seed, nb = len(insts), w["seed"], w["nb"]
 
     def ctx_of(chains, options):
         c = vns.Context(insts, seed=seed, chains=chains, nb_list=nb, trace=False, options=options)
@@ -218,108 +455,10 @@ def paper_quality(args, vns, stream, insts, seed, nb):
     return out
 
 
-LEARNED_SETUP = {
-    # evaluation workload -> (training workload, first training index, training instances, chains while logging)
-    "plain_100x52": ("learned_100x52", 100, 16, 16),
-    "learned_batched_1024": ("learned_batched_1024", 4096, 16, 4),
-}
-
-
-def learned_vs_plain(args, vns, stream, table, key, name, insts, seed, chains, nb):
-    """Time to the plain method's best cost, per instance: plain search vs the learned search (scorer
-    trained on moves the search logged on disjoint training instances), same instances, seeds and chains,
-    on this GPU."""
-    import numpy as np
-    from paper_1704_05132_amd.instances import workload
-    target = insts[0] if len(insts) == 1 else insts
-    n_inst, chunk = len(insts), args.chunk
-
-    def make(options=None):   # the tuned launch shape, then the given options over it
-        c = vns.Context(target, seed=seed, chains=chains, nb_list=nb, trace=False)
-        c.bind_stream(stream)
-        table.apply(c, key)
-        for opt, v in (options or {}).items():
-            c.set_option(opt, v)
-        return c
-
-    # plain: per-instance best after the workload's iterations, and the device time to first reach all
-    plain = chunked_search(make, n_inst, chains, args.steps, chunk)
-    B = plain["best"]
-    plain_ms = next(ms for ms, b in plain["hist"] if (b <= B).all())
-    plain_it = chunk * (1 + next(i for i, (_, b) in enumerate(plain["hist"]) if (b <= B).all()))
-
-    # the plain search with neighbourhoods not re-priced on an unchanged pattern: same moves, less work
-    pm = chunked_search(lambda: make({vns.OPT_VND_MEMO: 1}), n_inst, chains, args.steps, chunk, targets=B)
-
-    # training set: moves logged by the search on disjoint instances
-    tw, t0i, n_train, log_chains = LEARNED_SETUP[name]
-    train = [workload(tw, t0i + j) for j in range(min(args.learned_train_instances, n_train))]
-    t0 = time.perf_counter()
-    with vns.Context(train, seed=seed, chains=log_chains, nb_list=nb, trace=False,
-                     options={vns.OPT_LOG: 2_000_000}) as lg:
-        lg.bind_stream(stream)
-        lg.run(args.learned_log_iters)
-        log_ms = lg.stats()["last_run_ms"]
-        X, y = lg.move_log()
-    with make() as tr:
-        tr.mlp_init(7)
-        t1 = time.perf_counter()
-        loss = tr.mlp_train(X, y, epochs=args.learned_epochs, batch=4096, lr=2e-3, seed=11)
-        train_s = time.perf_counter() - t1
-        st = tr.stats()
-        train_dev_ms, train_rows = st["last_mlp_ms"], st["last_mlp_rows"]
-        params = tr.mlp_get()
-        # scorer alone: one launch over 2^20 feature rows (the logged moves, repeated)
-        Xs = np.resize(X, (1 << 20, X.shape[1])) if len(X) else np.zeros((1 << 20, 16), np.float32)
-        for _ in range(3):
-            tr.mlp_score(Xs)
-        st = tr.stats()
-        score_ms, score_rows = st["last_mlp_ms"], st["last_mlp_rows"]
-    collect_s = time.perf_counter() - t0 - train_s
-
-    def make_learned():
-        c = make({vns.OPT_LEARNED: args.learned_permille})
-        if c.get_option(vns.OPT_SPEC_ITERS) > 1:
-            # the learned kernel keeps the scorer's weights in registers (about 250 VGPRs, two wavefronts per
-            # SIMD), so its speculative launch takes two 4-wavefront workgroups per compute unit
-            c.set_option(vns.OPT_RUN_WAVES, 4)
-            c.set_option(vns.OPT_SPEC_ITERS, LEARNED_SPEC_M)
-        c.mlp_set(params)
-        return c
-
-    lrn = chunked_search(make_learned, n_inst, chains, 2 * args.steps, chunk, targets=B, horizon_ms=plain["total_ms"])
-    if lrn["share_at_horizon"] is None:   # reached (or stopped) before the plain run's total time
-        lrn["share_at_horizon"] = float(np.mean(lrn["best"] <= B))
-    out = {
-        "instances": n_inst, "chains": chains,
-        "plain_ms_to_best": plain_ms, "plain_iters_to_best": plain_it, "plain_total_ms": plain["total_ms"],
-        "plain_memo_ms_to_best": pm["ms"],
-        "learned_ms_to_plain_best": lrn["ms"], "learned_iters": lrn["iters"], "learned_reached": lrn["ms"] is not None,
-        "learned_share_at_plain_total_ms": lrn["share_at_horizon"],
-        "speedup": (plain_ms / lrn["ms"]) if lrn["ms"] else None,
-        "permille_priced": args.learned_permille, "chunk_iters": chunk,
-        "training": {"instances": len(train), "logged_moves": int(len(y)),
-                     "improving_share": float(np.mean(y < 0)) if len(y) else 0.0,
-                     "log_search_ms": log_ms, "collect_s": collect_s, "epochs": args.learned_epochs,
-                     "train_s": train_s, "final_loss": loss, "device_ms": train_dev_ms,
-                     "rows_per_s": train_rows / (train_dev_ms / 1e3) if train_dev_ms else None,
-                     "tflops": (train_rows * 3 * MLP_FLOP_PER_ROW / (train_dev_ms / 1e3) / 1e12
-                                if train_dev_ms else None)},
-        "scorer": {"kernel": "k_mlp_score", "rows": score_rows, "ms": score_ms,
-                   "rows_per_s": score_rows / (score_ms / 1e3), "bound": "mfma",
-                   "achieved": score_rows * MLP_FLOP_PER_ROW / (score_ms / 1e3) / 1e12, "peak": BF16_PEAK_TFLOPS,
-                   "unit": "TFLOP/s",
-                   "frac": score_rows * MLP_FLOP_PER_ROW / (score_ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
-                   "flop_per_row": MLP_FLOP_PER_ROW},
-        "note": "device time of the search launches only; scorer training is reported separately",
-    }
-    if n_inst == 1:
-        out["plain_best_F"] = int(B[0])
-        out["learned_best_F"] = int(lrn["best"][0])
-    else:
-        out["plain_best_F_sum"] = int(B.sum())
-        out["learned_best_F_sum"] = int(lrn["best"].sum())
-    return out
+def workload_insts(name):
+    from paper_1704_05132_amd.instances import WORKLOADS, workload
+    w = WORKLOADS[name]
+    return w, [workload(name, i) for i in range(w["n_inst"])]
 
 
 def main():
@@ -334,128 +473,88 @@ def main():
 
     import torch
     from paper_1704_05132_amd import autotune, vns
-    from paper_1704_05132_amd.instances import WORKLOADS, workload
 
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
-    name = args.workload
-    w = WORKLOADS[name]
-    insts = [workload(name, i) for i in range(w["n_inst"])]
-    target = insts[0] if len(insts) == 1 else insts
-    chains = w["chains"]
+    if args.valu_probe:
+        print(json.dumps(valu_probe()), flush=True)
+        return
     stream = torch.cuda.current_stream()
     table = autotune.TuneTable(TUNE_FILE)
-    key = autotune.signature(insts, chains)
+    name = args.workload
+    w, insts = workload_insts(name)
+    key = autotune.signature(insts, w["chains"])
+    iters = args.search_iters or w["iters"]
+    t_start = time.perf_counter()
 
-    def make(trace):
-        c = vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=trace,
-                        options={vns.OPT_GRAPH: 1} if args.graph else None)
-        c.bind_stream(stream)
-        table.apply(c, key)
-        return c
+    # --- the workload's plain search over its iterations, in launches of --chunk; the timed sweeps run on the
+    #     states it reached, and its per-instance bests are the learned search's targets ---
+    if args.only_sweep:   # one search launch (a profiler sees one dispatch of the search kernel)
+        plain = None
+        ctx = new_ctx(vns, insts, w, stream, table, key)
+        search_main = search_once(vns, ctx, iters)
+        search_main["best_F_sum"] = int(ctx.costs()[1].reshape(len(insts), w["chains"]).min(1).sum())
+    else:
+        plain = chunked_search(lambda: new_ctx(vns, insts, w, stream, table, key), len(insts), w["chains"], iters,
+                               args.chunk, keep=True)
+        ctx = plain.pop("ctx")
+        search_main = {"iters": iters, "launches": len(plain["hist"]), "iters_per_launch": args.chunk,
+                       "device_ms": plain["total_ms"], "move_evals": plain["evals"],
+                       "value": plain["evals"] / (plain["total_ms"] / 1e3), "unit": "move-evals/s",
+                       "best_F_sum": int(plain["best"].sum())}
+    Ks = [i.K for i in insts]
+    Ts = sorted({i.T for i in insts})
+    sweep = sweep_steps(torch, vns, ctx, stream, args.steps, args.warmup)
+    ctx.close()
+    out_ttb = None
+    if name in LEARNED_SETUP and not args.no_learned and not args.only_sweep:
+        out_ttb = learned_vs_plain(args, vns, stream, table, key, name, insts, w, plain)
 
-    # --- warmup: W iterations on a separate context (same data), then sweeps ---
-    warm = make(False)
-    if args.warmup > 0:
-        warm.run(args.warmup)
-    warm.eval_neighbourhood(7, vns.ALL_CHAINS, slot_prices=False)
+    config = {"workload": name, "instances": len(insts), "K": Ks[0] if len(Ks) == 1 else [min(Ks), max(Ks)],
+              "T": Ts[0] if len(Ts) == 1 else Ts, "chains_per_instance": w["chains"],
+              "chains": len(insts) * w["chains"], "neighbourhoods": ["flip_zM", "flip_zR", "shift"], "k_max": 5,
+              "seed": w["seed"], "search_iters": iters, "tuning": (table.get(key) or {}).get("choice"),
+              "step": "one exact sweep of every move of flip zM, flip zR and shift for every chain (k_eval), then "
+                      "each chain's (price, slot) argmin (k_chain_best) copied to the host; on the states of "
+                      f"the plain search after {iters} iterations"}
+    out = {
+        "metric": METRIC, "value": sweep["value"], "unit": "move-evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": sweep["device_ms"] / max(args.steps, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic", "config": config,
+        "move_evals_per_step": sweep["move_evals_per_step"], "wall_s": sweep["wall_s"],
+        "roofline": {"kernel": "k_eval", "launch": SWEEP_LAUNCH, "bound": "alu", "achieved": sweep["achieved"],
+                     "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s", "frac": sweep["frac"],
+                     "traffic": measured_traffic("k_eval", name, "sweep"),
+                     "kernel_ms_mean": sweep["kernel_ms_mean"], "ops_per_period_step": OPS_PER_PERIOD_STEP,
+                     "accumulators": "int32 under the create-time bounds; costs int64"},
+        "sweeps": {name: sweep},
+        "search": {name: search_main},
+    }
+    if out_ttb is not None:
+        out["time_to_plain_best"] = out_ttb
 
-    # --- timed: K iterations of all chains in one launch, from the initial solution ---
-    ctx = make(True)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    ctx.run(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = e0.elapsed_time(e1)
-    st = ctx.stats()
-    run_ms = st["last_run_ms"]          # HIP events around the search launch on the context stream
-    evals = st["last_run_evals"]
-    value = evals / (ev_ms / 1e3)
-    ms_per_step = ev_ms / args.steps
-
-    # best cost of the plain method per instance (over its chains) and the iteration it was first reached
-    bests = []
-    for i in range(len(insts)):
-        bF, bit = None, None
-        for c in range(chains):
-            rec = ctx.trajectory(i * chains + c)
-            fb = int(rec["F_best"][-1])
-            it = int(rec["iter"][int((rec["F_best"] == fb).argmax())])
-            if bF is None or fb < bF or (fb == bF and it < bit):
-                bF, bit = fb, it
-        bests.append((bF, bit))
-    last_it = max(it for _, it in bests)
-
-    # --- the same search with neighbourhoods not re-priced on an unchanged pattern (same moves applied) ---
-    memo = None
-    if name != "learned_batched_1024" and not args.no_extras:
-        with vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=False,
-                         options={vns.OPT_VND_MEMO: 1}) as mctx:
-            mctx.bind_stream(stream)
-            table.apply(mctx, key)
-            mctx.set_option(vns.OPT_VND_MEMO, 1)
-            mctx.run(args.steps)
-            ms_ = mctx.stats()
-            mb = mctx.costs()[1].reshape(len(insts), chains).min(1)
-            memo = {"kernel_ms": ms_["last_run_ms"], "move_evals": ms_["last_run_evals"],
-                    "iterations_per_s": args.steps / (ms_["last_run_ms"] / 1e3),
-                    "speedup_vs_every_neighbourhood": run_ms / ms_["last_run_ms"],
-                    "same_best": bool((mb == [b for b, _ in bests]).all())}
-
-    # --- the best-of-G search of Algorithm 2 (G shakes of x per iteration, the minimum kept), GVNS form and as
-    #     printed, on the same chains and iterations ---
-    best_of = None
-    if name == "plain_100x52" and not args.no_extras:
-        best_of = {"G": BEST_OF_G, "plain_best_F": int(min(b for b, _ in bests))}
-        for variant, literal in (("gvns", 0), ("literal", 1)):
-            with vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=False,
-                             options={vns.OPT_BEST_OF: BEST_OF_G, vns.OPT_BEST_OF_LITERAL: literal,
-                                      vns.OPT_RUN_WAVES: 4, vns.OPT_RUN_LDS: 65536}) as bctx:
-                bctx.bind_stream(stream)
-                bctx.run(args.steps)
-                bs = bctx.stats()
-                best_of[variant] = {"kernel_ms": bs["last_run_ms"], "move_evals": bs["last_run_evals"],
-                                    "move_evals_per_s": bs["last_run_evals"] / (bs["last_run_ms"] / 1e3),
-                                    "best_F": int(bctx.costs()[1].min())}
-
-            # device time until the best-of search holds the plain search's best cost (launches of --chunk)
-            def make_best(literal=literal):
-                c = vns.Context(target, seed=w["seed"], chains=chains, nb_list=w["nb"], trace=False,
-                                options={vns.OPT_BEST_OF: BEST_OF_G, vns.OPT_BEST_OF_LITERAL: literal,
-                                         vns.OPT_RUN_WAVES: 4, vns.OPT_RUN_LDS: 65536})
-                c.bind_stream(stream)
-                return c
-
-            import numpy as np
-            r = chunked_search(make_best, 1, chains, args.steps, args.chunk,
-                               targets=np.array([best_of["plain_best_F"]], np.int64))
-            best_of[variant]["ms_to_plain_best"] = r["ms"]
-            best_of[variant]["iters_to_plain_best"] = r["iters"] if r["ms"] is not None else None
-
-    # --- full-neighbourhood sweep of all chains (pricing kernel alone) ---
-    sweep_ms, sweep_ev, sweep_steps = [], 0, 0
-    for _ in range(args.sweep_reps):
-        ctx.eval_neighbourhood(7, vns.ALL_CHAINS, slot_prices=False)
-        s = ctx.stats()
-        sweep_ms.append(s["last_eval_ms"])
-        sweep_ev, sweep_steps = s["last_eval_evals"], s["last_eval_period_steps"]
-    sweep_med = statistics.median(sweep_ms)
-    # the same sweeps priced incrementally (each move decoded only until it rejoins the current pattern)
-    inc_ms, inc_dec = [], 0
-    if not args.no_extras:
-        ctx.set_option(vns.OPT_EVAL_INCREMENTAL, 1)
-        for _ in range(args.sweep_reps):
-            ctx.eval_neighbourhood(7, vns.ALL_CHAINS, slot_prices=False)
-            s = ctx.stats()
-            inc_ms.append(s["last_eval_ms"])
-            inc_dec = s["last_eval_decoded_steps"]
-        ctx.set_option(vns.OPT_EVAL_INCREMENTAL, 0)
-    inc_med = statistics.median(inc_ms) if inc_ms else None
+    if not args.only_sweep:
+        # the other configurations' searches over their own iterations, and their sweeps
+        for other in ("plain_100x52", "batched_4096"):
+            if other == name:
+                continue
+            w2, insts2 = workload_insts(other)
+            key2 = autotune.signature(insts2, w2["chains"])
+            c2 = new_ctx(vns, insts2, w2, stream, table, key2)
+            s2 = search_once(vns, c2, w2["iters"])
+            if other == "plain_100x52":
+                s2["traffic"] = measured_traffic(s2["kernel"], other, "search")
+            out["search"][other] = s2
+            out["sweeps"][other] = sweep_steps(torch, vns, c2, stream, max(args.steps, 20), args.warmup)
+            c2.close()
+            if other == "plain_100x52" and not args.no_learned:
+                p2 = chunked_search(lambda: new_ctx(vns, insts2, w2, stream, table, key2), 1, w2["chains"],
+                                    w2["iters"], args.chunk)
+                out["time_to_plain_best_100x52"] = learned_vs_plain(args, vns, stream, table, key2, other, insts2,
+                                                                    w2, p2)
+    if name == "paper_300x52":
+        out["paper_quality"] = paper_quality(args, vns, stream, insts, w)
 
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -464,78 +563,11 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
-    peak = VALU_PEAK_OPS / 1e12
-    # algorithmic work = the iterations the search consumed; speculative iterations computed after an
-    # accepted one in their round are thrown away and counted apart (executed_frac includes them)
-    achieved = st["last_run_period_steps"] * OPS_PER_PERIOD_STEP / (run_ms / 1e3) / 1e12
-    spec_m, discarded = st["last_run_spec_iters"], st["last_run_discarded_evals"]
-    executed = (evals + discarded) / evals if evals else 1.0
-    run_kernel = "k_run_coop" if spec_m > 1 else "k_run"
-    sweep_achieved = sweep_steps * OPS_PER_PERIOD_STEP / (sweep_med / 1e3) / 1e12
-    Ks = [i.K for i in insts]
-    Ts = sorted({i.T for i in insts})
-    config = {"workload": name, "instances": len(insts), "K": Ks[0] if len(Ks) == 1 else [min(Ks), max(Ks)],
-              "T": Ts[0] if len(Ts) == 1 else Ts, "chains": chains, "iters": args.steps,
-              "neighbourhoods": ["flip_zM", "flip_zR", "shift"], "k_max": 5, "seed": w["seed"],
-              "graph": bool(args.graph), "tuning": (table.get(key) or {}).get("choice"),
-              "step": "one GVNS iteration of all chains; K steps = one vns_run(K) launch"}
-    out = {
-        "metric": "exact move-evals/s (int64 cost) + time-to-plain-best-cost, learned vs plain",
-        "value": value,
-        "unit": "move-evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic",
-        "config": config,
-        "result_dtype": "int64",
-        "move_evals": evals,
-        "wall_s": wall,
-        "kernel_ms": run_ms,
-        "plain_best": ({"F": bests[0][0], "iteration": bests[0][1], "ms": (bests[0][1] + 1) * ms_per_step}
-                       if len(insts) == 1 else
-                       {"F_sum": int(sum(f for f, _ in bests)), "last_iteration_improved": last_it,
-                        "ms": (last_it + 1) * ms_per_step}),
-        "vnd_memo": memo,
-        "best_of": best_of,
-        "roofline": {"kernel": run_kernel, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "TOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(run_kernel, name),
-                     "ops_per_period_step": OPS_PER_PERIOD_STEP,
-                     "executed_frac": achieved * executed / peak},
-        "speculative_iterations": {"per_chain": spec_m, "discarded_move_evals": discarded,
-                                   "executed_over_consumed": executed},
-        "sweep": {"kernel": "k_eval", "move_evals": sweep_ev, "median_ms": sweep_med,
-                  "value": sweep_ev / (sweep_med / 1e3), "unit": "move-evals/s", "achieved": sweep_achieved,
-                  "peak": peak, "frac": sweep_achieved / peak, "traffic": measured_traffic("k_eval", name)},
-        "sweep_incremental": None if inc_med is None else {"kernel": "k_eval_inc", "move_evals": sweep_ev, "median_ms": inc_med,
-                              "value": sweep_ev / (inc_med / 1e3), "unit": "move-evals/s",
-                              "speedup_vs_full_decode": sweep_med / inc_med,
-                              "decoded_period_steps": inc_dec, "full_decode_period_steps": sweep_steps,
-                              "decoded_share": inc_dec / sweep_steps if sweep_steps else None,
-                              "decoded_achieved": inc_dec * OPS_PER_PERIOD_STEP / (inc_med / 1e3) / 1e12,
-                              "note": "same exact prices; achieved counts the period-steps actually decoded"},
-    }
-    if name in LEARNED_SETUP and not args.no_learned:
-        out["time_to_plain_best"] = learned_vs_plain(args, vns, stream, table, key, name, insts, w["seed"], chains,
-                                                     w["nb"])
-    if name == "paper_300x52":
-        out["paper_quality"] = paper_quality(args, vns, stream, insts, w["seed"], w["nb"])
-    if name in ("learned_batched_1024", "paper_300x52") and not args.no_cpu_baseline:
-        out["cpu_baseline"] = None   # one oracle iteration from the initial solution of K >= 300 products takes minutes
-        args.no_cpu_baseline = True
-    if not args.no_cpu_baseline:
-        rng = __import__("numpy").random.default_rng(0)
-        order = rng.permutation(len(insts)) if len(insts) > 1 else [0] * 16
-        pairs = [(insts[i], w["seed"], int(i) * chains + (j % chains)) for j, i in enumerate(list(order)[:16])]
-        out["cpu_baseline"] = cpu_baseline(pairs, w["nb"], args.cpu_seconds, name)
+    torch.cuda.synchronize()
+    out["gpu_wall_s"] = time.perf_counter() - t_start
+    if not args.no_cpu_baseline and not args.only_sweep:
+        out["cpu_baseline"] = cpu_baseline(insts, w, name, args.cpu_seconds)
     print(json.dumps(out), flush=True)
-    ctx.close()
-    warm.close()
 
 
 if __name__ == "__main__":

@@ -10,6 +10,7 @@ PKG = Path(__file__).resolve().parent
 ROOT = PKG.parent
 CSRC = PKG / "csrc"
 SOURCES = ["vns_kernels.hip", "vns_mlp.hip", "vns_runtime.hip"]
+PROBE_SOURCES = ["valu_probe.hip"]   # the VALU issue-rate probe behind the pricing kernels' peak
 ARCH = os.environ.get("VNS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -23,13 +24,23 @@ HIPCC_FLAGS = [
 ]
 
 
+def _link(hipcc, objs, out, verbose):
+    tmp = out.with_name(out.name + ".tmp")
+    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    tmp.replace(out)
+
+
 def build(verbose: bool = False, jobs: int = 2) -> Path:
+    """Compile libvns.so and the issue-rate probe libvaluprobe.so; returns the path of libvns.so."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     out = PKG / "libvns.so"
     objdir = ROOT / "_build"
     objdir.mkdir(exist_ok=True)
     objs, procs = [], []
-    for src in SOURCES:
+    for src in SOURCES + PROBE_SOURCES:
         obj = objdir / (Path(src).stem + ".o")
         cmd = [hipcc, *HIPCC_FLAGS, "-c", str(CSRC / src), "-o", str(obj)]
         if verbose:
@@ -43,12 +54,8 @@ def build(verbose: bool = False, jobs: int = 2) -> Path:
             raise RuntimeError(f"hipcc failed on {src}:\n{err}")
         if err and verbose:
             print(err, file=sys.stderr)
-    tmp = PKG / "libvns.so.tmp"
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *map(str, objs), "-o", str(tmp)]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    tmp.replace(out)
+    _link(hipcc, objs[:len(SOURCES)], out, verbose)
+    _link(hipcc, objs[len(SOURCES):], PKG / "libvaluprobe.so", verbose)
     return out
 
 

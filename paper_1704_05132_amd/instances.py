@@ -14,7 +14,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Instance", "draw_instance", "workload", "WORKLOADS", "edge_instance"]
+__all__ = ["Instance", "draw_instance", "workload", "WORKLOADS", "edge_instance", "random_pattern"]
 
 
 @dataclass
@@ -30,6 +30,7 @@ class Instance:
     tag: str = field(default="")
     pM: np.ndarray = None   # int32 [K] unit cost of a manufactured item (None: 0)
     pR: np.ndarray = None   # int32 [K] unit cost of a remanufactured item (None: 0)
+    strict: bool = False    # decode reading: a remanufacture-only shortfall is infeasible (not carried back)
 
     def arrays(self):
         """(D, R, kM, kR, hM, hR) as C-contiguous int32 arrays."""
@@ -51,7 +52,7 @@ class Instance:
         pM, pR = self.unit_costs()
         return Instance(1, self.T, self.D[sl].copy(), self.R[sl].copy(), self.kM[sl].copy(),
                         self.kR[sl].copy(), self.hM[sl].copy(), self.hR[sl].copy(), f"{self.tag}/p{k}",
-                        pM[sl].copy(), pR[sl].copy())
+                        pM[sl].copy(), pR[sl].copy(), self.strict)
 
 
 def draw_instance(rng: np.random.Generator, K: int, T: int, ret_lo: float = 0.2, ret_hi: float = 0.8,
@@ -154,3 +155,13 @@ def edge_instance(kind: str, K: int, T: int, seed: int = 0) -> Instance:
     elif kind != "uniform":
         raise KeyError(kind)
     return inst
+
+
+def random_pattern(inst: Instance, rng: np.random.Generator, p_m: float = 0.3, p_r: float = 0.2):
+    """Random setup rows (zM, zR) as [K, T] uint8: zM(k, t) ~ Bernoulli(p_m) with zM(k, 0) = 1 for every product,
+    zR(k, t) ~ Bernoulli(p_r), drawn in that order.  A manufacturing setup in the first period makes every
+    pattern feasible under the carry-back reading of a remanufacture-only shortfall."""
+    zM = (rng.random((inst.K, inst.T)) < p_m).astype(np.uint8)
+    zM[:, 0] = 1
+    zR = (rng.random((inst.K, inst.T)) < p_r).astype(np.uint8)
+    return zM, zR
