@@ -253,6 +253,23 @@ vns_status vns_eval_neighbourhood(vns_ctx *ctx, uint32_t nb_mask, int32_t chain,
                                   int32_t *best_slot);
 
 /*
+ * vns_eval_neighbourhood_noalloc — for callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same pricing as vns_eval_neighbourhood, with
+ * the same arguments, outputs (host pointers) and results, but it allocates nothing, on the device or on the
+ * host.  Its scratch (evaluation counters, per-product argmin keys, the table of pricing workgroups, built on
+ * the device, and the slot-price staging) lives in one static 8 MiB device array per GPU, held until the
+ * process ends.  Limits: 48 bytes per (chain, product) priced, plus 8 bytes per slot when slot_price is
+ * requested, plus 16 KiB, within the 8 MiB (for example every slot of one chain of 300 x 52, or the argmins
+ * of 64 chains of 100 x 52); a larger request returns VNS_EINVAL without running.  Every call on a GPU shares
+ * that GPU's array and it keeps the last call's contents (the call clears what must start at zero): calls
+ * that overlap on one GPU, from several threads or streams, race.  It always decodes every move in full
+ * (VNS_OPT_EVAL_INCREMENTAL is not used); prices and counted evaluations equal vns_eval_neighbourhood's.
+ */
+vns_status vns_eval_neighbourhood_noalloc(vns_ctx *ctx, uint32_t nb_mask, int32_t chain, int64_t *slot_price,
+                                          int64_t *prod_best, int32_t *prod_best_slot, int64_t *best,
+                                          int32_t *best_slot);
+
+/*
  * vns_run — every chain advances `iters` GVNS iterations (Algorithm 2): Shake(x, k) with Philox4x64-10
  * (key (seed, chain), counter (iteration, draw, 0, 0)), VND (Algorithm 1) with the neighbourhood list,
  * accept if F strictly drops (k = 1), else k = k + 1 wrapping after k_max.  iters >= 0.  The whole run is

@@ -13,6 +13,8 @@
 //   k_run_learned   the same with the learned scorer choosing which moves are priced exactly
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "vns_device.hpp"
 #include "vns_launch.hpp"
 #include "vns_search.hpp"
@@ -221,6 +223,7 @@ template <bool INC>
 __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__restrict__ wg, EvalShared &sh,
                                           int4 *s_snap) {
     const EvalWg d = wg[blockIdx.x];
+    if (d.n == 0) return;   // an empty entry of a device-built table (uniform for the workgroup)
     const int g0 = d.g0, K = d.K, T = d.T, p = d.p, n = d.n;
     const ProdParams pp = a.prod[d.prod];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -370,6 +373,33 @@ __global__ __launch_bounds__(256) void k_eval_inc(EvalArgs a, const EvalWg *__re
     __shared__ EvalShared sh;
     extern __shared__ __attribute__((aligned(16))) int4 s_snap[];
     eval_body<true>(a, wg, sh, s_snap);
+}
+
+// The pricing table for chains g0 .. g0+ng-1 and zeroed counters, on the device (see EvalPrepArgs).
+__global__ __launch_bounds__(256) void k_eval_prep(EvalPrepArgs a) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = tid; i < a.n_cp; i += stride) {
+        const int64_t cp = a.cp_begin + i;
+        const int g = a.cp_chain[cp];
+        const ChainInfo ci = a.chains[g];
+        const int first = max(a.g0, ci.inst * a.chains_per_inst);            // the instance's first chain in range
+        const int end = min(a.g0 + a.ng, (ci.inst + 1) * a.chains_per_inst);  // and one past its last
+        EvalWg w{};
+        if ((g - first) % a.group == 0) {
+            const int p = (int)(cp - ci.cp0);
+            w.cp = cp;
+            w.g0 = g;
+            w.n = min(a.group, end - g);
+            w.K = ci.K;
+            w.T = ci.T;
+            w.p = p;
+            w.prod = ci.prod0 + p;
+            w.row = a.prod[ci.prod0 + p].row;
+        }
+        a.table[i] = w;
+    }
+    for (int64_t j = tid; j < counter_words(); j += stride) a.counters[j] = 0ull;
 }
 
 // ---------------------------------------------------------------------------------------------------
@@ -1311,6 +1341,13 @@ hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s) {
 hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s) {
     if (n_wg <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_eval, dim3((unsigned)n_wg), dim3(256), 0, s, a, wg);
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_prep(const EvalPrepArgs &a, hipStream_t s) {
+    const int64_t n = std::max<int64_t>(a.n_cp, counter_words());
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_eval_prep, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

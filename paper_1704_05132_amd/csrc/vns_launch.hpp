@@ -69,6 +69,8 @@ struct EvalLearnedArgs {
 hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s);
 hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64_t n_cp, hipStream_t s);
 hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s);
+// The pricing table of a chain range and zeroed counters, built on the device (no host staging).
+hipError_t launch_eval_prep(const EvalPrepArgs &a, hipStream_t s);
 // Incremental pricing of the same sweep; lds_bytes of dynamic LDS hold each workgroup's base snapshots
 // (kSnapBytes per chain and period 0..T).
 hipError_t launch_eval_inc(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, size_t lds_bytes, hipStream_t s);

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,9 +27,41 @@ static_assert(VNS_MLP_PARAMS == mlp::kParams, "scorer parameter count");
 
 static void mlp_he_uniform(uint64_t seed, std::vector<float> &p);
 
+// Scratch of the allocation-free pricing call (vns_eval_neighbourhood_noalloc): the evaluation counters,
+// the per-product argmin keys, the pricing workgroup table and the slot-price staging.  One copy per GPU,
+// held until the process ends, shared by every call on that GPU (calls that overlap on one GPU race).  Host
+// code never passes the array's name to a kernel or a copy: it uses the device address that
+// hipGetSymbolAddress returned for that GPU at context creation.
+constexpr size_t kScratchBytes = 8u << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` on each GPU (null until resolved)
+
+// Resolves the device address of `scratch` on `device` (which must be current) once per device.
+hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+void *scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
 // vns_test_inject_failure: countdowns to a simulated allocation failure / HIP failure (0 = off)
 thread_local int32_t g_inject_alloc = 0;
 thread_local int32_t g_inject_device = 0;
@@ -415,6 +448,7 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
         if (e_ != hipSuccess) return bail(hip_fail(c, e_, #expr)); \
     } while (0)
     VNS_CREATE_HIP(hipGetDevice(&c->device));
+    VNS_CREATE_HIP(scratch_setup(c->device));   // the allocation-free pricing call's scratch on this GPU
     {
         int v = 0;
         VNS_CREATE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
@@ -820,6 +854,101 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
         VNS_HIP(c, hipMemcpyAsync(best_slot, c->d_best_slot, sizeof(int32_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
     unsigned long long ev[3] = {0, 0, 0};
     VNS_HIP(c, read_counters(c, ev));
+    float ms = 0.f;
+    VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->stats.last_eval_evals = (int64_t)ev[0];
+    c->stats.last_eval_period_steps = (int64_t)ev[1];
+    c->stats.last_eval_decoded_steps = (int64_t)ev[2];
+    c->stats.last_eval_ms = ms;
+    return VNS_OK;
+}
+
+// The same pricing with its scratch in the per-GPU static array: no device or host allocation.  The table
+// of pricing workgroups is built on the device (one entry per (chain, product), empty for chains that do
+// not lead a group), and every move is decoded in full.
+extern "C" vns_status vns_eval_neighbourhood_noalloc(vns_ctx *c, uint32_t nb_mask, int32_t chain, int64_t *slot_price,
+                                                     int64_t *prod_best, int32_t *prod_best_slot, int64_t *best,
+                                                     int32_t *best_slot) {
+    VNS_LIVE(c);
+    if (nb_mask == 0 || (nb_mask & ~7u)) return fail(c, VNS_EINVAL, "bad neighbourhood mask");
+    int32_t g0, ng;
+    if (chain == VNS_ALL_CHAINS) {
+        g0 = 0;
+        ng = (int32_t)c->chains.size();
+    } else {
+        vns_status s = check_chain(c, chain);
+        if (s != VNS_OK) return s;
+        g0 = chain;
+        ng = 1;
+    }
+    const ChainInfo &first = c->chains[(size_t)g0];
+    const ChainInfo &last = c->chains[(size_t)(g0 + ng - 1)];
+    const int64_t cp_begin = first.cp0, n_cp = last.cp0 + last.K - first.cp0;
+    const int64_t slot_begin = c->price_off[(size_t)g0];
+    const int64_t n_slots = c->price_off[(size_t)(g0 + ng - 1)] + 4LL * last.K * last.T - slot_begin;
+    // scratch layout: counters, argmin keys, workgroup table, slot prices (each 256-byte aligned)
+    const size_t ctr_bytes = align256(sizeof(unsigned long long) * (size_t)counter_words());
+    const size_t key_bytes = align256(sizeof(uint64_t) * (size_t)n_cp);
+    const size_t tab_bytes = align256(sizeof(EvalWg) * (size_t)n_cp);
+    const size_t sp_bytes = slot_price ? align256(sizeof(int64_t) * (size_t)n_slots) : 0;
+    if (ctr_bytes + key_bytes + tab_bytes + sp_bytes > kScratchBytes)
+        return fail(c, VNS_EINVAL, "vns_eval_neighbourhood_noalloc: the chains priced need more than its 8 MiB static "
+                                   "scratch (48 bytes per (chain, product), plus 8 per slot with slot prices); "
+                                   "price fewer chains per call or use vns_eval_neighbourhood");
+    unsigned char *base = static_cast<unsigned char *>(scratch_of(c->device));
+    if (!base) return fail(c, VNS_EDEVICE, "the static scratch of this GPU has no device address");
+    unsigned long long *ctr = reinterpret_cast<unsigned long long *>(base);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(base + ctr_bytes);
+    EvalWg *tab = reinterpret_cast<EvalWg *>(base + ctr_bytes + key_bytes);
+    int64_t *sp = reinterpret_cast<int64_t *>(base + ctr_bytes + key_bytes + tab_bytes);
+
+    EvalPrepArgs pa{};
+    pa.chains = c->d_chains;
+    pa.prod = c->d_prod;
+    pa.cp_chain = c->d_cp_chain;
+    pa.cp_begin = cp_begin;
+    pa.n_cp = n_cp;
+    pa.g0 = g0;
+    pa.ng = ng;
+    pa.group = c->eval_group;
+    pa.chains_per_inst = (int32_t)c->chains_per_inst;
+    pa.table = tab;
+    pa.counters = ctr;
+    VNS_HIP(c, launch_eval_prep(pa, c->stream));
+    EvalArgs ea{};
+    ea.cp_chain = c->d_cp_chain;
+    ea.chains = c->d_chains;
+    ea.prod = c->d_prod;
+    ea.rows = c->d_rows;
+    ea.cur = c->d_cur;
+    ea.cur_cost = c->d_cur_cost;
+    ea.cstate = c->d_cs;
+    ea.slot_price = slot_price ? sp - slot_begin : nullptr;   // indexed by absolute slot offset
+    ea.price_off = c->d_price_off;
+    ea.prod_key = keys - cp_begin;                           // indexed by absolute (chain, product)
+    ea.evals = ctr;
+    ea.nb_mask = nb_mask;
+    VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
+    VNS_HIP(c, launch_eval(ea, tab, n_cp, c->stream));
+    VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
+    ChainBestArgs cb{c->d_chains, c->d_cs, c->d_cur_cost, keys - cp_begin, c->d_prod_price, c->d_prod_slot, c->d_best,
+                     c->d_best_slot, g0};
+    VNS_HIP(c, launch_chain_best(cb, ng, c->stream));
+    if (slot_price)
+        VNS_HIP(c, hipMemcpyAsync(slot_price, sp, sizeof(int64_t) * (size_t)n_slots, hipMemcpyDeviceToHost, c->stream));
+    if (prod_best)
+        VNS_HIP(c, hipMemcpyAsync(prod_best, c->d_prod_price + cp_begin, sizeof(int64_t) * (size_t)n_cp, hipMemcpyDeviceToHost, c->stream));
+    if (prod_best_slot)
+        VNS_HIP(c, hipMemcpyAsync(prod_best_slot, c->d_prod_slot + cp_begin, sizeof(int32_t) * (size_t)n_cp, hipMemcpyDeviceToHost, c->stream));
+    if (best) VNS_HIP(c, hipMemcpyAsync(best, c->d_best, sizeof(int64_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
+    if (best_slot)
+        VNS_HIP(c, hipMemcpyAsync(best_slot, c->d_best_slot, sizeof(int32_t) * (size_t)ng, hipMemcpyDeviceToHost, c->stream));
+    unsigned long long h[counter_words()];
+    VNS_HIP(c, hipMemcpyAsync(h, ctr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    VNS_HIP(c, hipStreamSynchronize(c->stream));
+    unsigned long long ev[3] = {0, 0, 0};
+    for (int q = 0; q < kCounterSlots; ++q)
+        for (int w = 0; w < 3; ++w) ev[w] += h[(size_t)q * kCounterStride + (size_t)w];
     float ms = 0.f;
     VNS_HIP(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.last_eval_evals = (int64_t)ev[0];

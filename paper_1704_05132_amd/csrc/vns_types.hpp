@@ -179,6 +179,19 @@ struct EvalWg {
     int32_t pad;
 };
 
+// The pricing workgroup table built on the device, for the allocation-free pricing call: entry i is the
+// (chain, product) cp_begin + i; a chain leads a group when it is the first of its instance in the range or
+// `group` chains after the previous leader, and a non-leader's entry is empty (n = 0: its workgroup exits).
+struct EvalPrepArgs {
+    const ChainInfo *chains;
+    const ProdParams *prod;
+    const int32_t *cp_chain;
+    int64_t cp_begin, n_cp;
+    int32_t g0, ng, group, chains_per_inst;
+    EvalWg *table;                // [n_cp]
+    unsigned long long *counters; // counter_words() words, set to zero
+};
+
 struct EvalArgs {
     const int32_t *cp_chain;     // [sum over chains of K] chain of each (chain, product)
     const ChainInfo *chains;

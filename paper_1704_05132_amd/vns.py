@@ -47,6 +47,7 @@ SIGNATURES = {
     "vns_workspace_bytes": (_c.c_int, [_P, _c.c_uint32, _c.POINTER(_c.c_size_t)]),
     "vns_bind_workspace": (_c.c_int, [_P, _P, _c.c_size_t, _c.c_uint32]),
     "vns_eval_neighbourhood": (_c.c_int, [_P, _c.c_uint32, _c.c_int32, _P, _P, _P, _P, _P]),
+    "vns_eval_neighbourhood_noalloc": (_c.c_int, [_P, _c.c_uint32, _c.c_int32, _P, _P, _P, _P, _P]),
     "vns_run": (_c.c_int, [_P, _c.c_int32]),
     "vns_get_cost": (_c.c_int, [_P, _c.c_int32, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64)]),
     "vns_get_costs": (_c.c_int, [_P, _P, _P]),
@@ -247,6 +248,23 @@ class Context:
         opt = lambda a: _ptr(a) if a is not None else None
         self._check(lib().vns_eval_neighbourhood(self.h, int(nb_mask), int(chain), opt(sp), opt(pb), opt(ps), _ptr(b),
                                                  _ptr(bs)))
+        return dict(slot_price=sp, prod_best=pb, prod_best_slot=ps, best=b, best_slot=bs)
+
+    def eval_neighbourhood_noalloc(self, nb_mask: int = 7, chain: int = ALL_CHAINS, slot_prices: bool = True,
+                                   prod_best: bool = True):
+        """vns_eval_neighbourhood_noalloc: the same pricing with its scratch in the library's static per-GPU
+        array (no allocation); same outputs as eval_neighbourhood."""
+        chains = range(self.n_chains) if chain == ALL_CHAINS else [chain]
+        n_slots = sum(4 * self.chain_instance(g).K * self.chain_instance(g).T for g in chains) if slot_prices else 0
+        n_prod = sum(self.chain_instance(g).K for g in chains) if prod_best else 0
+        sp = np.empty(n_slots, np.int64) if slot_prices else None
+        pb = np.empty(n_prod, np.int64) if prod_best else None
+        ps = np.empty(n_prod, np.int32) if prod_best else None
+        b = np.empty(len(chains), np.int64)
+        bs = np.empty(len(chains), np.int32)
+        opt = lambda a: _ptr(a) if a is not None else None
+        self._check(lib().vns_eval_neighbourhood_noalloc(self.h, int(nb_mask), int(chain), opt(sp), opt(pb),
+                                                         opt(ps), _ptr(b), _ptr(bs)))
         return dict(slot_price=sp, prod_best=pb, prod_best_slot=ps, best=b, best_slot=bs)
 
     def run(self, iters: int):
