@@ -7,7 +7,9 @@ chain takes it minutes. At full size the checks are therefore:
   * every sampled chain's final solution: its objective is exact and it is a local optimum of every
     neighbourhood (oracle prices of all its moves);
   * every chain: the records are consistent (acceptance iff strictly better, best non-increasing);
-  * full sweeps at full size: every slot price of sampled chains equals the oracle's.
+  * full sweeps at full size: every slot price of sampled chains equals the oracle's, at the search's own
+    state and at random feasible patterns drawn by the seeded generator (set on sampled chains before a sweep
+    of every chain in the benchmarked launch).
 """
 import os
 import sys
@@ -16,7 +18,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1704_05132_amd.instances import WORKLOADS, workload
+from paper_1704_05132_amd.instances import WORKLOADS, random_pattern, workload
 
 pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -111,11 +113,37 @@ def test_batched_4096_bench_launch(vns):
             check_final(ctx, g, insts[i])
 
 
+def sweep_random_patterns(vns, ctx, insts, chains, picks, seed):
+    """Random feasible patterns (seeded generator) on the chains `picks`, then the benchmarked step: one
+    sweep of every chain with each chain's (price, slot) argmin.  Each picked chain's argmin is checked
+    against the oracle's argmin of its prices of the same pattern, and a sweep of that chain alone against
+    every one of the oracle's slot prices."""
+    rng = np.random.default_rng(seed)
+    pats = {}
+    for g in picks:
+        inst = insts[g // chains]
+        zM, zR = random_pattern(inst, rng)
+        ctx.set_solution(g, zM, zR)
+        pats[g] = (zM, zR)
+    out = ctx.eval_neighbourhood(7, vns.ALL_CHAINS, slot_prices=False, prod_best=False)
+    for g, (zM, zR) in pats.items():
+        inst = insts[g // chains]
+        say(f"    sweep at a random pattern: chain {g} (K={inst.K}, T={inst.T})")
+        ref, _ = oracle.price_all(inst, zM, zR, 7)
+        F = oracle.objective(inst, zM, zR)[0]
+        assert ctx.cost(g) == (F, F)
+        assert (int(out["best"][g]), int(out["best_slot"][g])) == oracle.argmin(ref), g
+        one = ctx.eval_neighbourhood(7, g)
+        assert (one["slot_price"] == ref).all(), g
+
+
 def test_learned_batched_1024_launch(vns):
     name = "learned_batched_1024"
     w = WORKLOADS[name]
     insts = [workload(name, i) for i in range(w["n_inst"])]
-    small = sorted(range(len(insts)), key=lambda i: insts[i].K * insts[i].T)[:3]
+    by_size = sorted(range(len(insts)), key=lambda i: insts[i].K * insts[i].T)
+    # the smallest instances of each horizon: T = 52 (two setup words) and T = 104 (four)
+    small = [i for i in by_size if insts[i].T == 52][:3] + [i for i in by_size if insts[i].T == 104][:3]
     with tuned_context(vns, name, insts) as ctx:
         say(f"  {name}: {len(insts)} instances x {w['chains']} chains, 3 iterations, one launch")
         ctx.run(3)
@@ -124,6 +152,9 @@ def test_learned_batched_1024_launch(vns):
             say(f"    instance {i} (K={insts[i].K}, T={insts[i].T}) chain {g}")
             check_prefix(ctx, g, insts[i], w["seed"], 3)
             check_final(ctx, g, insts[i])
+        # the benchmarked step (a sweep of every chain) at random patterns of sampled chains, both horizons
+        picks = [small[0] * w["chains"] + 1, small[3] * w["chains"] + 9, by_size[-1] * w["chains"] + 15]
+        sweep_random_patterns(vns, ctx, insts, w["chains"], picks, seed=77)
     # the learned search fused in the same persistent kernel: exact objectives and local optima
     with tuned_context(vns, name, insts, options={vns.OPT_LEARNED: 100}) as ctx:
         ctx.run(2)
@@ -133,3 +164,20 @@ def test_learned_batched_1024_launch(vns):
             g = i * w["chains"] + 2
             check_records(ctx.trajectory(g))
             check_final(ctx, g, insts[i])
+
+
+def test_paper_300x52_launch(vns):
+    """The paper's benchmark shape (108 instances of 300 x 52, 8 chains each, as the quality table runs
+    them): the first iterations' records of sampled chains, and full sweeps at random patterns."""
+    name = "paper_300x52"
+    w = WORKLOADS[name]
+    insts = [workload(name, i) for i in range(w["n_inst"])]
+    with vns.Context(insts, seed=w["seed"], chains=w["chains"], nb_list=w["nb"],
+                     options={vns.OPT_RUN_WAVES: 2}) as ctx:
+        say(f"  {name}: {len(insts)} instances x {w['chains']} chains, 2 iterations, one launch")
+        ctx.run(2)
+        for g in (0, 8 * 57 + 3):
+            say(f"    chain {g}: records vs the oracle")
+            check_prefix(ctx, g, insts[g // w["chains"]], w["seed"], 2)
+            check_records(ctx.trajectory(g))
+        sweep_random_patterns(vns, ctx, insts, w["chains"], [3, 8 * 107 + 7], seed=78)
