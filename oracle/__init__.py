@@ -8,6 +8,12 @@ Parity status per function (what pins it, see tests/test_oracle_pins.py):
   decode         brute force vs Wagner-Whitin DP and per-pattern LP(z) equality when R = 0; LP(z) <= decode
                  and MILP <= min decode when R > 0; closed forms; hand-worked golden examples; flow-balance
                  invariants on random instances.
+  decode, strict (a remanufacture-only shortfall is infeasible): equal to the carry-back decode wherever the
+                 carry-back decode moved no shortfall, infeasible exactly where it did (every pattern of small
+                 instances); hand-worked golden examples.
+  decode, disposal (unneeded returns disposed of): the recoverable holding equals the optimum of the LP that
+                 keeps the decode's lots and chooses the disposals (scipy HiGHS), for every pattern of small
+                 instances; unchanged without returns; hand-worked golden examples.
   price_all      brute-force table of all 2^(2T) patterns (K = 1, T <= 6): every slot's price.
   vnd            move by move against a VND written in the tests over brute-force cost tables of every
                  pattern (the per-product best move of each neighbourhood in list order, applied only when
@@ -51,6 +57,10 @@ def lib():
         L = ctypes.CDLL(str(path))
         c = ctypes
         inst = [_i32p] * 8   # D, R, kM, kR, hM, hR, pM, pR
+        L.orc_set_strict.restype = None
+        L.orc_set_strict.argtypes = [c.c_int]
+        L.orc_set_dispose.restype = None
+        L.orc_set_dispose.argtypes = [c.c_int]
         L.orc_decode.restype = c.c_int64
         L.orc_decode.argtypes = [c.c_int, _i32p, _i32p] + [c.c_int64] * 6 + [_u8p, _u8p, _i64p, _i64p, _i64p, _i64p]
         L.orc_objective.restype = c.c_int64
@@ -93,6 +103,10 @@ def lib():
 
 
 def _inst(inst):
+    """The instance's arrays for a call, with its decode readings (carry-back or strict; disposal or not) put
+    in force."""
+    lib().orc_set_strict(1 if getattr(inst, "strict", False) else 0)
+    lib().orc_set_dispose(1 if getattr(inst, "dispose", False) else 0)
     return inst.arrays() + inst.unit_costs()
 
 
@@ -101,10 +115,14 @@ def _rows(z, K, T):
     return a
 
 
-def decode(T, D, R, kM, kR, hM, hR, zM, zR, pM=0, pR=0):
+def decode(T, D, R, kM, kR, hM, hR, zM, zR, pM=0, pR=0, strict=False, dispose=False):
     """Decode one product: returns (cost, xM, xR, yM, yR); cost is INF when infeasible.  pM, pR: unit costs of
-    a manufactured and a remanufactured item."""
+    a manufactured and a remanufactured item; strict: a remanufacture-only shortfall is infeasible instead of
+    carried back; dispose: returns no lot needs are disposed of (recoverable holding only on the kept stock;
+    yR is still the stock without disposal)."""
     xM, xR, yM, yR = (np.zeros(T, np.int64) for _ in range(4))
+    lib().orc_set_strict(1 if strict else 0)
+    lib().orc_set_dispose(1 if dispose else 0)
     c = lib().orc_decode(int(T), np.ascontiguousarray(D, np.int32), np.ascontiguousarray(R, np.int32),
                          int(kM), int(kR), int(hM), int(hR), int(pM), int(pR), np.ascontiguousarray(zM, np.uint8),
                          np.ascontiguousarray(zR, np.uint8), xM, xR, yM, yR)

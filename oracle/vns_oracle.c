@@ -26,6 +26,29 @@
 
 #define ORC_INF INT64_MAX
 
+/* The reading of a remanufacture-only shortfall in force for this thread's calls:
+ *   0 (default) carry-back (R5): the last manufacturing lot makes the shortfall and holds it;
+ *   1 strict (R5-alt): a shortfall makes the pattern infeasible. */
+static _Thread_local int orc_strict = 0;
+
+void orc_set_strict(int strict)
+{
+    orc_strict = strict ? 1 : 0;
+}
+
+/* Disposal of returns in force for this thread's calls:
+ *   0 (default) no disposal (R7): every return is held as recoverable stock until it is remanufactured or
+ *     the horizon ends;
+ *   1 disposal (R29): returns may be disposed of at no cost.  The lots are the decode's; the stock kept at the
+ *     end of period t is what a later lot still needs, yR(t) - min_{s >= t} yR(s) with yR the stock without
+ *     disposal (the rest is disposed of as it arrives), and recoverable holding is charged on the kept stock. */
+static _Thread_local int orc_dispose = 0;
+
+void orc_set_dispose(int dispose)
+{
+    orc_dispose = dispose ? 1 : 0;
+}
+
 /* ------------------------------------------------------------------------------------------------ */
 /* Decode of one product (Section 2 quantities x_M, x_R, y_M, y_R).                                  */
 /* Returns the cost, or ORC_INF when the pattern cannot meet demand.  The four arrays receive the     */
@@ -64,7 +87,7 @@ int64_t orc_decode(int T, const int32_t *D, const int32_t *R,
 
         int64_t shortfall = need - xR[t] - xM[t];
         if (shortfall > 0) {
-            if (lastM < 0) { feasible = 0; break; }
+            if (lastM < 0 || orc_strict) { feasible = 0; break; }
             /* the last manufacturing lot makes the shortfall and holds it until t */
             xM[lastM] += shortfall;
             for (int tau = lastM; tau < t; ++tau) yM[tau] += shortfall;
@@ -88,6 +111,15 @@ int64_t orc_decode(int T, const int32_t *D, const int32_t *R,
             sYR += yR[t];
             sXM += xM[t];
             sXR += xR[t];
+        }
+        if (orc_dispose) {
+            /* recoverable holding on the kept stock only: subtract the suffix minima of the stock path */
+            int64_t suffix_min = yR[T - 1], sMin = 0;
+            for (int t = T - 1; t >= 0; --t) {
+                if (yR[t] < suffix_min) suffix_min = yR[t];
+                sMin += suffix_min;
+            }
+            sYR -= sMin;
         }
         /* setups, holding, and the unit costs of the items made (p_M, p_R of Algorithm 1's signature) */
         cost = kM * nM + kR * nR + hM * sYM + hR * sYR + pM * sXM + pR * sXR;

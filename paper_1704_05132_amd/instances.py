@@ -31,6 +31,7 @@ class Instance:
     pM: np.ndarray = None   # int32 [K] unit cost of a manufactured item (None: 0)
     pR: np.ndarray = None   # int32 [K] unit cost of a remanufactured item (None: 0)
     strict: bool = False    # decode reading: a remanufacture-only shortfall is infeasible (not carried back)
+    dispose: bool = False   # decode reading: returns no lot needs are disposed of (no holding charged on them)
 
     def arrays(self):
         """(D, R, kM, kR, hM, hR) as C-contiguous int32 arrays."""
@@ -52,7 +53,7 @@ class Instance:
         pM, pR = self.unit_costs()
         return Instance(1, self.T, self.D[sl].copy(), self.R[sl].copy(), self.kM[sl].copy(),
                         self.kR[sl].copy(), self.hM[sl].copy(), self.hR[sl].copy(), f"{self.tag}/p{k}",
-                        pM[sl].copy(), pR[sl].copy(), self.strict)
+                        pM[sl].copy(), pR[sl].copy(), self.strict, self.dispose)
 
 
 def draw_instance(rng: np.random.Generator, K: int, T: int, ret_lo: float = 0.2, ret_hi: float = 0.8,

@@ -444,3 +444,178 @@ def test_unit_costs_in_the_search():
     assert price.min() >= ch.F
     plain = draw_instance(np.random.default_rng(5), 6, 10)
     assert oracle.objective(inst, ch.zM, ch.zR)[0] != oracle.objective(plain, ch.zM, ch.zR)[0]
+
+
+# ----------------------------------------------------------------------------------------------------------
+# The strict reading of a remanufacture-only shortfall (R5-alt)
+# ----------------------------------------------------------------------------------------------------------
+GOLDEN_STRICT = os.path.join(os.path.dirname(__file__), "golden", "decode_strict_hand.json")
+
+
+def test_strict_hand_worked_examples():
+    with open(GOLDEN_STRICT) as f:
+        ex = json.load(f)["examples"]
+    for e in ex:
+        T = len(e["D"])
+        args = (T, np.array(e["D"], np.int32), np.array(e["R"], np.int32), e["kM"], e["kR"], e["hM"], e["hR"],
+                np.array(e["zM"], np.uint8), np.array(e["zR"], np.uint8))
+        c_strict = oracle.decode(*args, strict=True)[0]
+        c_carry = oracle.decode(*args)[0]
+        assert (c_strict if c_strict != INF else -1) == e["cost"], e["name"]
+        assert (c_carry if c_carry != INF else -1) == e["carry_back_cost"], e["name"]
+
+
+def _carried(inst, zM, zR):
+    """Whether the carry-back decode moved a shortfall: stock held into a setup period (the look-ahead decode
+    ends every setup interval with empty serviceable stock unless a later shortfall was carried back)."""
+    c, xM, xR, yM, yR = _dec(inst, zM, zR)
+    if c == INF:
+        return None
+    setups = np.nonzero(np.asarray(zM) | np.asarray(zR))[0]
+    return any(t >= 1 and yM[t - 1] > 0 for t in setups)
+
+
+@pytest.mark.parametrize("seed", range(6))
+@pytest.mark.parametrize("T", [1, 3, 5])
+def test_strict_is_carry_back_without_a_carried_shortfall(seed, T):
+    """Every pattern: the strict decode is feasible exactly where the carry-back decode is feasible and moved
+    no shortfall, and then both give the same lots and cost."""
+    rng = np.random.default_rng([71, seed, T])
+    inst = _one(rng, T)
+    if seed % 3 == 1:
+        inst.R[0] = rng.integers(0, 400, T)   # returns above demand too
+    n_infeasible = 0
+    for bm in range(1 << T):
+        for br in range(1 << T):
+            zM, zR = _rows(bm, T), _rows(br, T)
+            carried = _carried(inst, zM, zR)
+            st = oracle.decode(inst.T, inst.D[0], inst.R[0], inst.kM[0], inst.kR[0], inst.hM[0], inst.hR[0], zM, zR,
+                               strict=True)
+            if carried is None or carried:
+                assert st[0] == INF, (bm, br)
+                n_infeasible += carried is True
+            else:
+                cb = _dec(inst, zM, zR)
+                assert st[0] == cb[0], (bm, br)
+                for a, b in zip(st[1:], cb[1:]):
+                    assert (a == b).all()
+    if T >= 3:
+        assert n_infeasible > 0
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("T", [2, 4, 6])
+def test_strict_bruteforce_min_equals_wagner_whitin_without_returns(seed, T):
+    """Without returns a remanufacture-only interval with demand is infeasible under the strict reading, so
+    its brute-force optimum is the textbook lot-sizing optimum."""
+    rng = np.random.default_rng([72, seed, T])
+    inst = _one(rng, T, no_returns=True)
+    inst.strict = True
+    best = min(oracle.objective(inst, _rows(bm, T)[None, :], _rows(br, T)[None, :])[0]
+               for bm in range(1 << T) for br in range(1 << T))
+    assert best == wagner_whitin(inst.D[0], int(inst.kM[0]), int(inst.hM[0]))
+
+
+def test_strict_search_states_are_strict_feasible():
+    """The oracle's search under the strict reading moves only between strictly feasible patterns, and every
+    reported objective is the strict objective of the state."""
+    inst = edge_instance("uniform", 6, 14, seed=3)
+    inst.strict = True
+    ch = oracle.Chain(inst, 5, 0)
+    rec = ch.run(25)
+    F = oracle.objective(inst, ch.zM, ch.zR)[0]
+    assert F == ch.F != INF and (rec["F_local"] <= rec["F_shaken"]).all()
+    price, _ = oracle.price_all(inst, ch.zM, ch.zR, 7)
+    assert price.min() >= F
+    # the same state under the carry-back reading costs the same (it moves no shortfall)
+    inst2 = edge_instance("uniform", 6, 14, seed=3)
+    assert oracle.objective(inst2, ch.zM, ch.zR)[0] == F
+
+
+# ----------------------------------------------------------------------------------------------------------
+# Disposal of returns no lot needs (R29)
+# ----------------------------------------------------------------------------------------------------------
+GOLDEN_DISPOSE = os.path.join(os.path.dirname(__file__), "golden", "decode_dispose_hand.json")
+
+
+def test_dispose_hand_worked_examples():
+    with open(GOLDEN_DISPOSE) as f:
+        ex = json.load(f)["examples"]
+    for e in ex:
+        T = len(e["D"])
+        args = (T, np.array(e["D"], np.int32), np.array(e["R"], np.int32), e["kM"], e["kR"], e["hM"], e["hR"],
+                np.array(e["zM"], np.uint8), np.array(e["zR"], np.uint8))
+        assert oracle.decode(*args, dispose=True)[0] == e["cost"], e["name"]
+        assert oracle.decode(*args)[0] == e["no_disposal_cost"], e["name"]
+
+
+def lp_kept_recoverable(R, xR):
+    """Least total recoverable stock with the lots fixed and free disposal: min sum y(t) subject to
+    y(t) = y(t-1) + R(t) - xR(t) - w(t), y >= 0, w >= 0 (variables [y, w]); scipy HiGHS."""
+    T = len(R)
+    A = np.zeros((T, 2 * T))
+    b = np.zeros(T)
+    for t in range(T):
+        A[t, t] = 1
+        if t > 0:
+            A[t, t - 1] = -1
+        A[t, T + t] = 1
+        b[t] = R[t] - xR[t]
+    r = linprog(np.r_[np.ones(T), np.zeros(T)], A_eq=A, b_eq=b, bounds=[(0, None)] * (2 * T), method="highs")
+    assert r.status == 0
+    return r.fun
+
+
+@pytest.mark.parametrize("seed", range(5))
+@pytest.mark.parametrize("T", [2, 4, 5])
+@pytest.mark.parametrize("strict", [False, True])
+def test_dispose_holding_is_the_disposal_lp_optimum(seed, T, strict):
+    """Every pattern: the lots do not change, and the recoverable holding charged is hR times the least
+    recoverable stock any disposal plan keeps for those lots (an LP over the disposals)."""
+    rng = np.random.default_rng([73, seed, T])
+    inst = _one(rng, T)
+    if seed % 2:
+        inst.R[0] = rng.integers(0, 300, T)
+    k = 0
+    n_saved = 0
+    for bm in range(1 << T):
+        for br in range(1 << T):
+            zM, zR = _rows(bm, T), _rows(br, T)
+            a = (inst.T, inst.D[k], inst.R[k], inst.kM[k], inst.kR[k], inst.hM[k], inst.hR[k], zM, zR)
+            c0, xM, xR, yM, yR = oracle.decode(*a, strict=strict)
+            c1, xM1, xR1, yM1, yR1 = oracle.decode(*a, strict=strict, dispose=True)
+            if c0 == INF:
+                assert c1 == INF
+                continue
+            assert (xM1 == xM).all() and (xR1 == xR).all() and (yM1 == yM).all()
+            kept = lp_kept_recoverable(inst.R[k], xR)
+            expect = c0 - int(inst.hR[k]) * int(yR.sum()) + int(inst.hR[k]) * int(round(kept))
+            assert c1 == expect, (bm, br)
+            n_saved += c1 < c0
+    assert n_saved > 0
+
+
+def test_dispose_without_returns_changes_nothing():
+    rng = np.random.default_rng(74)
+    for T in (1, 3, 6):
+        inst = _one(rng, T, no_returns=True)
+        for bm in range(1 << T):
+            for br in range(1 << T):
+                zM, zR = _rows(bm, T), _rows(br, T)
+                a = (inst.T, inst.D[0], inst.R[0], inst.kM[0], inst.kR[0], inst.hM[0], inst.hR[0], zM, zR)
+                assert oracle.decode(*a, dispose=True)[0] == oracle.decode(*a)[0]
+
+
+def test_dispose_in_the_search():
+    """The oracle's search with disposal: objective of every state recomputed, local optimality, and the
+    disposal objective never above the no-disposal one of the same state."""
+    inst = edge_instance("big_returns", 5, 12, seed=6)
+    inst.dispose = True
+    ch = oracle.Chain(inst, 3, 1)
+    ch.run(20)
+    F = oracle.objective(inst, ch.zM, ch.zR)[0]
+    assert F == ch.F
+    price, _ = oracle.price_all(inst, ch.zM, ch.zR, 7)
+    assert price.min() >= F
+    plain = edge_instance("big_returns", 5, 12, seed=6)
+    assert oracle.objective(plain, ch.zM, ch.zR)[0] >= F
