@@ -123,12 +123,22 @@ enum vns_option {
     VNS_OPT_BEST_OF_LITERAL = 17, /* 0/1 (default 0): best-of-G as Algorithm 2 prints it: k never changes and
                               the selected result always replaces x (accepted = 1 in every record);
                               with VNS_OPT_BEST_OF = 0 or 1 it runs one stream                       */
-    VNS_OPT_EVAL_INCREMENTAL = 18 /* 0/1 (default 0): vns_eval_neighbourhood prices every move exactly but
+    VNS_OPT_EVAL_INCREMENTAL = 18, /* 0/1 (default 0): vns_eval_neighbourhood prices every move exactly but
                               decodes it only from its first changed period, starting from the current
                               pattern's state there, until its state equals the current pattern's again
                               (the rest of the cost then differs by known amounts) or it turns
                               infeasible.  Same prices, argmins and counted evaluations;
                               vns_stats.last_eval_decoded_steps reports the period-steps decoded      */
+    VNS_OPT_DECODE = 19    /* decode reading, a bit set (default 0); the paper leaves both points open
+                              (Section 2 names returns and recoverable stock without the rules):
+                              bit 1 (strict): a period whose latest setup is remanufacturing only must be
+                              covered by the returns there; a shortfall makes the pattern infeasible
+                              instead of being made and held by the last manufacturing lot;
+                              bit 2 (disposal): returns no lot needs are disposed of at no cost, and
+                              recoverable holding is charged on the stock later lots still need, per
+                              period yR(t) - min over s >= t of yR(s).  Setting it restarts every chain
+                              from the initial solution.  The learned search, the speculative VND,
+                              incremental pricing and vns_eval_learned take only 0 (VNS_EINVAL)       */
 };
 
 /* One GVNS iteration of one chain. */

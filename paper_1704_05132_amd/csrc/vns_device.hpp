@@ -56,6 +56,14 @@ __device__ __forceinline__ bool apply_move(Bits &b, int l, int T) {
     return true;
 }
 
+// Readings of the decode (a bit set of a context's VNS_OPT_DECODE, a template argument of the kernels):
+//   kModelStrict   a period whose latest setup is remanufacturing only and lacks returns makes the pattern
+//                  infeasible, instead of the shortfall being made by the last manufacturing lot;
+//   kModelDispose  returns no lot needs are disposed of, and recoverable holding is charged on the kept stock.
+constexpr int kModelStrict = 1;
+constexpr int kModelDispose = 2;
+constexpr int kModels = 4;
+
 // State of the forward decode of one pattern (one lane).
 struct DecodeState {
     int32_t lim = 0, XR = 0, lsR = 0, lastM = 0, A1 = 0, A2 = 0;
@@ -75,10 +83,14 @@ __device__ __forceinline__ void and_or(int32_t &acc, int32_t a, int32_t b) {
 }
 
 // One period-step: sm, sr are the setup bits of period tau as 0 / -1 masks, dp = (D(tau), PR(tau)).
+template <int MODEL = 0>
 __device__ __forceinline__ void decode_step(DecodeState &s, int32_t sm, int32_t sr, int32_t tau, int2 dp) {
     s.lim = sel(sm, s.XR, s.lim);         // a manufacturing setup closes the remanufacturing capacity
     s.lastM = sel(sm, tau, s.lastM);
-    s.nolast &= ~sm;
+    if constexpr ((MODEL & kModelStrict) != 0)
+        s.nolast = ~sm & (s.nolast | sr);   // no manufacturing allowed since the latest setup (R-only, or none)
+    else
+        s.nolast &= ~sm;                    // no manufacturing setup yet
     s.lim = sel(sr, dp.y, s.lim);         // a remanufacturing setup may use every return so far
     s.lsR = sel(sr, tau, s.lsR);
     const int32_t xn = min(s.XR + dp.x, s.lim);
@@ -87,13 +99,39 @@ __device__ __forceinline__ void decode_step(DecodeState &s, int32_t sm, int32_t 
     mad_u24(s.A1, u, s.lsR);
     const int32_t rr = dp.x - u;          // units manufactured at lastM for period tau
     mad_u24(s.A2, rr, s.lastM);
-    and_or(s.bad, rr, s.nolast);          // demand with no manufacturing setup at or before it
+    and_or(s.bad, rr, s.nolast);          // demand manufactured where no manufacturing lot may make it
+}
+
+// Disposal (kModelDispose): sum over t of m(t) = min_{s >= t} yR(s), the recoverable stock without disposal
+// that no later lot uses, from a backward pass.  yR(t) = PR(t) - c, with c the units remanufactured by the end
+// of t's setup interval (XR after the forward pass for the last one); going back over a remanufacturing setup,
+// c drops by the interval's demand (a lot that left stock covered all of it; one that used every return left
+// yR = 0 there, so every earlier m is 0 whatever c is, and m is clamped at 0).  Only the first NW setup words
+// of b are read.
+template <int NW, class RowPtr>
+__device__ __forceinline__ int32_t dispose_credit(const Bits &b, RowPtr row, int T, int32_t XR) {
+    int32_t c = XR, dint = 0, m = INT32_MAX, acc = 0;
+#pragma unroll
+    for (int j = NW - 1; j >= 0; --j) {
+        if (32 * j >= T) continue;
+        const int32_t wr = (int32_t)b.r[j], ws = (int32_t)(b.m[j] | b.r[j]);
+        for (int t = min(32 * j + 31, T - 1); t >= 32 * j; --t) {
+            const int2 dp = row[t];
+            dint += dp.x;
+            m = max(min(m, dp.y - c), 0);   // min(m, yR(t)), never below 0 (one v_med3_i32)
+            acc += m;
+            c -= dint & __builtin_amdgcn_sbfe(wr, t & 31, 1);   // a remanufacturing lot covered the interval
+            dint &= ~__builtin_amdgcn_sbfe(ws, t & 31, 1);      // a setup starts the interval
+        }
+    }
+    return acc;
 }
 
 // Cost from the final decode state; only the first NW setup words of b are read (the others are zero when
-// T <= 32 NW).
+// T <= 32 NW).  credit: the disposal reading's sum of never-needed recoverable stock (0 otherwise).
 template <int NW = kWords>
-__device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bits &b, int T, const ProdParams &pp) {
+__device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bits &b, int T, const ProdParams &pp,
+                                                 int32_t credit = 0) {
     if (s.bad) return kInf;
     int32_t nM = 0, nR = 0;
 #pragma unroll
@@ -104,7 +142,7 @@ __device__ __forceinline__ int64_t decode_finish(const DecodeState &s, const Bit
     // kM nM + kR nR + hM (S_tD - A1 - A2) + hR (S_PR - T XR + A1) + pM (SD - XR) + pR XR, the constant and
     // the XR terms folded into C and cXR (every demanded item is made once, XR of them remanufactured)
     return (int64_t)pp.kM * nM + (int64_t)pp.kR * nR - (int64_t)pp.hM * ((int64_t)s.A1 + (int64_t)s.A2) +
-           (int64_t)pp.hR * s.A1 + pp.cXR * s.XR + pp.C;
+           (int64_t)pp.hR * ((int64_t)s.A1 - credit) + pp.cXR * s.XR + pp.C;
 }
 
 template <class RowPtr>
@@ -114,11 +152,12 @@ __device__ __forceinline__ void load_chunk(RowPtr row, int at, int2 (&c)[4]) {
 }
 
 // Four period-steps from period tau (a multiple of four) of the setup words m, r that hold it.
+template <int MODEL = 0>
 __device__ __forceinline__ void decode_chunk(DecodeState &s, int32_t m, int32_t r, int tau, const int2 (&c)[4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        decode_step(s, __builtin_amdgcn_sbfe(m, (tau + i) & 31, 1), __builtin_amdgcn_sbfe(r, (tau + i) & 31, 1), tau + i,
-                    c[i]);
+        decode_step<MODEL>(s, __builtin_amdgcn_sbfe(m, (tau + i) & 31, 1), __builtin_amdgcn_sbfe(r, (tau + i) & 31, 1),
+                           tau + i, c[i]);
 }
 
 // Exact cost of one product's pattern (kInf when infeasible), any T <= kTMax.  row points at the product's
@@ -126,7 +165,7 @@ __device__ __forceinline__ void decode_chunk(DecodeState &s, int32_t m, int32_t 
 // be the same in every active lane.  The periods are walked in chunks of four; the rows of the next chunk
 // are read while the current one is decoded, alternating between two register sets so that nothing is
 // copied, and never past period T - 1.
-template <int NW = kWords, class RowPtr>
+template <int NW = kWords, int MODEL = 0, class RowPtr>
 __device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T, const ProdParams &pp) {
     static_assert(NW >= 1 && NW <= kWords, "setup words");
     T = __builtin_amdgcn_readfirstlane(T);
@@ -142,21 +181,24 @@ __device__ __forceinline__ int64_t decode_cost(const Bits &b, RowPtr row, int T,
         const int wend = min(32 * j + 32, T);
         for (; tau + 8 <= wend; tau += 8) {
             load_chunk(row, min(tau + 4, Tc), cb);
-            decode_chunk(s, m, r, tau, ca);
+            decode_chunk<MODEL>(s, m, r, tau, ca);
             load_chunk(row, min(tau + 8, Tc), ca);
-            decode_chunk(s, m, r, tau + 4, cb);
+            decode_chunk<MODEL>(s, m, r, tau + 4, cb);
         }
         if (tau + 4 <= wend) {
             load_chunk(row, min(tau + 4, Tc), cb);
-            decode_chunk(s, m, r, tau, ca);
+            decode_chunk<MODEL>(s, m, r, tau, ca);
 #pragma unroll
             for (int i = 0; i < 4; ++i) ca[i] = cb[i];
             tau += 4;
         }
         for (; tau < wend; ++tau)   // the last one to three periods
-            decode_step(s, __builtin_amdgcn_sbfe(m, tau & 31, 1), __builtin_amdgcn_sbfe(r, tau & 31, 1), tau, row[tau]);
+            decode_step<MODEL>(s, __builtin_amdgcn_sbfe(m, tau & 31, 1), __builtin_amdgcn_sbfe(r, tau & 31, 1), tau,
+                               row[tau]);
     }
-    return decode_finish<NW>(s, b, T, pp);
+    int32_t credit = 0;
+    if constexpr ((MODEL & kModelDispose) != 0) credit = dispose_credit<NW>(b, row, T, s.XR);
+    return decode_finish<NW>(s, b, T, pp, credit);
 }
 
 // Apply a move given as (block, t) to the first NW setup words of b: block 0 flips zM(t), 1 flips zR(t),
@@ -189,8 +231,8 @@ __device__ __forceinline__ void xor_move(Bits &b, int blk, int t) {
     }
 }
 
-// Feasibility of a pattern: only the periods before the first manufacturing setup can fail (afterwards
-// every shortfall is made by a manufacturing lot).  Uniform use by a whole wave.
+// Feasibility of a pattern under the carry-back reading: only the periods before the first manufacturing
+// setup can fail (afterwards every shortfall is made by a manufacturing lot).  Uniform use by a whole wave.
 template <class RowPtr>
 __device__ __forceinline__ bool feasible(const Bits &b, RowPtr row, int T) {
     int32_t lim = 0, XR = 0;
@@ -210,6 +252,17 @@ __device__ __forceinline__ bool feasible(const Bits &b, RowPtr row, int T) {
         XR = xn;
     }
     return true;
+}
+
+// Whether a shaken product's pattern is feasible under the reading MODEL: with the carry-back reading a
+// manufacturing setup in period 0 is enough, else the prefix check; with the strict reading the full decode.
+template <int MODEL, class RowPtr>
+__device__ __forceinline__ bool shake_feasible(const Bits &b, RowPtr row, int T, const ProdParams &pp) {
+    if constexpr ((MODEL & kModelStrict) != 0) {
+        return decode_cost<kWords, MODEL & kModelStrict>(b, row, T, pp) != kInf;
+    } else {
+        return (b.m[0] & 1u) != 0u || feasible(b, row, T);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------------

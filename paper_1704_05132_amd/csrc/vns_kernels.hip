@@ -26,6 +26,7 @@ namespace vns {
 // k_init_costs: one workgroup per chain.  Costs of the current solution, copy to the working solution,
 // F, best, shake size 1.
 // ---------------------------------------------------------------------------------------------------
+template <int MODEL>
 __global__ __launch_bounds__(256) void k_init_costs(InitArgs a) {
     const int g = a.chain0 + blockIdx.x;
     const ChainInfo ci = a.chains[g];
@@ -35,7 +36,7 @@ __global__ __launch_bounds__(256) void k_init_costs(InitArgs a) {
         const ProdParams pp = a.prod[ci.prod0 + p];
         const int64_t cp = ci.cp0 + p;
         const Bits b = a.cur[cp];
-        const int64_t c = decode_cost(b, a.rows + pp.row, ci.T, pp);
+        const int64_t c = decode_cost<kWords, MODEL>(b, a.rows + pp.row, ci.T, pp);
         a.cur_cost[cp] = c;
         a.work[cp] = b;
         a.work_cost[cp] = c;
@@ -92,7 +93,7 @@ static_assert(kEvalGroup <= 16 && kTMax <= 128, "item packing");
 __device__ __forceinline__ uint16_t pack_item(int j, int blk, int t) { return (uint16_t)((j << 9) | (blk << 7) | t); }
 
 // One lane per item: apply the move to the chain's pattern, decode, fold (cost, slot) into the chain's key.
-template <int NW>
+template <int NW, int MODEL>
 __device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, int N, int T, const ProdParams &pp) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int basei = wave * 64; basei < N; basei += blockDim.x) {
@@ -103,7 +104,7 @@ __device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, in
         const int slot = blk * T + t;
         Bits mb = sh.bits[j];
         xor_move<NW>(mb, blk, t);
-        const int64_t c = decode_cost<NW>(mb, sh.row, T, pp);
+        const int64_t c = decode_cost<NW, MODEL>(mb, sh.row, T, pp);
         if (in) {
             if (c != kInf) atomicMin(&sh.key[j], ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
             if (a.slot_price) a.slot_price[sh.out_off[j] + slot] = c == kInf ? kInf : sh.F[j] - sh.cost[j] + c;
@@ -219,7 +220,7 @@ __device__ __forceinline__ void eval_items_inc(const EvalArgs &a, EvalShared &sh
     atomicAdd(&sh.decoded, decoded);
 }
 
-template <bool INC>
+template <bool INC, int MODEL = 0>
 __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__restrict__ wg, EvalShared &sh,
                                           int4 *s_snap) {
     const EvalWg d = wg[blockIdx.x];
@@ -345,9 +346,9 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
             eval_items_inc<4>(a, sh, snapA, snapB, N, T, pp);
     } else {
         if (T <= 64)
-            eval_items<2>(a, sh, N, T, pp);
+            eval_items<2, MODEL>(a, sh, N, T, pp);
         else
-            eval_items<4>(a, sh, N, T, pp);
+            eval_items<4, MODEL>(a, sh, N, T, pp);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x) a.prod_key[d.cp + (int64_t)j * K] = sh.key[j];
@@ -363,9 +364,10 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
 
 }  // namespace
 
+template <int MODEL>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restrict__ wg) {
     __shared__ EvalShared sh;
-    eval_body<false>(a, wg, sh, nullptr);
+    eval_body<false, MODEL>(a, wg, sh, nullptr);
 }
 
 // The same sweep priced incrementally; dynamic LDS holds the base snapshots (24 bytes per chain and period).
@@ -521,7 +523,7 @@ struct SpecShared {
     int32_t next;         // next product index to hand out
 };
 
-template <bool SPEC, bool LEARNED, bool COOP = false>
+template <bool SPEC, bool LEARNED, bool COOP = false, int MODEL = 0>
 __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecShared &sp, int2 *s_rows) {
     static_assert(!(SPEC && LEARNED), "the speculative VND prices whole neighbourhoods");
     static_assert(!(COOP && SPEC), "speculative iterations run the sequential VND");
@@ -667,8 +669,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 Bits b = s_cur[draw ? pd : 0];
                 if (draw) {
                     apply_move(b, ld, T);
-                    ok = (b.m[0] & 1u) != 0u;   // a manufacturing setup in period 0 makes any pattern feasible
-                    if (!ok) ok = rows_in_lds ? feasible(b, s_rows + pd * T, T) : feasible(b, inst_rows + pd * T, T);
+                    const ProdParams pp = a.prod[ci.prod0 + pd];
+                    ok = rows_in_lds ? shake_feasible<MODEL>(b, s_rows + pd * T, T, pp)
+                                     : shake_feasible<MODEL>(b, inst_rows + pd * T, T, pp);
                 }
                 const unsigned long long okm = __ballot(ok);
                 if (ok) {
@@ -686,9 +689,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
                     Bits b = e >= 0 ? sh.db[e] : s_cur[p];
                     apply_move(b, l, T);
-                    // a manufacturing setup in period 0 makes any pattern feasible; otherwise check the prefix
-                    bool ok = (b.m[0] & 1u) != 0u;
-                    if (!ok) ok = rows_in_lds ? feasible(b, s_rows + p * T, T) : feasible(b, inst_rows + p * T, T);
+                    const ProdParams pp = a.prod[ci.prod0 + p];
+                    const bool ok = rows_in_lds ? shake_feasible<MODEL>(b, s_rows + p * T, T, pp)
+                                                : shake_feasible<MODEL>(b, inst_rows + p * T, T, pp);
                     if (ok) {
                         if (e < 0) {
                             e = nd++;
@@ -899,7 +902,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                             }
                         } else {
                             int64_t idc = 0;
-                            key = wave_best_move(b, row, T, pp, nb, sh.list[wave], need_ident, &idc, evals, chash, &ckey,
+                            key = wave_best_move<MODEL>(b, row, T, pp, nb, sh.list[wave], need_ident, &idc, evals, chash,
+                                                        &ckey,
                                                  &nitems);
                             if (need_ident) {
                                 cost = idc;
@@ -1252,11 +1256,12 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
 
 }  // namespace
 
+template <int MODEL>
 __global__ __launch_bounds__(512) void k_run(RunArgs a) {
     __shared__ RunShared sh;
     __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
-    run_chain<false, false>(a, sh, sp, s_rows);
+    run_chain<false, false, false, MODEL>(a, sh, sp, s_rows);
 }
 
 __global__ __launch_bounds__(1024) void k_run_spec(RunArgs a) {
@@ -1268,11 +1273,12 @@ __global__ __launch_bounds__(1024) void k_run_spec(RunArgs a) {
 
 // speculative iterations: m workgroups per chain compute the next m iterations side by side (cooperative
 // launch: every workgroup of a chain is resident while it waits for the others)
+template <int MODEL>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_run_coop(RunArgs a) {
     __shared__ RunShared sh;
     __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
-    run_chain<false, false, true>(a, sh, sp, s_rows);
+    run_chain<false, false, true, MODEL>(a, sh, sp, s_rows);
 }
 
 // learned VND: the scorer's weight fragments stay in registers for the whole launch
@@ -1332,16 +1338,34 @@ __global__ void k_advance(int64_t *it, int32_t iters) { *it += iters; }
 // ---------------------------------------------------------------------------------------------------
 // Host-side launchers (called by the runtime).
 // ---------------------------------------------------------------------------------------------------
-hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s) {
+// One instantiation per decode reading (kModelStrict | kModelDispose).
+template <template <int> class Pick>
+static const void *by_model(int model) {
+    switch (model) {
+        case 1: return Pick<1>::fn();
+        case 2: return Pick<2>::fn();
+        case 3: return Pick<3>::fn();
+        default: return Pick<0>::fn();
+    }
+}
+template <int M> struct PickInit { static const void *fn() { return reinterpret_cast<const void *>(&k_init_costs<M>); } };
+template <int M> struct PickEval { static const void *fn() { return reinterpret_cast<const void *>(&k_eval<M>); } };
+template <int M> struct PickRun { static const void *fn() { return reinterpret_cast<const void *>(&k_run<M>); } };
+template <int M> struct PickCoop { static const void *fn() { return reinterpret_cast<const void *>(&k_run_coop<M>); } };
+
+hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s, int model) {
     if (n_chains <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init_costs, dim3(n_chains), dim3(256), 0, s, a);
-    return hipGetLastError();
+    InitArgs args = a;
+    void *params[] = {&args};
+    return hipLaunchKernel(by_model<PickInit>(model), dim3(n_chains), dim3(256), params, 0, s);
 }
 
-hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s) {
+hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s, int model) {
     if (n_wg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_eval, dim3((unsigned)n_wg), dim3(256), 0, s, a, wg);
-    return hipGetLastError();
+    EvalArgs args = a;
+    const EvalWg *w = wg;
+    void *params[] = {&args, &w};
+    return hipLaunchKernel(by_model<PickEval>(model), dim3((unsigned)n_wg), dim3(256), params, 0, s);
 }
 
 hipError_t launch_eval_prep(const EvalPrepArgs &a, hipStream_t s) {
@@ -1369,16 +1393,16 @@ hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64
     return hipGetLastError();
 }
 
-static const void *run_kernel(RunKind kind) {
+static const void *run_kernel(RunKind kind, int model) {
     switch (kind) {
         case RunKind::kSpec: return reinterpret_cast<const void *>(&k_run_spec);
         case RunKind::kLearned: return reinterpret_cast<const void *>(&k_run_learned);
-        default: return reinterpret_cast<const void *>(&k_run);
+        default: return by_model<PickRun>(model);
     }
 }
 
-hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_bytes) {
-    const void *fn = run_kernel(kind);
+hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_bytes, int model) {
+    const void *fn = run_kernel(kind, model);
     hipFuncAttributes fa;
     hipError_t e = hipFuncGetAttributes(&fa, fn);
     if (e != hipSuccess) return e;
@@ -1386,13 +1410,13 @@ hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_byt
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes);
 }
 
-static const void *coop_kernel(bool learned) {
-    return learned ? reinterpret_cast<const void *>(&k_run_learned_coop) : reinterpret_cast<const void *>(&k_run_coop);
+static const void *coop_kernel(bool learned, int model) {
+    return learned ? reinterpret_cast<const void *>(&k_run_learned_coop) : by_model<PickCoop>(model);
 }
 
-hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bool learned) {
+hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bool learned, int model) {
     *fits = false;
-    const void *fn = coop_kernel(learned);
+    const void *fn = coop_kernel(learned, model);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     int per_cu = 0, dev = 0, cus = 0;
@@ -1407,11 +1431,11 @@ hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bo
 }
 
 hipError_t launch_run_coop(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
-                           hipStream_t s, bool learned) {
+                           hipStream_t s, bool learned, int model) {
     if (n_chains <= 0 || a.iters <= 0) return hipSuccess;
     RunArgs args = a;
     void *params[] = {&args};
-    hipError_t e = hipLaunchCooperativeKernel(coop_kernel(learned),
+    hipError_t e = hipLaunchCooperativeKernel(coop_kernel(learned, model),
                                               dim3((unsigned)(n_chains * a.coop_m)), dim3(64 * waves), params,
                                               (unsigned)lds_bytes, s);
     if (e != hipSuccess) return e;
@@ -1420,15 +1444,11 @@ hipError_t launch_run_coop(const RunArgs &a, int n_chains, int waves, size_t lds
 }
 
 hipError_t launch_run(const RunArgs &a, RunKind kind, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
-                      hipStream_t s) {
+                      hipStream_t s, int model) {
     if (n_chains <= 0 || a.iters <= 0) return hipSuccess;
-    if (kind == RunKind::kSpec)
-        hipLaunchKernelGGL(k_run_spec, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
-    else if (kind == RunKind::kLearned)
-        hipLaunchKernelGGL(k_run_learned, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
-    else
-        hipLaunchKernelGGL(k_run, dim3(n_chains), dim3(64 * waves), lds_bytes, s, a);
-    hipError_t e = hipGetLastError();
+    RunArgs args = a;
+    void *params[] = {&args};
+    hipError_t e = hipLaunchKernel(run_kernel(kind, model), dim3(n_chains), dim3(64 * waves), params, lds_bytes, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(1), 0, s, it_counter, a.iters);
     return hipGetLastError();

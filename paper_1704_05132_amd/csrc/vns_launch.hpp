@@ -36,7 +36,8 @@ struct ChainBestArgs {
 enum class RunKind { kPlain = 0, kSpec = 1, kLearned = 2 };
 
 // Static LDS bytes of a search kernel variant, and permission for it to request dynamic_bytes more.
-hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_bytes);
+// model: the decode reading (kModelStrict | kModelDispose; the plain sequential VND only).
+hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_bytes, int model);
 // Learned scorer (vns_mlp.hip).  P: 5313 float32 parameters.  Scores of n feature rows [n][16].
 hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *out, hipStream_t s);
 // Gradient (and loss in grad_out[5313]) of the mean squared error over rows idx[0..n) (all rows when idx is
@@ -66,9 +67,9 @@ struct EvalLearnedArgs {
     int32_t permille;
 };
 
-hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s);
+hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s, int model);
 hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64_t n_cp, hipStream_t s);
-hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s);
+hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s, int model);
 // The pricing table of a chain range and zeroed counters, built on the device (no host staging).
 hipError_t launch_eval_prep(const EvalPrepArgs &a, hipStream_t s);
 // Incremental pricing of the same sweep; lds_bytes of dynamic LDS hold each workgroup's base snapshots
@@ -78,12 +79,12 @@ hipError_t launch_chain_best(const ChainBestArgs &a, int n_chains, hipStream_t s
 // Speculative iterations (a.coop_m workgroups per chain, cooperative launch): whether blocks workgroups of
 // `waves` wavefronts and lds_bytes of dynamic LDS are all resident at once, and the launch itself (then the
 // device iteration counter advances by a.iters).  learned: the learned search's kernel.
-hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bool learned);
+hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bool learned, int model);
 hipError_t launch_run_coop(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
-                           hipStream_t s, bool learned);
+                           hipStream_t s, bool learned, int model);
 // The search kernel variant `kind` over n_chains workgroups, then the device iteration counter advances by a.iters (two kernels on s;
 // both can be captured in a graph).
 hipError_t launch_run(const RunArgs &a, RunKind kind, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
-                      hipStream_t s);
+                      hipStream_t s, int model);
 
 }  // namespace vns

@@ -105,6 +105,7 @@ struct vns_ctx {
     int32_t best_of = 0;                  // best-of-G search: streams per iteration (0, 1 = the plain chain)
     int32_t best_literal = 0;             //   as printed (k fixed, the minimum always kept)
     int32_t eval_inc = 0;                 // pricing sweeps decode each move only until it rejoins the base
+    int32_t model = 0;                    // decode reading: kModelStrict | kModelDispose (VNS_OPT_DECODE)
     CoopCtl *d_coop_ctl = nullptr;        // speculative iterations: per-chain control, per-slot summaries and
     CoopSlot *d_coop_slot = nullptr;      //   VND results
     Bits *d_coop_res = nullptr;
@@ -341,7 +342,7 @@ static vns_status setup_chains(vns_ctx *c) {
     VNS_HIP(c, hipMemcpyAsync(c->d_cur, bits.data(), sizeof(Bits) * (size_t)cp, hipMemcpyHostToDevice, c->stream));
     InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs,
                 c->d_bestx, 0};
-    VNS_HIP(c, launch_init(ia, (int)G, c->stream));
+    VNS_HIP(c, launch_init(ia, (int)G, c->stream, c->model));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     c->iteration = 0;
     c->stats = vns_stats{};
@@ -577,6 +578,10 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v != 0 && v != 1) return fail(c, VNS_EINVAL, "eval_incremental must be 0 or 1");
             c->eval_inc = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_DECODE:
+            if (v < 0 || v >= kModels) return fail(c, VNS_EINVAL, "decode reading must be in 0..3");
+            c->model = (int32_t)v;
+            return setup_chains(c);   // every chain restarts from the initial solution under the new costs
         case VNS_OPT_LEARNED:
             if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
             c->permille = (int32_t)v;
@@ -620,6 +625,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_BEST_OF: *v = c->best_of; return VNS_OK;
         case VNS_OPT_BEST_OF_LITERAL: *v = c->best_literal; return VNS_OK;
         case VNS_OPT_EVAL_INCREMENTAL: *v = c->eval_inc; return VNS_OK;
+        case VNS_OPT_DECODE: *v = c->model; return VNS_OK;
         case VNS_OPT_LOG: *v = c->log_cap; return VNS_OK;
         default: return fail(const_cast<vns_ctx *>(c), VNS_EINVAL, "unknown option");
     }
@@ -748,6 +754,8 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
                                              int32_t *best_slot) {
     VNS_LIVE(c);
     if (nb_mask == 0 || (nb_mask & ~7u)) return fail(c, VNS_EINVAL, "bad neighbourhood mask");
+    if (c->eval_inc && c->model != 0)
+        return fail(c, VNS_EINVAL, "incremental pricing takes only the default decode reading (VNS_OPT_DECODE = 0)");
     int32_t g0, ng;
     if (chain == VNS_ALL_CHAINS) {
         g0 = 0;
@@ -838,7 +846,7 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
         VNS_HIP(c, launch_eval_inc(ea, d_tab, c->eval_wg_n, (size_t)group * (size_t)(maxT + 1) * kSnapBytes,
                                    c->stream));
     else
-        VNS_HIP(c, launch_eval(ea, d_tab, c->eval_wg_n, c->stream));
+        VNS_HIP(c, launch_eval(ea, d_tab, c->eval_wg_n, c->stream, c->model));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     ChainBestArgs cb{c->d_chains, c->d_cs, c->d_cur_cost, c->d_prod_key, c->d_prod_price, c->d_prod_slot,
                      c->d_best, c->d_best_slot, g0};
@@ -929,7 +937,7 @@ extern "C" vns_status vns_eval_neighbourhood_noalloc(vns_ctx *c, uint32_t nb_mas
     ea.evals = ctr;
     ea.nb_mask = nb_mask;
     VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-    VNS_HIP(c, launch_eval(ea, tab, n_cp, c->stream));
+    VNS_HIP(c, launch_eval(ea, tab, n_cp, c->stream, c->model));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     ChainBestArgs cb{c->d_chains, c->d_cs, c->d_cur_cost, keys - cp_begin, c->d_prod_price, c->d_prod_slot, c->d_best,
                      c->d_best_slot, g0};
@@ -1012,7 +1020,10 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     const RunKind kind = c->permille > 0 ? RunKind::kLearned : spec ? RunKind::kSpec : RunKind::kPlain;
     const int waves = spec ? c->spec_waves : c->run_waves;
     size_t static_lds = 0;
-    VNS_HIP(c, run_kernel_lds(kind, &static_lds, 0));
+    if (c->model != 0 && kind != RunKind::kPlain)
+        return fail(c, VNS_EINVAL, "the learned search and the speculative VND take only the default decode reading "
+                                   "(VNS_OPT_DECODE = 0)");
+    VNS_HIP(c, run_kernel_lds(kind, &static_lds, 0, c->model));
     const int64_t learned = c->permille > 0 ? (int64_t)waves * kLearnedWaveBytes : 0;
     const int64_t room = c->max_lds_per_wg - (int64_t)static_lds - learned;   // dynamic LDS left for rows
     const int64_t slices = (int64_t)waves * kTMax;                   // per-wave rows when the instance does not fit
@@ -1031,7 +1042,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     const size_t rows_bytes = (size_t)run_rows_entries(ra.lds_rows, waves) * sizeof(int2);
     ra.state_off = state_bytes > 0 ? (int32_t)(rows_bytes + (size_t)learned) : -1;
     const size_t lds = rows_bytes + (size_t)learned + (size_t)state_bytes;
-    VNS_HIP(c, run_kernel_lds(kind, &static_lds, lds));
+    VNS_HIP(c, run_kernel_lds(kind, &static_lds, lds, c->model));
     // speculative iterations: plain search without the move log (a discarded iteration's moves must not be
     // logged), not captured, and every workgroup of the launch resident at once
     // best-of-G (Algorithm 2): the same cooperative launch with G workgroups per chain, one per random stream
@@ -1045,12 +1056,12 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         if (kind != RunKind::kPlain || c->use_graph || ra.log_x != nullptr || c->spec_iters > 1)
             return fail(c, VNS_EINVAL, "best-of-G runs the plain search alone: no learned scorer, speculative VND or "
                                        "iterations, move log or graph capture");
-        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, false));
+        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, false, c->model));
         if (!coop)
             return fail(c, VNS_EINVAL, "best-of-G needs its G workgroups per chain resident at once: use fewer "
                                        "chains, wavefronts per workgroup or streams");
     } else if (m > 1 && kind != RunKind::kSpec && !c->use_graph && ra.log_x == nullptr) {
-        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, coop_learned));
+        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, coop_learned, c->model));
     }
     c->stats.last_run_spec_iters = coop && !best ? m : 1;
     CoopCtl *d_ctl = c->d_coop_ctl;
@@ -1109,7 +1120,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         ra.best_of = best ? 1 : 0;
         ra.best_literal = c->best_literal;
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-        VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream, coop_learned));
+        VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream, coop_learned, c->model));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     } else if (c->use_graph) {
         const int64_t key[5] = {iters, G, waves * 4 + (int64_t)kind, (int64_t)lds, (int64_t)(intptr_t)ra.trace};
@@ -1118,7 +1129,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         if (!same || !c->graph_exec) {
             drop_graph(c);
             VNS_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            hipError_t le = launch_run(ra, kind, (int)G, waves, lds, c->d_iter, c->stream);
+            hipError_t le = launch_run(ra, kind, (int)G, waves, lds, c->d_iter, c->stream, c->model);
             hipGraph_t gr = nullptr;
             hipError_t ce = hipStreamEndCapture(c->stream, &gr);
             if (le != hipSuccess) {
@@ -1135,7 +1146,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     } else {
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-        VNS_HIP(c, launch_run(ra, kind, (int)G, waves, lds, c->d_iter, c->stream));
+        VNS_HIP(c, launch_run(ra, kind, (int)G, waves, lds, c->d_iter, c->stream, c->model));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     }
     std::vector<ChainState> cs((size_t)G);
@@ -1237,7 +1248,7 @@ extern "C" vns_status vns_set_unit_costs(vns_ctx *c, const int32_t *pM, const in
     // every chain's costs from its current solution, as at creation: F = best = the new objective, k = 1
     InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs,
                 c->d_bestx, 0};
-    VNS_HIP(c, launch_init(ia, (int)c->chains.size(), c->stream));
+    VNS_HIP(c, launch_init(ia, (int)c->chains.size(), c->stream, c->model));
     VNS_HIP(c, hipStreamSynchronize(c->stream));
     c->prod_host = prod;
     return VNS_OK;
@@ -1246,7 +1257,7 @@ extern "C" vns_status vns_set_unit_costs(vns_ctx *c, const int32_t *pM, const in
 static vns_status reinit_chain(vns_ctx *c, int32_t chain) {
     InitArgs ia{c->d_chains, c->d_prod, c->d_rows, c->d_cur, c->d_cur_cost, c->d_work, c->d_work_cost, c->d_cs,
                 c->d_bestx, chain};
-    VNS_HIP(c, launch_init(ia, 1, c->stream));
+    VNS_HIP(c, launch_init(ia, 1, c->stream, c->model));
     return VNS_OK;
 }
 
@@ -1532,6 +1543,8 @@ extern "C" vns_status vns_eval_learned(vns_ctx *c, uint32_t nb, int32_t chain, i
                                        uint8_t *selected, int64_t *prod_best, int32_t *prod_best_slot, uint8_t *fallback) {
     VNS_LIVE(c);
     if (nb != VNS_NB_FLIP_M && nb != VNS_NB_FLIP_R && nb != VNS_NB_SHIFT) return fail(c, VNS_EINVAL, "nb must be one neighbourhood");
+    if (c->model != 0)
+        return fail(c, VNS_EINVAL, "the learned choice takes only the default decode reading (VNS_OPT_DECODE = 0)");
     if (top_permille < 1 || top_permille > 1000) return fail(c, VNS_EINVAL, "top_permille must be in 1..1000");
     vns_status st = check_chain(c, chain);
     if (st != VNS_OK) return st;

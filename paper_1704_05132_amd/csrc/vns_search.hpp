@@ -89,7 +89,7 @@ __device__ __forceinline__ int move_list(const Bits &b, int T, uint32_t nb, uint
 // One lane per item of a neighbourhood's move list (plus, at index nitems, the unchanged pattern when
 // total > nitems): exact costs folded into the lane's best key; the contrast item's key and the unchanged
 // pattern's cost are kept by the lanes that priced them.  NW setup words (2 when T <= 64).
-template <int NW>
+template <int NW, int MODEL = 0>
 __device__ __forceinline__ void price_items(const Bits &b, const int2 *row, int T, const ProdParams &pp,
                                             const uint16_t *list, int nitems, int nflip, bool fm, int total,
                                             int citem, uint64_t &best, uint64_t &ck, int64_t &idc) {
@@ -102,7 +102,7 @@ __device__ __forceinline__ void price_items(const Bits &b, const int2 *row, int 
             const int blk = (slot >= T) + (slot >= 2 * T) + (slot >= 3 * T);
             xor_move<NW>(mb, blk, slot - blk * T);
         }
-        const int64_t c = decode_cost<NW>(mb, row, T, pp);
+        const int64_t c = decode_cost<NW, MODEL>(mb, row, T, pp);
         if (idx == nitems) idc = c;
         const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
         if (idx == citem) ck = key;
@@ -114,6 +114,7 @@ __device__ __forceinline__ void price_items(const Bits &b, const int2 *row, int 
 // With `ident`, one more item prices the unchanged pattern and its cost is returned in *ident_cost.  With
 // contrast >= 0 (any non-negative hash), *contrast_key receives the key of item contrast mod the number of
 // moves (kInfKey when infeasible or when there is no move).
+template <int MODEL = 0>
 __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *row, int T, const ProdParams &pp,
                                                    uint32_t nb, uint16_t *list, bool ident, int64_t *ident_cost,
                                                    int64_t &evals, int contrast = -1, uint64_t *contrast_key = nullptr,
@@ -128,9 +129,9 @@ __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *ro
     int64_t idc = 0;
     const int citem = (contrast >= 0 && nitems > 0) ? contrast % nitems : -1;
     if (T <= 64)
-        price_items<2>(b, row, T, pp, list, nitems, nflip, fm, total, citem, best, ck, idc);
+        price_items<2, MODEL>(b, row, T, pp, list, nitems, nflip, fm, total, citem, best, ck, idc);
     else
-        price_items<4>(b, row, T, pp, list, nitems, nflip, fm, total, citem, best, ck, idc);
+        price_items<4, MODEL>(b, row, T, pp, list, nitems, nflip, fm, total, citem, best, ck, idc);
     if (ident) *ident_cost = __shfl(idc, nitems & 63, 64);
     if (contrast_key) *contrast_key = citem >= 0 ? __shfl(ck, citem & 63, 64) : kInfKey;
     return wave_min_u64(best);

@@ -21,7 +21,8 @@ VNS_OK, VNS_EINVAL, VNS_ENOMEM, VNS_EDEVICE, VNS_ERANGE, VNS_ESTATE = 0, -1, -2,
 NB_FLIP_M, NB_FLIP_R, NB_SHIFT = 1, 2, 4
 OPT_CHAINS, OPT_KMAX, OPT_NB_LIST, OPT_TRACE, OPT_RUN_WAVES, OPT_EVAL_GROUP, OPT_RUN_LDS, OPT_GRAPH = 1, 2, 3, 4, 5, 6, 7, 8
 OPT_LEARNED, OPT_LOG, OPT_SPECULATE, OPT_SPEC_WAVES, OPT_STATE_LDS, OPT_VND_MEMO = 9, 10, 11, 12, 13, 14
-OPT_SPEC_ITERS, OPT_BEST_OF, OPT_BEST_OF_LITERAL, OPT_EVAL_INCREMENTAL = 15, 16, 17, 18
+OPT_SPEC_ITERS, OPT_BEST_OF, OPT_BEST_OF_LITERAL, OPT_EVAL_INCREMENTAL, OPT_DECODE = 15, 16, 17, 18, 19
+DECODE_STRICT, DECODE_DISPOSE = 1, 2
 MLP_PARAMS, MLP_FEATURES = 5313, 16
 ALL_CHAINS = -1
 SOLUTION_CURRENT, SOLUTION_BEST = 0, 1
@@ -162,6 +163,11 @@ class Context:
         for key, val in (options or {}).items():
             self.set_option(key, val)
         self.chains_per_inst = int(chains)
+        models = {(1 if getattr(i, "strict", False) else 0) | (2 if getattr(i, "dispose", False) else 0) for i in insts}
+        if len(models) > 1:
+            raise ValueError("every instance of a context must take the same decode reading")
+        if models != {0}:
+            self.set_option(OPT_DECODE, models.pop())
         if any(i.has_unit_costs() for i in insts):
             u = [i.unit_costs() for i in insts]
             self.set_unit_costs(np.concatenate([a for a, _ in u]), np.concatenate([b for _, b in u]))
