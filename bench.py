@@ -28,7 +28,9 @@ Beside it, on the same GPU in the same run:
   * `time_to_plain_best_100x52`: the same comparison on the 100 x 52 instance (64 chains, 2000 iterations).
   * `cpu_baseline`: the CPU oracle's exact sweep (every move of the three neighbourhoods priced by its
     look-ahead decode) on a sample of the workload's instances, one thread and every host thread.
---workload paper_300x52 adds the Table-1-shaped comparison of the searches on 108 instances of 300 x 52.
+  * `paper_quality`: a Table-1-shaped comparison on the paper's benchmark shape (108 synthetic instances of
+    300 x 52): GVNS, best-of-4 in both forms and the learned search, the same device time each; the CPU leg
+    adds the oracle's serial VND from the initial solution.
 """
 from __future__ import annotations
 
@@ -108,8 +110,9 @@ def parse():
     ap.add_argument("--learned-permille", type=int, default=100, help="share of moves priced exactly (1/1000)")
     ap.add_argument("--learned-log-iters", type=int, default=200)
     ap.add_argument("--learned-epochs", type=int, default=8)
-    ap.add_argument("--quality-ms", type=float, default=2000.0,
-                    help="paper_300x52: device time each search arm of the quality table gets")
+    ap.add_argument("--quality-ms", type=float, default=1000.0,
+                    help="device time each search arm of the Table-1-shaped comparison gets")
+    ap.add_argument("--no-quality", action="store_true", help="skip the Table-1-shaped comparison on 300 x 52")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a device copy of this many MiB (counter calibration for profiling runs)")
     ap.add_argument("--valu-probe", action="store_true", help="run the VALU issue-rate probe and print its JSON")
@@ -397,12 +400,14 @@ def valu_probe():
     return out
 
 
-def paper_quality(args, vns, stream, insts, w):
+def paper_quality(args, vns, stream):
     """A table shaped like the paper's Table 1 on its benchmark shape (synthetic: 108 instances of 300
     products x 52 periods): every search gets the same device time on all instances at once, with 8
-    workgroups per instance, and the best cost per instance is compared across searches."""
+    workgroups per instance, and the best cost per instance is compared across searches.  The serial VND arm
+    (the oracle on the host) is added by the CPU-baseline leg, serial_vnd_arm."""
     import numpy as np
     from paper_1704_05132_amd.instances import workload
+    w, insts = workload_insts("paper_300x52")
     n, seed, nb = len(insts), w["seed"], w["nb"]
 
     def ctx_of(chains, options):
@@ -445,6 +450,7 @@ def paper_quality(args, vns, stream, insts, w):
     arms["learned"] = (run_for(make_learned, 8), 8, 1)
     table = np.stack([r[0] for r, _, _ in arms.values()])
     best = table.min(0)
+    paper_quality.best_per_instance = best   # the serial VND arm's gaps are measured against it
     out = {"instances": n, "K": insts[0].K, "T": insts[0].T, "device_ms_per_search": args.quality_ms,
            "chunk_iters": args.chunk, "logged_moves": int(len(y)), "note": "best cost per instance after the same "
            "device time; best_on counts the instances where a search holds the lowest cost (ties count for each)"}
@@ -452,6 +458,35 @@ def paper_quality(args, vns, stream, insts, w):
         out[a] = {"mean_best_F": float(table[i].mean()), "best_on": int((table[i] == best).sum()),
                   "mean_gap_pct": float(((table[i] - best) / best).mean() * 100), "iterations": it, "device_ms": ms,
                   "chains_per_instance": chains, "streams": streams}
+    return out
+
+
+def serial_vnd_arm(target_best):
+    """The serial VND arm of the Table-1-shaped comparison (the paper's serial baseline): the oracle's VND
+    (Algorithm 1, every product in every pass) from the initial solution zM = 1, zR = 0 on each of the 108
+    instances, one instance per host thread; its cost against the best the device searches reached."""
+    import numpy as np
+    import oracle
+    w, insts = workload_insts("paper_300x52")
+    nthreads = host_threads()
+
+    def one(inst):
+        t0 = time.perf_counter()
+        F, _, _, ev = oracle.vnd(inst, np.ones((inst.K, inst.T), np.uint8), np.zeros((inst.K, inst.T), np.uint8),
+                                 w["nb"])
+        return F, ev, time.perf_counter() - t0
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(nthreads) as ex:
+        res = list(ex.map(one, insts))
+    wall = time.perf_counter() - t0
+    F = np.array([r[0] for r in res], np.int64)
+    out = {"what": "oracle VND (Algorithm 1) from the initial solution, one instance per host thread",
+           "mean_F": float(F.mean()), "move_evals": int(sum(r[1] for r in res)),
+           "cpu_s_per_instance": float(np.mean([r[2] for r in res])), "wall_s": wall, "threads": nthreads}
+    if target_best is not None:
+        out["best_on"] = int((F <= target_best).sum())
+        out["mean_gap_pct"] = float(((F - target_best) / target_best).mean() * 100)
     return out
 
 
@@ -553,8 +588,8 @@ def main():
                                     w2["iters"], args.chunk)
                 out["time_to_plain_best_100x52"] = learned_vs_plain(args, vns, stream, table, key2, other, insts2,
                                                                     w2, p2)
-    if name == "paper_300x52":
-        out["paper_quality"] = paper_quality(args, vns, stream, insts, w)
+    if not args.only_sweep and not args.no_quality:
+        out["paper_quality"] = paper_quality(args, vns, stream)
 
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -567,6 +602,8 @@ def main():
     out["gpu_wall_s"] = time.perf_counter() - t_start
     if not args.no_cpu_baseline and not args.only_sweep:
         out["cpu_baseline"] = cpu_baseline(insts, w, name, args.cpu_seconds)
+        if "paper_quality" in out:
+            out["paper_quality"]["serial_vnd"] = serial_vnd_arm(getattr(paper_quality, "best_per_instance", None))
     print(json.dumps(out), flush=True)
 
 

@@ -275,3 +275,39 @@ def test_learned_search_local_optima_long_horizon(vns, T):
             rec = ctx.trajectory(g)
             assert (rec["F_local"] <= rec["F_shaken"]).all()
             assert ((rec["accepted"][1:] == 1) == (rec["F_local"][1:] < rec["F_best"][:-1])).all()
+
+
+def test_learned_vs_plain_on_the_batched_shape(vns):
+    """The learned search against the method without the network, at equal iterations on instances of the
+    learned + batched shape (T = 52 and 104, returns U(0.1, 0.9)): the scorer, trained on moves logged on
+    disjoint instances, lets the search price fewer moves exactly while it reaches costs within 1% of the plain
+    search's.  Device times are printed; on this GPU the learned search is the slower of the two (scoring
+    every move costs about as much as pricing it, and every VND ends with a full exact pass)."""
+    name = "learned_batched_1024"
+    pool = [workload(name, i) for i in range(64)]
+    insts = sorted(pool, key=lambda x: x.K)[:8]
+    assert {i.T for i in insts} == {52, 104}
+    train = [workload(name, 4096 + j) for j in range(4)]
+    with vns.Context(train, seed=5, chains=4, trace=False, options={vns.OPT_LOG: 500000}) as lg:
+        lg.run(100)
+        X, y = lg.move_log()
+    iters, chains = 150, 4
+    out = {}
+    for arm in ("plain", "learned"):
+        with vns.Context(insts, seed=5, chains=chains, trace=False) as ctx:
+            if arm == "learned":
+                ctx.mlp_init(7)
+                ctx.mlp_train(X, y, epochs=6, batch=4096, lr=2e-3, seed=11)
+                ctx.set_option(vns.OPT_LEARNED, 100)
+            ctx.run(iters)
+            st = ctx.stats()
+            best = ctx.costs()[1].reshape(len(insts), chains).min(1)
+            out[arm] = dict(ms=st["last_run_ms"], evals=st["last_run_evals"], best=best,
+                            nb_evals=st["last_run_learned_evals"], fallbacks=st["last_run_fallbacks"])
+    p, l = out["plain"], out["learned"]
+    say(f"  {iters} iterations: plain {p['ms']:.1f} ms, {p['evals']} exact evaluations, sum {p['best'].sum()}")
+    say(f"  learned: {l['ms']:.1f} ms, {l['evals']} exact evaluations ({l['evals'] / p['evals']:.2f}x), "
+        f"fallback rate {l['fallbacks'] / l['nb_evals']:.2f}, sum {l['best'].sum()} "
+        f"({(l['best'].sum() / p['best'].sum() - 1) * 100:+.3f}%)")
+    assert l["evals"] < p["evals"]
+    assert abs(l["best"].sum() / p["best"].sum() - 1) < 0.01
