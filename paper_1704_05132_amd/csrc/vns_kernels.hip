@@ -75,26 +75,31 @@ __global__ __launch_bounds__(256) void k_init_costs(InitArgs a) {
 namespace {
 
 struct EvalShared {
-    int2 row[kTMax];
-    Bits bits[kEvalGroup];
-    unsigned long long key[kEvalGroup];
-    int64_t F[kEvalGroup];
-    int64_t cost[kEvalGroup];
-    int64_t out_off[kEvalGroup];
-    int32_t off[kEvalGroup + 1];
-    int32_t nswap[kEvalGroup];
-    // the workgroup's moves, chain by chain (flips, then zM swaps, then zR swaps): chain << 9 | block << 7 | t
-    uint16_t item[kEvalGroup * 4 * kTMax];
+    int2 row[kTMax];              // the rows of the workgroup's products, one after the other (np T <= kTMax)
+    ProdParams pp[kEvalProds];    // their parameters (more than one product)
+    Bits bits[kEvalPairs];        // per (chain, product) pair j = product index * chains + chain index
+    unsigned long long key[kEvalPairs];
+    int64_t F[kEvalPairs];
+    int64_t cost[kEvalPairs];
+    int64_t out_off[kEvalPairs];
+    int32_t off[kEvalPairs + 1];
+    int32_t nswap[kEvalPairs];
+    // the workgroup's moves, pair by pair (flips, then zM swaps, then zR swaps): pair << 9 | block << 7 | t
+    uint16_t item[kEvalItems];
     int32_t tcount[kTMax];        // incremental pricing: moves per period, then their offsets
     int32_t decoded;              //   and the period-steps its batches ran, per lane
 };
-static_assert(kEvalGroup <= 16 && kTMax <= 128, "item packing");
+static_assert(kEvalPairs <= 128 && kTMax <= 128, "item packing");
+static_assert(kEvalGroup * 4 * kTMax <= kEvalItems, "one product of a full group of chains fits the item table");
 
 __device__ __forceinline__ uint16_t pack_item(int j, int blk, int t) { return (uint16_t)((j << 9) | (blk << 7) | t); }
 
-// One lane per item: apply the move to the chain's pattern, decode, fold (cost, slot) into the chain's key.
+// One lane per item: apply the move to the pair's pattern, decode, fold (cost, slot) into the pair's key.
+// One product (np = 1): its row and parameters are the same for every lane; several (short horizons): each
+// lane reads those of its pair's product.
 template <int NW, int MODEL>
-__device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, int N, int T, const ProdParams &pp) {
+__device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, int N, int T, const ProdParams &pp,
+                                           int nc, int np) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int basei = wave * 64; basei < N; basei += blockDim.x) {
         const int idx = basei + lane;
@@ -104,7 +109,13 @@ __device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, in
         const int slot = blk * T + t;
         Bits mb = sh.bits[j];
         xor_move<NW>(mb, blk, t);
-        const int64_t c = decode_cost<NW, MODEL>(mb, sh.row, T, pp);
+        int64_t c;
+        if (np == 1) {
+            c = decode_cost<NW, MODEL>(mb, sh.row, T, pp);
+        } else {
+            const int pi = j / nc;
+            c = decode_cost<NW, MODEL>(mb, sh.row + pi * T, T, sh.pp[pi]);
+        }
         if (in) {
             if (c != kInf) atomicMin(&sh.key[j], ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
             if (a.slot_price) a.slot_price[sh.out_off[j] + slot] = c == kInf ? kInf : sh.F[j] - sh.cost[j] + c;
@@ -224,18 +235,23 @@ template <bool INC, int MODEL = 0>
 __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__restrict__ wg, EvalShared &sh,
                                           int4 *s_snap) {
     const EvalWg d = wg[blockIdx.x];
-    if (d.n == 0) return;   // an empty entry of a device-built table (uniform for the workgroup)
-    const int g0 = d.g0, K = d.K, T = d.T, p = d.p, n = d.n;
+    if (d.n == 0) return;   // an empty entry (uniform for the workgroup)
+    const int g0 = d.g0, K = d.K, T = d.T, p = d.p, nc = d.n;
+    const int np = INC ? 1 : max(d.np, 1);
+    const int n = nc * np;  // pairs: j = product index * nc + chain index
     const ProdParams pp = a.prod[d.prod];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int t = threadIdx.x; t < T; t += blockDim.x) sh.row[t] = a.rows[d.row + t];
+    for (int t = threadIdx.x; t < np * T; t += blockDim.x) sh.row[t] = a.rows[d.row + t];
+    if (np > 1)
+        for (int q = threadIdx.x; q < np; q += blockDim.x) sh.pp[q] = a.prod[d.prod + q];
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const int64_t cp = d.cp + (int64_t)j * K;
+        const int pi = j / nc, ci = j - pi * nc;
+        const int64_t cp = d.cp + (int64_t)ci * K + pi;
         sh.bits[j] = a.cur[cp];
         sh.cost[j] = a.cur_cost[cp];
-        sh.F[j] = a.cstate[g0 + j].F;
+        sh.F[j] = a.cstate[g0 + ci].F;
         sh.key[j] = kInfKey;
-        sh.out_off[j] = a.slot_price ? a.price_off[g0 + j] + (int64_t)p * 4 * T : 0;
+        sh.out_off[j] = a.slot_price ? a.price_off[g0 + ci] + (int64_t)(p + pi) * 4 * T : 0;
     }
     __syncthreads();
 
@@ -346,12 +362,15 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
             eval_items_inc<4>(a, sh, snapA, snapB, N, T, pp);
     } else {
         if (T <= 64)
-            eval_items<2, MODEL>(a, sh, N, T, pp);
+            eval_items<2, MODEL>(a, sh, N, T, pp, nc, np);
         else
-            eval_items<4, MODEL>(a, sh, N, T, pp);
+            eval_items<4, MODEL>(a, sh, N, T, pp, nc, np);
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < n; j += blockDim.x) a.prod_key[d.cp + (int64_t)j * K] = sh.key[j];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const int pi = j / nc, ci = j - pi * nc;
+        a.prod_key[d.cp + (int64_t)ci * K + pi] = sh.key[j];
+    }
     if (threadIdx.x == 0) {
         unsigned long long *ctr = a.evals + (size_t)(blockIdx.x & (kCounterSlots - 1)) * kCounterStride;
         atomicAdd(ctr, (unsigned long long)N);
@@ -398,6 +417,7 @@ __global__ __launch_bounds__(256) void k_eval_prep(EvalPrepArgs a) {
             w.p = p;
             w.prod = ci.prod0 + p;
             w.row = a.prod[ci.prod0 + p].row;
+            w.np = 1;
         }
         a.table[i] = w;
     }

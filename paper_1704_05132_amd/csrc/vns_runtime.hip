@@ -152,7 +152,8 @@ struct vns_ctx {
     int64_t graph_key[5] = {-1, -1, -1, -1, -1};  // (iters, chains, waves, LDS bytes, trace buffer)
     EvalWg *d_eval_wg = nullptr;          // k_eval workgroup table of the last chain range priced
     int64_t eval_wg_n = 0;
-    int64_t eval_wg_key[3] = {-1, -1, -1};  // (first chain, number of chains, group size) of that table
+    int64_t eval_wg_key[4] = {-1, -1, -1, -1};  // (first chain, number of chains, group size, incremental) of
+                                                 // that table (incremental pricing takes one product per entry)
 
     char *ws = nullptr;                   // caller-owned workspace (vns_bind_workspace), its size and flags
     size_t ws_bytes = 0;
@@ -249,7 +250,7 @@ static void free_chains(vns_ctx *c) {
     c->trace_iters = 0;
     dfree(c->d_eval_wg);
     c->eval_wg_n = 0;
-    c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = -1;
+    c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = c->eval_wg_key[3] = -1;
 }
 
 static void free_log(vns_ctx *c) {
@@ -707,7 +708,7 @@ extern "C" vns_status vns_bind_workspace(vns_ctx *c, void *p, size_t bytes, uint
     if (flags & ~(VNS_WS_RUN | VNS_WS_EVAL | VNS_WS_EVAL_PRICES)) return fail(c, VNS_EINVAL, "unknown workspace flags");
     VNS_HIP(c, hipStreamSynchronize(c->stream));   // no running call still uses the previous buffer
     drop_graph(c);
-    c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = -1;   // the cached table lives in one of them
+    c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = c->eval_wg_key[3] = -1;   // the cached table lives in one of them
     if (!p || flags == 0) {
         c->ws = nullptr;
         c->ws_bytes = 0;
@@ -793,16 +794,27 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     const int32_t group = c->eval_inc ? std::max<int32_t>(1, std::min<int32_t>(c->eval_group,
                                                                               kSnapLdsMax / ((maxT + 1) * kSnapBytes)))
                                       : c->eval_group;
-    const int64_t key[3] = {g0, ng, group};
+    const int64_t key[4] = {g0, ng, group, c->eval_inc};
     EvalWg *d_tab = ws_tab ? reinterpret_cast<EvalWg *>(c->ws + wl.eval_off) : c->d_eval_wg;
-    if (!(key[0] == c->eval_wg_key[0] && key[1] == c->eval_wg_key[1] && key[2] == c->eval_wg_key[2])) {
+    if (!(key[0] == c->eval_wg_key[0] && key[1] == c->eval_wg_key[1] && key[2] == c->eval_wg_key[2] &&
+          key[3] == c->eval_wg_key[3])) {
         std::vector<EvalWg> tab;
         int32_t g = g0;
         while (g < g0 + ng) {
             const ChainInfo &ci = c->chains[(size_t)g];
             int32_t n = 1;
             while (n < group && g + n < g0 + ng && c->chains[(size_t)(g + n)].inst == ci.inst) ++n;
-            for (int32_t p = 0; p < ci.K; ++p) {
+            // short horizons (T <= 32): several products per workgroup, so that a workgroup prices about 1024
+            // moves (about 3T per pair) and its set-up is shared; their rows, pairs and moves must fit its LDS.
+            // Longer horizons keep one product per workgroup: fewer, larger workgroups made the 100 x 52 sweep
+            // (1300 workgroups) slower.
+            int32_t np = 1;
+            if (!c->eval_inc && ci.T <= kEvalShortT) {
+                const int32_t want = (kEvalTargetMoves + 3 * n * ci.T - 1) / (3 * n * ci.T);
+                np = std::max<int32_t>(1, std::min({want, kTMax / ci.T, kEvalPairs / n, kEvalProds,
+                                                    kEvalItems / (4 * n * ci.T)}));
+            }
+            for (int32_t p = 0; p < ci.K; p += np) {
                 EvalWg w{};
                 w.cp = ci.cp0 + p;
                 w.g0 = g;
@@ -812,12 +824,13 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
                 w.p = p;
                 w.prod = ci.prod0 + p;
                 w.row = c->prod_row[(size_t)(ci.prod0 + p)];
+                w.np = std::min<int32_t>(np, ci.K - p);
                 tab.push_back(w);
             }
             g += n;
         }
         c->eval_wg_n = 0;
-        c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = -1;
+        c->eval_wg_key[0] = c->eval_wg_key[1] = c->eval_wg_key[2] = c->eval_wg_key[3] = -1;
         if (!ws_tab) {
             dfree(c->d_eval_wg);
             VNS_HIP(c, dmalloc(&c->d_eval_wg, tab.size()));
@@ -825,7 +838,7 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
         }
         VNS_HIP(c, hipMemcpyAsync(d_tab, tab.data(), sizeof(EvalWg) * tab.size(), hipMemcpyHostToDevice, c->stream));
         c->eval_wg_n = (int64_t)tab.size();
-        for (int i = 0; i < 3; ++i) c->eval_wg_key[i] = key[i];
+        for (int i = 0; i < 4; ++i) c->eval_wg_key[i] = key[i];
     }
     EvalArgs ea{};
     ea.cp_chain = c->d_cp_chain;

@@ -20,6 +20,11 @@ constexpr int kTMax = 32 * kWords;
 constexpr int kShakeMax = 64;
 constexpr int kMaxWaves = 16;     // wavefronts per search workgroup (8 for the sequential VND, 16 speculative)
 constexpr int kEvalGroup = 16;
+constexpr int kEvalPairs = 64;    // (chain, product) pairs one pricing workgroup may price
+constexpr int kEvalProds = 8;     //   of at most this many products (short horizons: their rows share LDS)
+constexpr int kEvalItems = 8192;  //   and at most this many moves
+constexpr int kEvalTargetMoves = 1024;  // moves a pricing workgroup should get (4 passes of its 256 lanes)
+constexpr int kEvalShortT = 32;         //   by pricing several products when T is at most this
 constexpr int kSnapBytes = 24;          // incremental pricing: base state per chain and period (int4 + int2)
 constexpr int kSnapLdsMax = 40 * 1024;  //   and the dynamic LDS a pricing workgroup may use for them
 // Workgroup counters are spread over kCounterSlots slots, kCounterStride words apart (one 64-byte line
@@ -165,18 +170,17 @@ __host__ __device__ inline int run_rows_entries(int lds_rows, int waves) {
     return (e + 1) & ~1;
 }
 
-// One k_eval workgroup: product cp - chains[cp_chain[cp]].cp0 of the n consecutive chains starting with the
-// chain of cp (chains of one instance are consecutive, their products K apart).
-// One pricing workgroup: product p of chains g0 .. g0+n-1 of one instance.  Everything the workgroup needs
-// to start is here, so its first loads do not wait on one another.
+// One pricing workgroup: products p .. p+np-1 of chains g0 .. g0+n-1 of one instance (chains of an instance
+// are consecutive, their products K apart; its products' rows are consecutive).  n = 0: an empty entry.
+// Everything the workgroup needs to start is here, so its first loads do not wait on one another.
 struct EvalWg {
     int64_t cp;      // (chain g0, product p) index into the solution arrays
     int32_t g0, n;   // first chain, number of chains
     int32_t K, T;    // the instance's products and periods
-    int32_t p;       // product index within the instance
-    int32_t prod;    // global product index (ProdParams)
-    int32_t row;     // offset of the product's row
-    int32_t pad;
+    int32_t p;       // first product index within the instance
+    int32_t prod;    // its global product index (ProdParams)
+    int32_t row;     // offset of its row
+    int32_t np;      // products (1, or more for short horizons)
 };
 
 // The pricing workgroup table built on the device, for the allocation-free pricing call: entry i is the
