@@ -182,6 +182,15 @@ def sweep_steps(torch, vns, ctx, stream, steps, warmup):
             "frac": achieved / (VALU_PEAK_OPS / 1e12)}
 
 
+def warm_search(vns, make_ctx):
+    """A few iterations on a throwaway context of the same launch shape.  The first cooperative launch in a
+    process waits for the runtime's one-time set-up (a 4.5 ms gap before the kernel starts on the 100 x 52
+    launch), which the library's events would otherwise count as search time."""
+    c = make_ctx()
+    c.run(4)
+    c.close()
+
+
 def search_once(vns, ctx, iters):
     """One launch of `iters` GVNS iterations of every chain; the search kernel's rate and roofline (the
     evaluations the search consumed; speculative iterations thrown away are counted apart)."""
@@ -527,6 +536,7 @@ def main():
     #     states it reached, and its per-instance bests are the learned search's targets ---
     if args.only_sweep:   # one search launch (a profiler sees one dispatch of the search kernel)
         plain = None
+        warm_search(vns, lambda: new_ctx(vns, insts, w, stream, table, key))
         ctx = new_ctx(vns, insts, w, stream, table, key)
         search_main = search_once(vns, ctx, iters)
         search_main["best_F_sum"] = int(ctx.costs()[1].reshape(len(insts), w["chains"]).min(1).sum())
@@ -576,10 +586,9 @@ def main():
                 continue
             w2, insts2 = workload_insts(other)
             key2 = autotune.signature(insts2, w2["chains"])
+            warm_search(vns, lambda: new_ctx(vns, insts2, w2, stream, table, key2))
             c2 = new_ctx(vns, insts2, w2, stream, table, key2)
             s2 = search_once(vns, c2, w2["iters"])
-            if other == "plain_100x52":
-                s2["traffic"] = measured_traffic(s2["kernel"], other, "search")
             out["search"][other] = s2
             out["sweeps"][other] = sweep_steps(torch, vns, c2, stream, max(args.steps, 20), args.warmup)
             c2.close()
