@@ -505,21 +505,6 @@ __device__ __forceinline__ int next_index(int32_t &counter, int lane) {
     return __shfl(v, 0, 64);
 }
 
-// Bounded wait until *p >= v, false if the wait ran out (after `ticks` of the steady clock, or
-// kCoopSpinLimit polls).  The polls are relaxed (an acquire per poll would invalidate the caches the other
-// workgroups of the XCD are working from); one acquire follows success.
-__device__ __forceinline__ bool coop_wait_ge(int32_t *p, int32_t v, int64_t ticks) {
-    const int64_t t0 = wall_clock64();
-    for (uint32_t n = 0; n < kCoopSpinLimit; ++n) {
-        if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= v) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            return true;
-        }
-        if (wall_clock64() - t0 > ticks) return false;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return false;
-}
 
 // Speculative VND (plain search): each product in work is handled by a group of n_nb wavefronts, one per
 // neighbourhood of the list.  In every round the neighbourhoods not yet settled in the current pass are
@@ -616,6 +601,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     const uint64_t nflip_all = 2ull * (uint64_t)K * (uint64_t)T;
 
     int32_t coop_round = 0;   // speculative iterations: the round this workgroup computes
+    int32_t coop_known = -1;  //   thread 0: the round counter as last acquired (-1: not yet)
     int64_t done_it = 0;      //   and the iterations resolved before it
     int64_t executed = 0;     //   move-evaluations this workgroup computed (thread 0)
     for (int i = 0; COOP || i < a.iters; ++i) {
@@ -633,7 +619,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             // then reads a newer state than that round's; its summary carries the older round and is
             // never used.
             if (threadIdx.x == 0) {
-                sh.coop_round = __hip_atomic_load(&a.coop_ctl[g].round, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                sh.coop_round = coop_known >= 0 ? coop_known
+                                                : __hip_atomic_load(&a.coop_ctl[g].round, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
                 sh.coop_cs = a.cstate[g];
                 sh.coop_done_it = a.coop_ctl[g].iters_done;
                 sh.coop_stop = sh.coop_done_it >= a.iters ||
@@ -1001,8 +988,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 mine->n_touch = cs.lopt ? nd : -1;   // -1: every product
                 for (int q = 0; q < nd; ++q) mine->dp[q] = sh.dp[q];
             }
-            // the VND results (written by every wavefront) and the summary, before the stamp
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            // the VND results (written by every wavefront) and the summary, before the stamp: each wavefront's
+            // stores completed, then one agent-scope release (it writes back the XCD's L2, whoever stored)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
             __syncthreads();
             if (go && threadIdx.x == 0)
                 __hip_atomic_store(&mine->stamp, coop_round + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1124,8 +1112,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         if (err) atomicOr(&ctl->err, err);
                     }
                 }
+                // (wavefront 0's acquires after the stamps invalidated the caches the compute unit reads
+                // through; the barrier orders every thread's reads of the results after them)
                 __syncthreads();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the slots' results, for every thread
                 const int acc = sh.coop_acc, bmode = sh.coop_bmode;
                 if (acc >= 0) {   // x takes the accepted iteration's VND results
                     const CoopSlot *sj = a.coop_slot + (int64_t)g * a.coop_m + acc;
@@ -1143,21 +1132,25 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     __syncthreads();
                     for (int q = threadIdx.x; q < K; q += blockDim.x) a.best[cp0 + q] = a.cur[cp0 + q];
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // x, before the round count
+                // every wavefront's stores to x completed, then one agent-scope release with the round count
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __syncthreads();
                 if (threadIdx.x == 0) {
                     a.cstate[g] = cs;
                     if (sh.coop_abort) ctl->abort = 1;
                     __hip_atomic_fetch_add(&ctl->round, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    coop_known = coop_round + 1;
                 }
             } else if (threadIdx.x == 0) {
-                if (!coop_wait_ge(&ctl->round, coop_round + 1, a.coop_wait_ticks)) {
+                // (the wait's acquire invalidates the caches the whole compute unit reads through; the barrier
+                // then orders the workgroup's later reads of x after it)
+                if (!coop_wait_ge(&ctl->round, coop_round + 1, a.coop_wait_ticks, &coop_known)) {
                     __hip_atomic_store(&ctl->abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     atomicOr(&ctl->err, 2);
+                    coop_known = -1;
                 }
             }
             __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the leader's writes, for every thread
             continue;
         }
 

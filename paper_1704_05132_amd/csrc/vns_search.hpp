@@ -16,6 +16,24 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Bounded wait until *p >= v, false if the wait ran out (after `ticks` of the steady clock, or
+// kCoopSpinLimit polls).  The polls are relaxed (an acquire per poll would invalidate the caches the other
+// workgroups of the XCD are working from); one acquire follows success.  *seen: the value observed.
+__device__ __forceinline__ bool coop_wait_ge(int32_t *p, int32_t v, int64_t ticks, int32_t *seen = nullptr) {
+    const int64_t t0 = wall_clock64();
+    for (uint32_t n = 0; n < kCoopSpinLimit; ++n) {
+        const int32_t now = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (now >= v) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (seen) *seen = now;
+            return true;
+        }
+        if (wall_clock64() - t0 > ticks) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
+
 // Bit t of v set iff swapping bits t and t+1 of z is a move (t < T-1 and the bits differ).
 __device__ __forceinline__ void swap_valid(const uint32_t (&z)[kWords], int T, uint32_t (&v)[kWords]) {
 #pragma unroll
