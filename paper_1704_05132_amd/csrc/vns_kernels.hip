@@ -544,6 +544,19 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             slot = blockIdx.x % m;
         }
     }
+    if constexpr (COOP) {
+        // Issue priority by slot: a round always needs slot 0 and needs slot j only if iterations 0..j-1 are
+        // all rejected, so on a shared SIMD the earlier slots go first and the later ones take what is left.
+        // (The best-of-G form needs every slot; its streams are alike.)
+        if (!a.best_of) {
+            if (slot == 0)
+                __builtin_amdgcn_s_setprio(3);
+            else if (slot < 4)
+                __builtin_amdgcn_s_setprio(2);
+            else if (slot < 8)
+                __builtin_amdgcn_s_setprio(1);
+        }
+    }
     const ChainInfo ci = a.chains[g];
     const int K = ci.K, T = ci.T;
     const int64_t cp0 = ci.cp0;
