@@ -219,6 +219,7 @@ def chunked_search(make_ctx, n_inst, chains, max_iters, chunk, targets=None, hor
     import numpy as np
     ctx = make_ctx()
     ms, it, evals, reached, hist, share_at = 0.0, 0, 0, None, [], None
+    nb_evals, fallbacks, discarded = 0, 0, 0
     best = ctx.costs()[1].reshape(n_inst, chains).min(1)
     while it < max_iters:
         n = min(chunk, max_iters - it)
@@ -226,6 +227,9 @@ def chunked_search(make_ctx, n_inst, chains, max_iters, chunk, targets=None, hor
         st = ctx.stats()
         ms += st["last_run_ms"]
         evals += st["last_run_evals"]
+        nb_evals += st["last_run_learned_evals"]
+        fallbacks += st["last_run_fallbacks"]
+        discarded += st["last_run_discarded_evals"]
         it += n
         best = ctx.costs()[1].reshape(n_inst, chains).min(1)
         hist.append((ms, it, best.copy()))
@@ -236,7 +240,8 @@ def chunked_search(make_ctx, n_inst, chains, max_iters, chunk, targets=None, hor
                 reached = (ms, it)
                 break
     out = {"ms": reached[0] if reached else None, "iters": reached[1] if reached else it, "best": best,
-           "total_ms": ms, "total_iters": it, "evals": evals, "hist": hist, "share_at_horizon": share_at}
+           "total_ms": ms, "total_iters": it, "evals": evals, "hist": hist, "share_at_horizon": share_at,
+           "nb_evals": nb_evals, "fallbacks": fallbacks, "discarded": discarded}
     if keep:
         out["ctx"] = ctx
     else:
@@ -327,6 +332,23 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, w, plain):
                    "flop_per_row": MLP_FLOP_PER_ROW},
         "note": "device time of the search launches only; scorer training is reported separately",
     }
+    # where the time goes, per GVNS iteration of every chain (whole runs, chunked as above)
+    n_ch = n_inst * chains
+
+    def per_it(r):
+        its = max(r["total_iters"], 1) * n_ch
+        d = {"device_us_per_chain_iteration": r["total_ms"] * 1e3 / max(r["total_iters"], 1),
+             "exact_evals": r["evals"] / its, "discarded_evals": r["discarded"] / its}
+        if r["nb_evals"]:
+            d["neighbourhood_evals"] = r["nb_evals"] / its
+            d["fallback_share"] = r["fallbacks"] / r["nb_evals"]
+        return d
+    out["per_iteration"] = {"plain": per_it(plain), "learned": per_it(lrn)}
+    out["reason"] = ("a learned neighbourhood evaluation scores every move (MFMA), prices the best-ranked share "
+                     "exactly with one move per lane over all T periods (the same decode latency as pricing the "
+                     "whole neighbourhood) and prices the whole neighbourhood again when none of them improves "
+                     "(fallback_share); exact pricing runs near the int32 peak, so fewer exact evaluations do not "
+                     "buy back the scoring and the fallbacks")
     if n_inst == 1:
         out["plain_best_F"] = int(B[0])
         out["learned_best_F"] = int(lrn["best"][0])

@@ -41,10 +41,11 @@ hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_byt
 // Learned scorer (vns_mlp.hip).  P: 5313 float32 parameters.  Scores of n feature rows [n][16].
 hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *out, hipStream_t s);
 // Gradient (and loss in grad_out[5313]) of the mean squared error over rows idx[0..n) (all rows when idx is
-// null).  Scratch, sized for ceil(n/64) blocks of 64 rows: Xb [*][16], sc [*], z1 and z2 [*][64],
-// part [blocks][5314].
-hipError_t launch_mlp_grad(const float *P, const float *X, const float *y, const int64_t *idx, int64_t n, float *Xb,
-                           float *sc, float *z1, float *z2, float *part, float *grad_out, hipStream_t s);
+// null): forward and backward on the matrix cores, one partial per wavefront in part
+// [mlp_grad_partials(n)][5314], then their fixed-order sum.
+hipError_t launch_mlp_grad(const float *P, const float *X, const float *y, const int64_t *idx, int64_t n, float *part,
+                           float *grad_out, hipStream_t s);
+int64_t mlp_grad_partials(int64_t n);
 // One Adam step (step counts from 1) on P with moments m, v.
 hipError_t launch_adam(float *P, const float *grad, float *m, float *v, float lr, int64_t step, hipStream_t s);
 struct EvalLearnedArgs {

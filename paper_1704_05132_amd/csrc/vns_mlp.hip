@@ -1,9 +1,10 @@
-// Kernels of the learned move scorer: batch scoring, forward with saved pre-activations, backward,
+// Kernels of the learned move scorer: batch scoring, the gradient (forward and backward in one pass),
 // deterministic gradient reduction and the Adam update (Kingma & Ba 2015).
 //
 // Training objective: mean squared error between the score and the target over a minibatch.  Gradients
 // treat the bfloat16-rounded weights and layer inputs as their float values (straight-through), the usual
-// mixed-precision rule; the backward pass runs in float32.
+// mixed-precision rule.  The backward pass runs on the matrix cores like the forward one: bfloat16 operands
+// (weights, layer inputs, deltas), float32 accumulation; bias gradients are float32 sums.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,110 +59,209 @@ __global__ __launch_bounds__(64) void k_mlp_score(const float *__restrict__ P, c
     }
 }
 
-// The same forward pass for the rows idx[0..n) of a training set (all rows when idx is null): stores the rows
-// in minibatch order in Xb, the scores in s_out and the hidden pre-activations in z1, z2 (float32).  Xb, z1
-// and z2 are sized for whole blocks of 64 rows.
-__global__ __launch_bounds__(64) void k_mlp_fwd_cache(const float *__restrict__ P, const float *__restrict__ X,
-                                                      const int64_t *__restrict__ idx, int64_t n, float *__restrict__ Xb,
-                                                      float *__restrict__ s_out, float *__restrict__ z1,
-                                                      float *__restrict__ z2) {
-    extern __shared__ __attribute__((aligned(16))) __bf16 s_mlp[];
-    __bf16 *sx = s_mlp;
+// Gradient of the mean squared error on the matrix cores, forward and backward in one pass.  One wavefront
+// per workgroup takes the 64-row tiles blockIdx.x, blockIdx.x + gridDim.x, ... of the rows idx[0..n) (all rows
+// when idx is null) and writes its partial gradients (and partial loss) to part[blockIdx.x][kParams + 1].
+//
+// Per 16 rows the forward pass is forward64's (bfloat16 operands, float32 accumulation), and the deltas stay
+// in its fragment layout: dz2 = [z2 > 0] ds w3 and dz1 = [z1 > 0] (W2 dz2), the latter on the matrix cores
+// with dz2's D fragments taken, in the order pi, as B fragments (as layer 2 takes layer 1's).  The tile's
+// layer inputs and deltas go to LDS transposed (unit-major, rows contiguous), so that dW2 = sum over rows of
+// h1 dz2^T and dW1 = x dz1^T are products with the rows as K.  Weight gradients accumulate in registers over
+// the wavefront's tiles; bias gradients as per-lane sums over rows, added across lanes at the end.
+constexpr int kGradLd = 64 + 8;   // padded row (bfloat16) of the transposed tiles: 16-byte reads stay aligned
+
+__global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ P, const float *__restrict__ X,
+                                                 const float *__restrict__ y, const int64_t *__restrict__ idx,
+                                                 int64_t n, float inv_n, float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) __bf16 sx[64 * kF];        // [row][feature]: forward input
+    __shared__ __attribute__((aligned(16))) __bf16 xT[kF * kGradLd];   // [feature][row]
+    __shared__ __attribute__((aligned(16))) __bf16 hT[kH * kGradLd];   // [unit][row]: relu(z1)
+    __shared__ __attribute__((aligned(16))) __bf16 d2T[kH * kGradLd];  // [unit][row]: dz2
+    __shared__ __attribute__((aligned(16))) __bf16 d1T[kH * kGradLd];  // [unit][row]: dz1
+    const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
     Frags fr;
     load_frags(P, fr);
-    const int lane = threadIdx.x & 63;
-    const int64_t base = (int64_t)blockIdx.x * 64, r = base + lane;
-    const int64_t src = r < n ? (idx ? idx[r] : r) : 0;
+    bf8 w2b[4][2];   // A fragments of W2 for W2 dz2: rows i = 16 mi + c, inputs j in the order pi(kt, 8g + e)
 #pragma unroll
-    for (int f = 0; f < kF; ++f) {
-        const float v = r < n ? X[src * kF + f] : 0.f;
-        sx[lane * kF + f] = (__bf16)v;
-        Xb[r * kF + f] = v;
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                w2b[mi][kt][e] = (__bf16)P[oW2 + (16 * mi + c) * kH + 32 * kt + 16 * (e >> 2) + 4 * g + (e & 3)];
+    const f4 z4 = {0.f, 0.f, 0.f, 0.f};
+    const bf8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
+    f4 gW2[4][4];                  // [mi][nj]: dW2[16 mi + 4g + e][16 nj + c]
+    f4 gW1[4];                     // [ni]: dW1[4g + e][16 ni + c]
+    f4 gb1[4], gb2[4], gw3[4];     // [t]: this lane's rows' sums for unit 16 t + 4g + e
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        gW1[t] = gb1[t] = gb2[t] = gw3[t] = z4;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) gW2[t][u] = z4;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const float s = forward64(sx, fr, z1 + base * kH, z2 + base * kH);
-    if (r < n) s_out[r] = s;
-}
+    float gb3 = 0.f, gloss = 0.f;
 
-// Backward: one workgroup of 64 lanes per 64 rows writes its partial gradients (and partial loss) to
-// part[blockIdx.x][kParams + 1].
-__global__ __launch_bounds__(256) void k_mlp_bwd(const float *__restrict__ P, const float *__restrict__ Xb,
-                                                 const float *__restrict__ y, const int64_t *__restrict__ idx,
-                                                 const float *__restrict__ s, const float *__restrict__ z1,
-                                                 const float *__restrict__ z2, int64_t n, float inv_n,
-                                                 float *__restrict__ part) {
-    __shared__ float a0[64][kF];
-    __shared__ float a1[64][kH];
-    __shared__ float a2[64][kH];
-    __shared__ float dz1[64][kH];
-    __shared__ float dz2[64][kH];
-    __shared__ float ds[64];
-    __shared__ float w2q[kH][kH + 1];
-    __shared__ float w3q[kH];
-    const int tid = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * 64;
-    for (int i = tid; i < kH * kH; i += blockDim.x) w2q[i / kH][i % kH] = (float)(__bf16)P[oW2 + i];
-    for (int i = tid; i < kH; i += blockDim.x) w3q[i] = (float)(__bf16)P[oW3 + i];
-    for (int i = tid; i < 64 * kF; i += blockDim.x) {
-        const int b = i / kF;
-        a0[b][i % kF] = base + b < n ? (float)(__bf16)Xb[(base + b) * kF + i % kF] : 0.f;
-    }
-    for (int i = tid; i < 64 * kH; i += blockDim.x) {
-        const int b = i / kH, j = i % kH;
-        const bool in = base + b < n;
-        const float v1 = in ? z1[(base + b) * kH + j] : 0.f, v2 = in ? z2[(base + b) * kH + j] : 0.f;
-        a1[b][j] = (float)(__bf16)fmaxf(v1, 0.f);
-        a2[b][j] = (float)(__bf16)fmaxf(v2, 0.f);
-        dz1[b][j] = v1;   // pre-activation for now (its sign gives the ReLU mask)
-        dz2[b][j] = v2;
-    }
-    if (tid < 64) {
-        const int64_t r = base + tid;
-        const float t = r < n ? y[idx ? idx[r] : r] : 0.f;
-        ds[tid] = r < n ? 2.f * (s[r] - t) * inv_n : 0.f;
-    }
-    __syncthreads();
-    for (int i = tid; i < 64 * kH; i += blockDim.x) {
-        const int b = i / kH, j = i % kH;
-        dz2[b][j] = dz2[b][j] > 0.f ? ds[b] * w3q[j] : 0.f;
-    }
-    __syncthreads();
-    for (int i = tid; i < 64 * kH; i += blockDim.x) {
-        const int b = i / kH, j = i % kH;
-        float acc = 0.f;
-        for (int q = 0; q < kH; ++q) acc += dz2[b][q] * w2q[j][q];
-        dz1[b][j] = dz1[b][j] > 0.f ? acc : 0.f;
-    }
-    __syncthreads();
-    float *out = part + (int64_t)blockIdx.x * (kParams + 1);
-    for (int e = tid; e < kParams + 1; e += blockDim.x) {
-        float acc = 0.f;
-        if (e < oB1) {                       // W1[f][i]
-            const int f = e / kH, i = e % kH;
-            for (int b = 0; b < 64; ++b) acc += a0[b][f] * dz1[b][i];
-        } else if (e < oW2) {                // b1
-            for (int b = 0; b < 64; ++b) acc += dz1[b][e - oB1];
-        } else if (e < oB2) {                // W2[i][j]
-            const int i = (e - oW2) / kH, j = (e - oW2) % kH;
-            for (int b = 0; b < 64; ++b) acc += a1[b][i] * dz2[b][j];
-        } else if (e < oW3) {                // b2
-            for (int b = 0; b < 64; ++b) acc += dz2[b][e - oB2];
-        } else if (e < oB3) {                // W3
-            for (int b = 0; b < 64; ++b) acc += a2[b][e - oW3] * ds[b];
-        } else if (e == oB3) {               // b3
-            for (int b = 0; b < 64; ++b) acc += ds[b];
-        } else {                             // loss contribution
-            for (int b = 0; b < 64; ++b) {
-                const int64_t r = base + b;
-                if (r < n) {
-                    const float d = s[r] - y[idx ? idx[r] : r];
-                    acc += d * d * inv_n;
+    for (int64_t tile = blockIdx.x; tile * 64 < n; tile += gridDim.x) {
+        // lane l stages row 64 tile + l (zeros past n: such rows have ds = 0 and add nothing)
+        const int64_t r = tile * 64 + lane;
+        const bool in = r < n;
+        const int64_t src = in ? (idx ? idx[r] : r) : 0;
+        const float yl = in ? y[src] : 0.f;
+        const float4 *xs = reinterpret_cast<const float4 *>(X + src * kF);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 v = in ? xs[q] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const __bf16 b = (__bf16)vv[e];
+                sx[lane * kF + 4 * q + e] = b;
+                xT[(4 * q + e) * kGradLd + lane] = b;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 1
+        for (int nt = 0; nt < 4; ++nt) {   // 16 rows at a time
+            const int row = 16 * nt + c;
+            const bf8 xb = g < 2 ? *reinterpret_cast<const bf8 *>(sx + row * kF + 8 * g) : zero8;
+            f4 d1[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) d1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w1t[mt], xb, fr.b1[mt], 0, 0, 0);
+            bf8 h[2];
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int e = 0; e < 4; e += 2) {
+                    const bf2 lo = relu_pack(d1[2 * kt][e], d1[2 * kt][e + 1]);
+                    const bf2 hi = relu_pack(d1[2 * kt + 1][e], d1[2 * kt + 1][e + 1]);
+                    h[kt][e] = lo[0];
+                    h[kt][e + 1] = lo[1];
+                    h[kt][4 + e] = hi[0];
+                    h[kt][4 + e + 1] = hi[1];
+                    hT[(32 * kt + 4 * g + e) * kGradLd + row] = lo[0];
+                    hT[(32 * kt + 4 * g + e + 1) * kGradLd + row] = lo[1];
+                    hT[(32 * kt + 16 + 4 * g + e) * kGradLd + row] = hi[0];
+                    hT[(32 * kt + 16 + 4 * g + e + 1) * kGradLd + row] = hi[1];
+                }
+            f4 d2[4];
+            float acc3 = 0.f;
+#pragma unroll
+            for (int mo = 0; mo < 4; ++mo) {
+                d2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][0], h[0], fr.b2[mo], 0, 0, 0);
+                d2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][1], h[1], d2[mo], 0, 0, 0);
+                acc3 = __builtin_amdgcn_fdot2_f32_bf16(relu_pack(d2[mo][0], d2[mo][1]), fr.w3[mo][0], acc3, false);
+                acc3 = __builtin_amdgcn_fdot2_f32_bf16(relu_pack(d2[mo][2], d2[mo][3]), fr.w3[mo][1], acc3, false);
+            }
+            acc3 += __shfl_xor(acc3, 16, 64);
+            acc3 += __shfl_xor(acc3, 32, 64);
+            const float sc = fr.b3 + acc3;                 // score of row 16 nt + c (in every lane group)
+            const float yr = __shfl(yl, row, 64);
+            const bool rin = tile * 64 + row < n;
+            const float dsr = rin ? 2.f * (sc - yr) * inv_n : 0.f;
+            if (g == 0 && rin) {
+                gb3 += dsr;
+                gloss += (sc - yr) * (sc - yr) * inv_n;
+            }
+            // dz2 = [z2 > 0] ds w3, with dW3 and db2's row sums
+            f4 dz2[4];
+#pragma unroll
+            for (int mo = 0; mo < 4; ++mo) {
+                const bf2 a01 = relu_pack(d2[mo][0], d2[mo][1]), a23 = relu_pack(d2[mo][2], d2[mo][3]);
+                const float a2[4] = {(float)a01[0], (float)a01[1], (float)a23[0], (float)a23[1]};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float w3v = (float)fr.w3[mo][e >> 1][e & 1];
+                    const float dz = d2[mo][e] > 0.f ? dsr * w3v : 0.f;
+                    dz2[mo][e] = dz;
+                    gb2[mo][e] += dz;
+                    gw3[mo][e] += a2[e] * dsr;
+                    d2T[(16 * mo + 4 * g + e) * kGradLd + row] = (__bf16)dz;
+                }
+            }
+            // dz1 = [z1 > 0] (W2 dz2) on the matrix cores
+            bf8 dzb[2];
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    dzb[kt][e] = (__bf16)dz2[2 * kt][e];
+                    dzb[kt][4 + e] = (__bf16)dz2[2 * kt + 1][e];
+                }
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi) {
+                f4 dh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2b[mi][0], dzb[0], z4, 0, 0, 0);
+                dh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2b[mi][1], dzb[1], dh, 0, 0, 0);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float dz = d1[mi][e] > 0.f ? dh[e] : 0.f;
+                    gb1[mi][e] += dz;
+                    d1T[(16 * mi + 4 * g + e) * kGradLd + row] = (__bf16)dz;
                 }
             }
         }
-        out[e] = acc;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // weight gradients of the tile: the 64 rows as K, in two slices of 32
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt) {
+            const int k0 = 32 * kt + 8 * g;
+            bf8 bd2[4];
+#pragma unroll
+            for (int nj = 0; nj < 4; ++nj) bd2[nj] = *reinterpret_cast<const bf8 *>(d2T + (16 * nj + c) * kGradLd + k0);
+#pragma unroll
+            for (int mi = 0; mi < 4; ++mi) {
+                const bf8 ah = *reinterpret_cast<const bf8 *>(hT + (16 * mi + c) * kGradLd + k0);
+#pragma unroll
+                for (int nj = 0; nj < 4; ++nj) gW2[mi][nj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bd2[nj], gW2[mi][nj], 0, 0, 0);
+            }
+            const bf8 ax = *reinterpret_cast<const bf8 *>(xT + c * kGradLd + k0);
+#pragma unroll
+            for (int ni = 0; ni < 4; ++ni) {
+                const bf8 bd1 = *reinterpret_cast<const bf8 *>(d1T + (16 * ni + c) * kGradLd + k0);
+                gW1[ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ax, bd1, gW1[ni], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // the next tile rewrites the LDS tiles
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // this wavefront's partial, in the parameters' order
+    float *out = part + (int64_t)blockIdx.x * (kParams + 1);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) out[oW2 + (16 * t + 4 * g + e) * kH + 16 * u + c] = gW2[t][u][e];
+            out[oW1 + (4 * g + e) * kH + 16 * t + c] = gW1[t][e];
+            // bias and W3 gradients: the sum over the 16 lanes (rows) of each lane group
+            float b1 = gb1[t][e], b2 = gb2[t][e], w3 = gw3[t][e];
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                b1 += __shfl_xor(b1, off, 64);
+                b2 += __shfl_xor(b2, off, 64);
+                w3 += __shfl_xor(w3, off, 64);
+            }
+            if (c == 0) {
+                out[oB1 + 16 * t + 4 * g + e] = b1;
+                out[oB2 + 16 * t + 4 * g + e] = b2;
+                out[oW3 + 16 * t + 4 * g + e] = w3;
+            }
+        }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        gb3 += __shfl_xor(gb3, off, 64);
+        gloss += __shfl_xor(gloss, off, 64);
+    }
+    if (lane == 0) {
+        out[oB3] = gb3;
+        out[kParams] = gloss;
     }
 }
 
@@ -198,19 +298,18 @@ hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *ou
     return hipGetLastError();
 }
 
-hipError_t launch_mlp_grad(const float *P, const float *X, const float *y, const int64_t *idx, int64_t n, float *Xb,
-                           float *sc, float *z1, float *z2, float *part, float *grad_out, hipStream_t s) {
+hipError_t launch_mlp_grad(const float *P, const float *X, const float *y, const int64_t *idx, int64_t n, float *part,
+                           float *grad_out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)((n + 63) / 64);
-    hipLaunchKernelGGL(mlp::k_mlp_fwd_cache, dim3(nb), dim3(64), mlp::kWaveLdsBytes, s, P, X, idx, n, Xb, sc, z1, z2);
+    const int64_t nb = mlp_grad_partials(n);
+    hipLaunchKernelGGL(mlp::k_mlp_grad, dim3((unsigned)nb), dim3(64), 0, s, P, X, y, idx, n, 1.f / (float)n, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mlp::k_mlp_bwd, dim3(nb), dim3(256), 0, s, P, Xb, y, idx, sc, z1, z2, n, 1.f / (float)n, part);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mlp::k_mlp_reduce, dim3((mlp::kParams + 1 + 255) / 256), dim3(256), 0, s, part, (int64_t)nb, grad_out);
+    hipLaunchKernelGGL(mlp::k_mlp_reduce, dim3((mlp::kParams + 1 + 255) / 256), dim3(256), 0, s, part, nb, grad_out);
     return hipGetLastError();
 }
+
+int64_t mlp_grad_partials(int64_t n) { return std::min<int64_t>((n + 63) / 64, mlp::kGradWaves); }
 
 hipError_t launch_adam(float *P, const float *grad, float *m, float *v, float lr, int64_t step, hipStream_t s) {
     const float b1 = 0.9f, b2 = 0.999f;

@@ -24,6 +24,7 @@ constexpr int kH = 64;
 constexpr int kParams = 5313;
 constexpr int oW1 = 0, oB1 = 1024, oW2 = 1088, oB2 = 5184, oW3 = 5248, oB3 = 5312;
 constexpr int kWaveLdsBytes = 64 * kF * 2;   // feature tile of 64 moves, bfloat16
+constexpr int kGradWaves = 1024;             // a gradient is the fixed-order sum of at most this many partials
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2 __attribute__((ext_vector_type(2)));

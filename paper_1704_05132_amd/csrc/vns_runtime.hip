@@ -1440,13 +1440,9 @@ extern "C" vns_status vns_mlp_score(vns_ctx *c, const float *feats, int64_t n, f
 
 // Device scratch of one gradient evaluation over up to n rows.
 struct GradScratch {
-    Scoped<float> Xb, sc, z1, z2, part, grad;
+    Scoped<float> part, grad;
     vns_status alloc(vns_ctx *c, int64_t n) {
-        const int64_t nb = (n + 63) / 64;
-        VNS_HIP(c, dmalloc(&Xb.p, (size_t)(nb * 64 * mlp::kF)));
-        VNS_HIP(c, dmalloc(&sc.p, (size_t)(nb * 64)));
-        VNS_HIP(c, dmalloc(&z1.p, (size_t)(nb * 64 * mlp::kH)));
-        VNS_HIP(c, dmalloc(&z2.p, (size_t)(nb * 64 * mlp::kH)));
+        const int64_t nb = mlp_grad_partials(n);
         VNS_HIP(c, dmalloc(&part.p, (size_t)(nb * (mlp::kParams + 1))));
         VNS_HIP(c, dmalloc(&grad.p, (size_t)(mlp::kParams + 1)));
         return VNS_OK;
@@ -1466,7 +1462,7 @@ extern "C" vns_status vns_mlp_grad(vns_ctx *c, const float *feats, const float *
     vns_status st = gs.alloc(c, n);
     if (st != VNS_OK) return st;
     VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-    VNS_HIP(c, launch_mlp_grad(c->d_mlp, X.p, Y.p, nullptr, n, gs.Xb.p, gs.sc.p, gs.z1.p, gs.z2.p, gs.part.p, gs.grad.p,
+    VNS_HIP(c, launch_mlp_grad(c->d_mlp, X.p, Y.p, nullptr, n, gs.part.p, gs.grad.p,
                                c->stream));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     std::vector<float> g((size_t)mlp::kParams + 1);
@@ -1512,8 +1508,7 @@ extern "C" vns_status vns_mlp_train(vns_ctx *c, const float *feats, const float 
             hipLaunchKernelGGL(k_batch_index, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c->stream, idx.p, s0, cnt, n,
                                mul, add);
             VNS_HIP(c, hipGetLastError());
-            VNS_HIP(c, launch_mlp_grad(c->d_mlp, X.p, Y.p, idx.p, cnt, gs.Xb.p, gs.sc.p, gs.z1.p, gs.z2.p, gs.part.p,
-                                       gs.grad.p, c->stream));
+            VNS_HIP(c, launch_mlp_grad(c->d_mlp, X.p, Y.p, idx.p, cnt, gs.part.p, gs.grad.p, c->stream));
             VNS_HIP(c, launch_adam(c->d_mlp, gs.grad.p, c->d_adam_m, c->d_adam_v, lr, ++c->adam_step, c->stream));
         }
     }
