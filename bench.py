@@ -58,6 +58,7 @@ VALU_PEAK_OPS = CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ * OPS_PER_PERIOD_ST
 TUNE_FILE = os.path.join(ROOT, "paper_1704_05132_amd", "tune_table.json")
 BEST_OF_G = 4                # best-of-G search (Algorithm 2) measured beside the plain one: shakes per iteration
 LEARNED_SPEC_M = 8           # speculative iterations of the learned search (4 wavefronts per workgroup)
+PACKED_P, PACKED_WAVES = 4, 1   # the packed learned search's batch and workgroup (its fastest measured shape)
 # learned scorer: 2 x (16*64 + 64*64 + 64) flops per scored move; dense bfloat16 matrix-core peak of MI355X
 MLP_FLOP_PER_ROW = 2 * (16 * 64 + 64 * 64 + 64)
 BF16_PEAK_TFLOPS = 2500.0
@@ -108,6 +109,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=8.0, help="target time of each oracle sample")
     ap.add_argument("--chunk", type=int, default=50, help="iterations per launch in the time-to-best runs")
     ap.add_argument("--learned-permille", type=int, default=100, help="share of moves priced exactly (1/1000)")
+    ap.add_argument("--learned-pack", type=int, default=0,
+                    help="learned VND: products per wavefront batch (packed form; 0 = one product at a time)")
+    ap.add_argument("--no-packed-leg", dest="packed_leg", action="store_false",
+                    help="skip the packed learned search on the batched set")
+    ap.add_argument("--learned-waves", type=int, default=0,
+                    help="learned search: wavefronts per workgroup (0 = the tuned plain search's)")
     ap.add_argument("--learned-log-iters", type=int, default=200)
     ap.add_argument("--learned-epochs", type=int, default=8)
     ap.add_argument("--quality-ms", type=float, default=1000.0,
@@ -298,25 +305,42 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, w, plain):
     collect_s = time.perf_counter() - t0 - train_s
 
     def make_learned():
-        c = make({vns.OPT_LEARNED: args.learned_permille})
+        c = make({vns.OPT_LEARNED: args.learned_permille, vns.OPT_LEARNED_PACK: args.learned_pack})
         if c.get_option(vns.OPT_SPEC_ITERS) > 1:
             # the learned kernel keeps the scorer's weights in registers (about 250 VGPRs, two wavefronts per
             # SIMD), so its speculative launch takes two 4-wavefront workgroups per compute unit
             c.set_option(vns.OPT_RUN_WAVES, 4)
             c.set_option(vns.OPT_SPEC_ITERS, LEARNED_SPEC_M)
+        if args.learned_waves:
+            c.set_option(vns.OPT_RUN_WAVES, args.learned_waves)
         c.mlp_set(params)
         return c
 
     lrn = chunked_search(make_learned, n_inst, chains, 2 * iters, chunk, targets=B, horizon_ms=plain["total_ms"])
     if lrn["share_at_horizon"] is None:   # reached (or stopped) before the plain run's total time
         lrn["share_at_horizon"] = float(np.mean(lrn["best"] <= B))
+    packed = None
+    if args.packed_leg and n_inst > 1 and not args.learned_pack:
+        # the packed form of the same learned search (VNS_OPT_LEARNED_PACK): same moves, its own time
+        def make_packed():
+            c = make({vns.OPT_LEARNED: args.learned_permille, vns.OPT_LEARNED_PACK: PACKED_P,
+                      vns.OPT_RUN_WAVES: PACKED_WAVES})
+            c.mlp_set(params)
+            return c
+        pk = chunked_search(make_packed, n_inst, chains, 2 * iters, chunk, targets=B)
+        packed = {"products_per_wavefront": PACKED_P, "waves": PACKED_WAVES, "ms_to_plain_best": pk["ms"],
+                  "iters": pk["iters"], "speedup": (plain_ms / pk["ms"]) if pk["ms"] else None,
+                  "device_us_per_chain_iteration": pk["total_ms"] * 1e3 / max(pk["total_iters"], 1),
+                  "reason": "each wavefront scores its batch's products one after another while the workgroup's "
+                            "other wavefronts idle, and the batch region's LDS lowers occupancy: fewer wavefronts "
+                            "per SIMD issue work, which outweighs the shared selection and fallback passes"}
     out = {
         "instances": n_inst, "chains": chains, "iters": iters, "chunk_iters": chunk,
         "plain_ms_to_best": plain_ms, "plain_iters_to_best": plain_it, "plain_total_ms": plain["total_ms"],
         "learned_ms_to_plain_best": lrn["ms"], "learned_iters": lrn["iters"], "learned_reached": lrn["ms"] is not None,
         "learned_share_at_plain_total_ms": lrn["share_at_horizon"],
         "speedup": (plain_ms / lrn["ms"]) if lrn["ms"] else None,
-        "permille_priced": args.learned_permille,
+        "permille_priced": args.learned_permille, "learned_pack": args.learned_pack,
         "training": {"instances": len(train), "logged_moves": int(len(y)),
                      "improving_share": float(np.mean(y < 0)) if len(y) else 0.0,
                      "log_search_ms": log_ms, "collect_s": collect_s, "epochs": args.learned_epochs,
@@ -344,6 +368,8 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, w, plain):
             d["fallback_share"] = r["fallbacks"] / r["nb_evals"]
         return d
     out["per_iteration"] = {"plain": per_it(plain), "learned": per_it(lrn)}
+    if packed is not None:
+        out["packed"] = packed
     out["reason"] = ("a learned neighbourhood evaluation scores every move (MFMA), prices the best-ranked share "
                      "exactly with one move per lane over all T periods (the same decode latency as pricing the "
                      "whole neighbourhood) and prices the whole neighbourhood again when none of them improves "
@@ -474,7 +500,8 @@ def paper_quality(args, vns, stream):
         params = tr.mlp_get()
 
     def make_learned():
-        c = ctx_of(8, {vns.OPT_LEARNED: args.learned_permille, vns.OPT_RUN_WAVES: 2})
+        c = ctx_of(8, {vns.OPT_LEARNED: args.learned_permille, vns.OPT_RUN_WAVES: args.learned_waves or 2,
+                       vns.OPT_LEARNED_PACK: args.learned_pack})
         c.mlp_set(params)
         return c
 

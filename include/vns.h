@@ -129,7 +129,7 @@ enum vns_option {
                               (the rest of the cost then differs by known amounts) or it turns
                               infeasible.  Same prices, argmins and counted evaluations;
                               vns_stats.last_eval_decoded_steps reports the period-steps decoded      */
-    VNS_OPT_DECODE = 19    /* decode reading, a bit set (default 0); the paper leaves both points open
+    VNS_OPT_DECODE = 19,   /* decode reading, a bit set (default 0); the paper leaves both points open
                               (Section 2 names returns and recoverable stock without the rules):
                               bit 1 (strict): a period whose latest setup is remanufacturing only must be
                               covered by the returns there; a shortfall makes the pattern infeasible
@@ -139,6 +139,12 @@ enum vns_option {
                               period yR(t) - min over s >= t of yR(s).  Setting it restarts every chain
                               from the initial solution.  The learned search, the speculative VND,
                               incremental pricing and vns_eval_learned take only 0 (VNS_EINVAL)       */
+    VNS_OPT_LEARNED_PACK = 20 /* learned VND only: P in 2..8 = a wavefront runs the VNDs of up to P products
+                              in lockstep (packed form), pricing their selections together in one pass
+                              and their fallbacks together in another; 0 or 1 (default 0) = one product
+                              at a time.  Moves, prices, records and counted evaluations are the same.
+                              Each wavefront then needs 2 KB + 2.1 KB per product of LDS, so fewer
+                              wavefronts per workgroup fit (vns_run returns VNS_EINVAL otherwise)      */
 };
 
 /* One GVNS iteration of one chain. */

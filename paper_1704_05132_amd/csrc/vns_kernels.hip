@@ -528,8 +528,9 @@ struct SpecShared {
     int32_t next;         // next product index to hand out
 };
 
-template <bool SPEC, bool LEARNED, bool COOP = false, int MODEL = 0>
+template <bool SPEC, bool LEARNED, bool COOP = false, int MODEL = 0, bool PACK = false>
 __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecShared &sp, int2 *s_rows) {
+    static_assert(!PACK || LEARNED, "the packed form is the learned VND's");
     static_assert(!(SPEC && LEARNED), "the speculative VND prices whole neighbourhoods");
     static_assert(!(COOP && SPEC), "speculative iterations run the sequential VND");
     int g = blockIdx.x, slot = 0;   // chain, and (speculative iterations) the iteration of a round it computes
@@ -607,7 +608,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     // learned search: this wavefront's tiles after the rows region (kept 16-byte aligned), and the scorer's
     // weight fragments
     const int rows_entries = run_rows_entries(a.lds_rows, W);
-    char *lbase = reinterpret_cast<char *>(s_rows + rows_entries) + wave * kLearnedWaveBytes;
+    char *lbase = reinterpret_cast<char *>(s_rows + rows_entries) +
+                  wave * (PACK ? pack_wave_bytes(a.learned_pack) : kLearnedWaveBytes);
     LearnedLds L{reinterpret_cast<__bf16 *>(lbase), reinterpret_cast<uint16_t *>(lbase + 64 * 16 * 2)};
     mlp::Frags fr;
     if constexpr (LEARNED) mlp::load_frags(a.mlp, fr);
@@ -724,7 +726,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             }
             if (lane == 0) {
                 sh.nd = nd;
-                sh.next_prod = W;   // wavefront w starts with product index w
+                // wavefront w starts with product index w (the packed learned VND: with batch w)
+                sh.next_prod = PACK ? W * a.learned_pack : W;
             }
         }
         __syncthreads();
@@ -860,6 +863,65 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             // products than wavefronts would otherwise put two on one wavefront however short the others
             // are); the products of a split round are shared out over the chain's workgroups in fixed order.
             const bool dyn = vstep == W;
+            if constexpr (PACK) {
+                // the packed learned VND: batches of up to P products, handed to wavefronts as they finish
+                const int P = a.learned_pack;
+                const PackLds PL = pack_lds(lbase, P);
+                auto round_now = [&]() -> int32_t {
+                    if constexpr (COOP) {
+                        if (may_abandon)
+                            return __hip_atomic_load(&a.coop_ctl[g].round, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    return coop_round;
+                };
+                for (int base = vfirst * P; base < nprod && !stale;) {
+                    const int cnt = min(P, nprod - base);
+                    if (lane == 0) {
+                        for (int i = 0; i < cnt; ++i) {
+                            const int idx = base + i;
+                            int p, e = -1;
+                            if (cs.lopt) {
+                                p = sh.dp[idx];
+                                e = idx;
+                            } else {
+                                p = idx;
+                                for (int q = 0; q < nd; ++q) e = (e < 0 && sh.dp[q] == p) ? q : e;
+                            }
+                            PackProd &pr = PL.pk[i];
+                            pr.p = p;
+                            pr.b = e >= 0 ? sh.db[e] : s_cur[p];
+                            pr.c_cur = s_cur_cost[p];
+                            pr.cost = e >= 0 ? kInf : pr.c_cur;   // a shaken product is priced with its first list
+                            pr.need_ident = e >= 0 ? 1 : 0;
+                        }
+                    }
+                    wave_sync_lds();
+                    if (!learned_vnd_packed(PL, cnt, rows_in_lds ? s_rows : nullptr, inst_rows, a.prod + ci.prod0, T,
+                                            a.nb_list, a.n_nb, a.memo, fr, a.permille, evals, nb_evals, fallbacks,
+                                            coop_round, round_now)) {
+                        stale = true;
+                        break;
+                    }
+                    for (int i = 0; i < cnt; ++i) {
+                        const PackProd &pr = PL.pk[i];
+                        if (lane == 0) {
+                            s_work[pr.p] = pr.b;
+                            s_work_cost[pr.p] = pr.cost;
+                        }
+                        part += pr.cost - pr.c_cur;
+                        shk += pr.shk;
+                        vnd_err |= pr.err;
+                    }
+                    wave_sync_lds();
+                    if (dyn) {
+                        int v = 0;
+                        if (lane == 0) v = atomicAdd(&sh.next_prod, P);
+                        base = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
+                    } else {
+                        base += vstep * P;
+                    }
+                }
+            } else {
             for (int idx = vfirst; idx < nprod && !stale;
                  idx = dyn ? __builtin_amdgcn_readfirstlane(next_index(sh.next_prod, lane)) : idx + vstep) {
                 int p, e = -1;
@@ -962,6 +1024,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     s_work_cost[p] = cost;
                 }
                 part += cost - c_cur;
+            }
             }
         }
         }   // go
@@ -1323,6 +1386,21 @@ __global__ __launch_bounds__(512) void k_run_learned(RunArgs a) {
     run_chain<false, true>(a, sh, sp, s_rows);
 }
 
+// the packed learned VND (batches of products per wavefront), alone and with speculative iterations
+__global__ __launch_bounds__(512) void k_run_learned_packed(RunArgs a) {
+    __shared__ RunShared sh;
+    __shared__ SpecShared sp;
+    extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
+    run_chain<false, true, false, 0, true>(a, sh, sp, s_rows);
+}
+
+__global__ __launch_bounds__(512) void k_run_learned_coop_packed(RunArgs a) {
+    __shared__ RunShared sh;
+    __shared__ SpecShared sp;
+    extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
+    run_chain<false, true, true, 0, true>(a, sh, sp, s_rows);
+}
+
 // ---------------------------------------------------------------------------------------------------
 // k_eval_learned: one wavefront per (chain, product) of a chain range: the learned choice of one
 // neighbourhood's move for the current solution, with the scores and the selection of every move.
@@ -1423,6 +1501,7 @@ static const void *run_kernel(RunKind kind, int model) {
     switch (kind) {
         case RunKind::kSpec: return reinterpret_cast<const void *>(&k_run_spec);
         case RunKind::kLearned: return reinterpret_cast<const void *>(&k_run_learned);
+        case RunKind::kLearnedPacked: return reinterpret_cast<const void *>(&k_run_learned_packed);
         default: return by_model<PickRun>(model);
     }
 }
@@ -1436,13 +1515,15 @@ hipError_t run_kernel_lds(RunKind kind, size_t *static_bytes, size_t dynamic_byt
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dynamic_bytes);
 }
 
-static const void *coop_kernel(bool learned, int model) {
-    return learned ? reinterpret_cast<const void *>(&k_run_learned_coop) : by_model<PickCoop>(model);
+static const void *coop_kernel(RunKind kind, int model) {
+    if (kind == RunKind::kLearned) return reinterpret_cast<const void *>(&k_run_learned_coop);
+    if (kind == RunKind::kLearnedPacked) return reinterpret_cast<const void *>(&k_run_learned_coop_packed);
+    return by_model<PickCoop>(model);
 }
 
-hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bool learned, int model) {
+hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, RunKind kind, int model) {
     *fits = false;
-    const void *fn = coop_kernel(learned, model);
+    const void *fn = coop_kernel(kind, model);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     int per_cu = 0, dev = 0, cus = 0;
@@ -1457,11 +1538,11 @@ hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bo
 }
 
 hipError_t launch_run_coop(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
-                           hipStream_t s, bool learned, int model) {
+                           hipStream_t s, RunKind kind, int model) {
     if (n_chains <= 0 || a.iters <= 0) return hipSuccess;
     RunArgs args = a;
     void *params[] = {&args};
-    hipError_t e = hipLaunchCooperativeKernel(coop_kernel(learned, model),
+    hipError_t e = hipLaunchCooperativeKernel(coop_kernel(kind, model),
                                               dim3((unsigned)(n_chains * a.coop_m)), dim3(64 * waves), params,
                                               (unsigned)lds_bytes, s);
     if (e != hipSuccess) return e;

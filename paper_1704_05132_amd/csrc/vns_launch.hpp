@@ -33,7 +33,7 @@ struct ChainBestArgs {
 };
 
 // Variants of the search kernel: sequential VND, speculative VND, learned VND.
-enum class RunKind { kPlain = 0, kSpec = 1, kLearned = 2 };
+enum class RunKind { kPlain = 0, kSpec = 1, kLearned = 2, kLearnedPacked = 3 };
 
 // Static LDS bytes of a search kernel variant, and permission for it to request dynamic_bytes more.
 // model: the decode reading (kModelStrict | kModelDispose; the plain sequential VND only).
@@ -79,10 +79,11 @@ hipError_t launch_eval_inc(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, si
 hipError_t launch_chain_best(const ChainBestArgs &a, int n_chains, hipStream_t s);
 // Speculative iterations (a.coop_m workgroups per chain, cooperative launch): whether blocks workgroups of
 // `waves` wavefronts and lds_bytes of dynamic LDS are all resident at once, and the launch itself (then the
-// device iteration counter advances by a.iters).  learned: the learned search's kernel.
-hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, bool learned, int model);
+// device iteration counter advances by a.iters).  kind: kPlain (any decode reading `model`), kLearned or
+// kLearnedPacked.
+hipError_t coop_fits(int waves, size_t lds_bytes, int64_t blocks, bool *fits, RunKind kind, int model);
 hipError_t launch_run_coop(const RunArgs &a, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,
-                           hipStream_t s, bool learned, int model);
+                           hipStream_t s, RunKind kind, int model);
 // The search kernel variant `kind` over n_chains workgroups, then the device iteration counter advances by a.iters (two kernels on s;
 // both can be captured in a graph).
 hipError_t launch_run(const RunArgs &a, RunKind kind, int n_chains, int waves, size_t lds_bytes, int64_t *it_counter,

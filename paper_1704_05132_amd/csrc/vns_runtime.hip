@@ -98,6 +98,7 @@ struct vns_ctx {
     int64_t max_lds_per_wg = 65536;       // device limit on LDS per workgroup (queried at create)
     int64_t coop_wait_ticks = 0;          // steady-clock ticks of kCoopWaitSeconds (clock rate queried at create)
     int32_t permille = 0;                 // learned scorer: top permille priced exactly (0 = plain search)
+    int32_t learned_pack = 0;             // learned VND: products per wavefront batch (0, 1 = one at a time)
     int32_t speculate = 0;                // plain search: speculative VND (neighbourhoods priced side by side)
     int32_t state_lds = 1;                // search kernel: chains' solution state in LDS when it fits
     int32_t vnd_memo = 0;                 // VND: skip neighbourhoods priced without improvement on this pattern
@@ -587,6 +588,10 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v < 0 || v > 1000) return fail(c, VNS_EINVAL, "learned permille must be in 0..1000");
             c->permille = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_LEARNED_PACK:
+            if (v < 0 || v > kPackMax) return fail(c, VNS_EINVAL, "learned pack must be in 0..8");
+            c->learned_pack = (int32_t)v;
+            return VNS_OK;
         case VNS_OPT_LOG: {
             if (v < 0 || v > ((int64_t)1 << 31)) return fail(c, VNS_EINVAL, "move-log capacity out of range");
             free_log(c);
@@ -618,6 +623,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_RUN_LDS: *v = c->run_lds_budget; return VNS_OK;
         case VNS_OPT_GRAPH: *v = c->use_graph; return VNS_OK;
         case VNS_OPT_LEARNED: *v = c->permille; return VNS_OK;
+        case VNS_OPT_LEARNED_PACK: *v = c->learned_pack; return VNS_OK;
         case VNS_OPT_SPECULATE: *v = c->speculate; return VNS_OK;
         case VNS_OPT_SPEC_WAVES: *v = c->spec_waves; return VNS_OK;
         case VNS_OPT_STATE_LDS: *v = c->state_lds; return VNS_OK;
@@ -1018,6 +1024,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     ra.nb_list = c->nb_list;
     ra.n_nb = c->n_nb;
     ra.permille = c->permille;
+    ra.learned_pack = c->permille > 0 ? c->learned_pack : 0;
     ra.mlp = c->d_mlp;
     ra.log_x = c->log_cap > 0 ? c->d_log_x : nullptr;
     ra.log_y = c->d_log_y;
@@ -1030,14 +1037,18 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     // speculative VND for plain runs (one wavefront per neighbourhood of each product), else one wavefront
     // per product
     const bool spec = c->speculate && c->permille == 0 && c->spec_waves >= c->n_nb;
-    const RunKind kind = c->permille > 0 ? RunKind::kLearned : spec ? RunKind::kSpec : RunKind::kPlain;
+    const RunKind kind = c->permille > 0 ? (c->learned_pack > 1 ? RunKind::kLearnedPacked : RunKind::kLearned)
+                         : spec          ? RunKind::kSpec
+                                         : RunKind::kPlain;
     const int waves = spec ? c->spec_waves : c->run_waves;
     size_t static_lds = 0;
     if (c->model != 0 && kind != RunKind::kPlain)
         return fail(c, VNS_EINVAL, "the learned search and the speculative VND take only the default decode reading "
                                    "(VNS_OPT_DECODE = 0)");
     VNS_HIP(c, run_kernel_lds(kind, &static_lds, 0, c->model));
-    const int64_t learned = c->permille > 0 ? (int64_t)waves * kLearnedWaveBytes : 0;
+    const bool packed = c->permille > 0 && c->learned_pack > 1;
+    const int64_t learned =
+        c->permille > 0 ? (int64_t)waves * (packed ? pack_wave_bytes(c->learned_pack) : kLearnedWaveBytes) : 0;
     const int64_t room = c->max_lds_per_wg - (int64_t)static_lds - learned;   // dynamic LDS left for rows
     const int64_t slices = (int64_t)waves * kTMax;                   // per-wave rows when the instance does not fit
     if (room < slices * (int64_t)sizeof(int2)) return fail(c, VNS_EINVAL, "not enough LDS for the search kernel");
@@ -1064,17 +1075,17 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     bool coop = false;
     // x stays in device memory: no state region; the learned search keeps its per-wavefront tiles
     const size_t lds_coop = rows_bytes + (size_t)learned;
-    const bool coop_learned = kind == RunKind::kLearned;
+    const bool coop_learned = kind == RunKind::kLearned || kind == RunKind::kLearnedPacked;
     if (best) {
         if (kind != RunKind::kPlain || c->use_graph || ra.log_x != nullptr || c->spec_iters > 1)
             return fail(c, VNS_EINVAL, "best-of-G runs the plain search alone: no learned scorer, speculative VND or "
                                        "iterations, move log or graph capture");
-        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, false, c->model));
+        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, RunKind::kPlain, c->model));
         if (!coop)
             return fail(c, VNS_EINVAL, "best-of-G needs its G workgroups per chain resident at once: use fewer "
                                        "chains, wavefronts per workgroup or streams");
     } else if (m > 1 && kind != RunKind::kSpec && !c->use_graph && ra.log_x == nullptr) {
-        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, coop_learned, c->model));
+        VNS_HIP(c, coop_fits(waves, lds_coop, G * m, &coop, kind, c->model));
     }
     c->stats.last_run_spec_iters = coop && !best ? m : 1;
     CoopCtl *d_ctl = c->d_coop_ctl;
@@ -1133,7 +1144,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         ra.best_of = best ? 1 : 0;
         ra.best_literal = c->best_literal;
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-        VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream, coop_learned, c->model));
+        VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream, kind, c->model));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     } else if (c->use_graph) {
         const int64_t key[5] = {iters, G, waves * 4 + (int64_t)kind, (int64_t)lds, (int64_t)(intptr_t)ra.trace};

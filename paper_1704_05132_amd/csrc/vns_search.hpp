@@ -161,6 +161,55 @@ struct LearnedLds {
     uint16_t *sel;     // [2 * kTMax]
 };
 
+// Steps 1 and 2 of a learned neighbourhood evaluation by one wavefront, for a neighbourhood of nitems >= 1
+// moves (list, nflip, fm from move_list): every move is scored, and the best-ranked
+// ceil(permille * nitems / 1000) (at least one; lowest score first, ties to the lower slot) are written to
+// sel in rank order.  Returns their number.  score_out / sel_out (by slot, may be null) receive the scores and
+// the selection.
+__device__ __forceinline__ int learned_select(const Bits &b, const int2 *row, int T, const ProdParams &pp, int nitems,
+                                              int nflip, bool fm, const uint16_t *list, __bf16 *sx, uint16_t *sel,
+                                              const mlp::Frags &fr, int permille, float *score_out, uint8_t *sel_out) {
+    const int lane = threadIdx.x & 63;
+    // 1. scores of every move, kept as (sortable score << 32 | slot) keys, up to four per lane
+    uint64_t sk[4] = {kInfKey, kInfKey, kInfKey, kInfKey};
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        if (ch * 64 >= nitems) break;
+        const int idx = ch * 64 + lane;
+        const int slot = idx < nitems ? item_slot(idx, nflip, fm, T, list) : 0;
+        float f[mlp::kF];
+        if (idx < nitems) {
+            mlp::move_features(b, row, T, pp, slot, f);
+        } else {
+#pragma unroll
+            for (int i = 0; i < mlp::kF; ++i) f[i] = 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < mlp::kF; ++i) sx[lane * mlp::kF + i] = (__bf16)f[i];
+        wave_sync_lds();
+        const float s = mlp::forward64(sx, fr);
+        if (idx < nitems) {
+            sk[ch] = ((uint64_t)mlp::sortable(s) << 32) | (uint64_t)slot;
+            if (score_out) score_out[slot] = s;
+        }
+    }
+    // 2. the best-ranked moves, by repeated wavefront minima
+    int n_sel = (permille * nitems + 999) / 1000;   // nitems >= 1 here
+    n_sel = n_sel < 1 ? 1 : (n_sel > nitems ? nitems : n_sel);
+    for (int r = 0; r < n_sel; ++r) {
+        uint64_t my = sk[0];
+#pragma unroll
+        for (int ch = 1; ch < 4; ++ch) my = sk[ch] < my ? sk[ch] : my;
+        const uint64_t m = wave_min_u64(my);
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) sk[ch] = sk[ch] == m ? kInfKey : sk[ch];
+        if (lane == 0) sel[r] = (uint16_t)(m & 0xFFFFu);
+        if (sel_out && lane == 0 && m != kInfKey) sel_out[m & 0xFFFFu] = 1;
+    }
+    wave_sync_lds();
+    return n_sel;
+}
+
 // Learned best move of one neighbourhood (one wavefront).  The scorer ranks the moves (lowest score first,
 // ties to the lower slot), the best-ranked ceil(permille * n / 1000) (at least one) are priced exactly and
 // the best of them is returned if it is cheaper than `cost`; otherwise the whole neighbourhood is priced
@@ -184,43 +233,8 @@ __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 
         if (ident) cost = decode_cost(b, row, T, pp);
         return kInfKey;
     }
-    // 1. scores of every move, kept as (sortable score << 32 | slot) keys, up to four per lane
-    uint64_t sk[4] = {kInfKey, kInfKey, kInfKey, kInfKey};
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-        if (ch * 64 >= nitems) break;
-        const int idx = ch * 64 + lane;
-        const int slot = idx < nitems ? item_slot(idx, nflip, fm, T, list) : 0;
-        float f[mlp::kF];
-        if (idx < nitems) {
-            mlp::move_features(b, row, T, pp, slot, f);
-        } else {
-#pragma unroll
-            for (int i = 0; i < mlp::kF; ++i) f[i] = 0.f;
-        }
-#pragma unroll
-        for (int i = 0; i < mlp::kF; ++i) L.sx[lane * mlp::kF + i] = (__bf16)f[i];
-        wave_sync_lds();
-        const float s = mlp::forward64(L.sx, fr);
-        if (idx < nitems) {
-            sk[ch] = ((uint64_t)mlp::sortable(s) << 32) | (uint64_t)slot;
-            if (score_out) score_out[slot] = s;
-        }
-    }
-    // 2. the best-ranked moves, by repeated wavefront minima
-    int n_sel = (permille * nitems + 999) / 1000;   // nitems >= 1 here
-    n_sel = n_sel < 1 ? 1 : (n_sel > nitems ? nitems : n_sel);
-    for (int r = 0; r < n_sel; ++r) {
-        uint64_t my = sk[0];
-#pragma unroll
-        for (int ch = 1; ch < 4; ++ch) my = sk[ch] < my ? sk[ch] : my;
-        const uint64_t m = wave_min_u64(my);
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) sk[ch] = sk[ch] == m ? kInfKey : sk[ch];
-        if (lane == 0) L.sel[r] = (uint16_t)(m & 0xFFFFu);
-        if (sel_out && lane == 0 && m != kInfKey) sel_out[m & 0xFFFFu] = 1;
-    }
-    wave_sync_lds();
+    // 1-2. scores of every move and the best-ranked ones
+    const int n_sel = learned_select(b, row, T, pp, nitems, nflip, fm, list, L.sx, L.sel, fr, permille, score_out, sel_out);
     // 3. exact prices of the selection (and of the unchanged pattern)
     const int total = n_sel + (ident ? 1 : 0);
     evals += n_sel;
@@ -245,6 +259,231 @@ __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 
     // 4. fallback: the whole neighbourhood, exactly
     fallback = 1;
     return wave_best_move(b, row, T, pp, nb, list, false, nullptr, evals);
+}
+
+// ---------------------------------------------------------------------------------------------------
+// The learned VND of several products at once, by one wavefront (packed form).  The products of a batch
+// step through Algorithm 1 in lockstep: per step every product still searching takes its next
+// neighbourhood (in list order, skipping one already priced without improvement on the current pattern when
+// the memo is on); each one's moves are scored and its best-ranked ones selected (learned_select, one
+// product at a time); then the selections of all of them, with the unchanged shaken patterns still to
+// price, are priced exactly in one pass; the products whose selection holds no improving move get their
+// whole neighbourhood priced, all of them in one pass again; and each applies its move.  Per product the
+// selections, prices, fallbacks, moves and counted evaluations are those of learned_best_move in the
+// one-product VND: only the packing of lanes differs.  A selection of a few moves no longer costs a whole
+// T-period pass of its own.
+// ---------------------------------------------------------------------------------------------------
+struct PackProd {
+    Bits b;                    // the product's current pattern
+    int64_t cost;              // its exact cost (kInf until the unchanged shaken pattern is priced)
+    int64_t c_cur;             // its cost in x
+    int64_t shk;               // cost after the shake minus cost in x (shaken products)
+    int64_t idc;               // this step's price of the unchanged pattern
+    unsigned long long best;   // this step's best key (the selection's, then the fallback's)
+    int32_t p, q, passes, clean, improved, need_ident, active, err;
+    int32_t nb, nitems, nflip, fm, nsel, fb;
+};
+static_assert(sizeof(PackProd) == kPackProdBytes, "the packed region's layout");
+
+// One wavefront's LDS for the packed form: the feature tile, the batch's records, move lists, selections and
+// (when the instance's rows are not resident) staged rows.
+struct PackLds {
+    __bf16 *sx;      // [64][16]
+    PackProd *pk;    // [P]
+    uint16_t *list;  // [P][2 kTMax]
+    uint16_t *sel;   // [P][2 kTMax]
+    int2 *rows;      // [P][kTMax]
+};
+
+// The region of pack_wave_bytes(P) bytes at base, for batches of up to P products.
+__device__ __forceinline__ PackLds pack_lds(char *base, int P) {
+    PackLds L;
+    L.sx = reinterpret_cast<__bf16 *>(base);
+    base += 64 * 16 * 2;
+    L.pk = reinterpret_cast<PackProd *>(base);
+    base += P * sizeof(PackProd);
+    L.list = reinterpret_cast<uint16_t *>(base);
+    base += P * 2 * kTMax * 2;
+    L.sel = reinterpret_cast<uint16_t *>(base);
+    base += P * 2 * kTMax * 2;
+    L.rows = reinterpret_cast<int2 *>(base);
+    return L;
+}
+
+// Item idx of a step's packed list: the product i with off[i] <= idx < off[i + 1] (n products).
+__device__ __forceinline__ int pack_owner(const int (&off)[kPackMax + 1], int n, int idx) {
+    int i = 0;
+#pragma unroll
+    for (int j = 1; j < kPackMax; ++j) i += (j < n && idx >= off[j]) ? 1 : 0;
+    return i;
+}
+
+// Runs the batch L.pk[0 .. n-1] (p, b, cost, c_cur, need_ident set by the caller) to its local optima.  rows:
+// the instance's rows when resident in LDS, else null (inst_rows in device memory are staged per product).
+// prod: the instance's product parameters.  round_now() is read before each step and compared with `round`
+// after it: false means the round moved on and the batch was abandoned.
+template <class RoundNow>
+__device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, const int2 *rows, const int2 *inst_rows,
+                                                   const ProdParams *prod, int T, uint32_t nb_list, int n_nb, int memo,
+                                                   const mlp::Frags &fr, int permille, int64_t &evals,
+                                                   int64_t &nb_evals, int64_t &fallbacks, int32_t round,
+                                                   RoundNow round_now) {
+    const int lane = threadIdx.x & 63;
+    if (lane == 0) {
+        for (int i = 0; i < n; ++i) {
+            PackProd &s = L.pk[i];
+            s.q = 0;
+            s.passes = 1;
+            s.clean = 0;
+            s.improved = 0;
+            s.active = 1;
+            s.err = 0;
+            s.shk = 0;
+        }
+    }
+    if (!rows) {
+        for (int i = 0; i < n; ++i) {
+            const int p = L.pk[i].p;
+            for (int t = lane; t < T; t += 64) L.rows[i * kTMax + t] = inst_rows[p * T + t];
+        }
+    }
+    wave_sync_lds();
+    auto row_of = [&](int i, int p) -> const int2 * { return rows ? rows + p * T : L.rows + i * kTMax; };
+    for (;;) {
+        // 1. each product's next neighbourhood (lane 0 advances the states)
+        if (lane == 0) {
+            for (int i = 0; i < n; ++i) {
+                PackProd &s = L.pk[i];
+                s.nb = -1;
+                while (s.active) {
+                    while (s.q < n_nb && memo && ((s.clean >> s.q) & 1)) ++s.q;
+                    if (s.q < n_nb) {
+                        s.nb = (int32_t)((nb_list >> (4 * s.q)) & 0xFu);
+                        break;
+                    }
+                    if (s.improved && s.passes < kMaxPasses) {   // another pass
+                        ++s.passes;
+                        s.improved = 0;
+                        s.q = 0;
+                    } else {
+                        s.err |= s.improved;   // the pass guard (cannot happen with a consistent decode)
+                        s.active = 0;
+                    }
+                }
+            }
+        }
+        wave_sync_lds();
+        int stepping = 0;
+        for (int i = 0; i < n; ++i) stepping += L.pk[i].nb >= 0 ? 1 : 0;
+        if (stepping == 0) return true;
+        const int32_t r0 = round_now();
+        // 2. move lists, scores and selections, one product at a time
+        for (int i = 0; i < n; ++i) {
+            const int nb = L.pk[i].nb;
+            if (nb < 0) continue;
+            const Bits b = L.pk[i].b;
+            const int p = L.pk[i].p;
+            const ProdParams pp = prod[p];
+            uint16_t *list = L.list + i * 2 * kTMax;
+            int nflip;
+            bool fm;
+            const int nitems = move_list(b, T, (uint32_t)nb, list, nflip, fm);
+            const int nsel = nitems > 0 ? learned_select(b, row_of(i, p), T, pp, nitems, nflip, fm, list, L.sx,
+                                                         L.sel + i * 2 * kTMax, fr, permille, nullptr, nullptr)
+                                        : 0;
+            if (lane == 0) {
+                PackProd &s = L.pk[i];
+                s.nitems = nitems;
+                s.nflip = nflip;
+                s.fm = fm ? 1 : 0;
+                s.nsel = nsel;
+                s.best = kInfKey;
+                s.fb = 0;
+            }
+        }
+        wave_sync_lds();
+        // 3. every selection, and every unchanged pattern still to price, in one packed list
+        int off[kPackMax + 1];
+        off[0] = 0;
+#pragma unroll
+        for (int i = 0; i < kPackMax; ++i)
+            off[i + 1] = off[i] + ((i < n && L.pk[i].nb >= 0) ? L.pk[i].nsel + L.pk[i].need_ident : 0);
+        const int total = off[kPackMax];
+        for (int basei = 0; basei < total; basei += 64) {
+            const int idx = basei + lane;
+            if (idx < total) {
+                const int i = pack_owner(off, n, idx), k = idx - off[i];
+                const int p = L.pk[i].p;
+                const int slot = k < L.pk[i].nsel ? (int)L.sel[i * 2 * kTMax + k] : -1;
+                Bits mb = L.pk[i].b;
+                if (slot >= 0) apply_move(mb, slot, T);
+                const int64_t c = decode_cost(mb, row_of(i, p), T, prod[p]);
+                if (slot < 0)
+                    L.pk[i].idc = c;
+                else if (c != kInf)
+                    atomicMin(&L.pk[i].best, ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
+            }
+        }
+        for (int i = 0; i < n; ++i) evals += L.pk[i].nb >= 0 ? L.pk[i].nsel : 0;
+        wave_sync_lds();
+        // 4. the unchanged patterns' prices, and which selections hold no improving move
+        if (lane == 0) {
+            for (int i = 0; i < n; ++i) {
+                PackProd &s = L.pk[i];
+                if (s.nb < 0) continue;
+                if (s.need_ident) {
+                    s.cost = s.idc;
+                    s.shk = s.idc - s.c_cur;
+                    s.need_ident = 0;
+                }
+                const bool better = s.best != kInfKey && (int64_t)(s.best >> kSlotBits) < s.cost;
+                s.fb = (s.nitems > 0 && !better) ? 1 : 0;
+                if (s.fb) s.best = kInfKey;
+            }
+        }
+        wave_sync_lds();
+        // 5. fallback: the whole neighbourhoods of those products, in one packed list
+#pragma unroll
+        for (int i = 0; i < kPackMax; ++i) off[i + 1] = off[i] + ((i < n && L.pk[i].nb >= 0 && L.pk[i].fb) ? L.pk[i].nitems : 0);
+        const int ftotal = off[kPackMax];
+        for (int basei = 0; basei < ftotal; basei += 64) {
+            const int idx = basei + lane;
+            if (idx < ftotal) {
+                const int i = pack_owner(off, n, idx), k = idx - off[i];
+                const int p = L.pk[i].p;
+                const int slot = item_slot(k, L.pk[i].nflip, L.pk[i].fm != 0, T, L.list + i * 2 * kTMax);
+                Bits mb = L.pk[i].b;
+                apply_move(mb, slot, T);
+                const int64_t c = decode_cost(mb, row_of(i, p), T, prod[p]);
+                if (c != kInf) atomicMin(&L.pk[i].best, ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
+            }
+        }
+        for (int i = 0; i < n; ++i) {
+            if (L.pk[i].nb < 0) continue;
+            evals += L.pk[i].fb ? L.pk[i].nitems : 0;
+            nb_evals += 1;
+            fallbacks += L.pk[i].fb;
+        }
+        wave_sync_lds();
+        // 6. each product's move, when it improves
+        if (lane == 0) {
+            for (int i = 0; i < n; ++i) {
+                PackProd &s = L.pk[i];
+                if (s.nb < 0) continue;
+                const unsigned long long key = s.best;
+                const bool applied = key != kInfKey && (int64_t)(key >> kSlotBits) < s.cost;
+                if (applied) {
+                    apply_move(s.b, (int)(key & ((1u << kSlotBits) - 1)), T);
+                    s.cost = (int64_t)(key >> kSlotBits);
+                    s.improved = 1;
+                }
+                s.clean = applied ? 0 : (s.clean | (1 << s.q));
+                ++s.q;
+            }
+        }
+        wave_sync_lds();
+        if (__builtin_amdgcn_readfirstlane(r0) != round) return false;
+    }
 }
 
 // Appends the records of an applied move and of a contrast move of the same neighbourhood to the move log:
