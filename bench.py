@@ -58,7 +58,7 @@ VALU_PEAK_OPS = CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_HZ * OPS_PER_PERIOD_ST
 TUNE_FILE = os.path.join(ROOT, "paper_1704_05132_amd", "tune_table.json")
 BEST_OF_G = 4                # best-of-G search (Algorithm 2) measured beside the plain one: shakes per iteration
 LEARNED_SPEC_M = 8           # speculative iterations of the learned search (4 wavefronts per workgroup)
-PACKED_P, PACKED_WAVES = 4, 1   # the packed learned search's batch and workgroup (its fastest measured shape)
+PACKED_P, PACKED_WAVES = 8, 2   # the packed learned search's batch and workgroup (its fastest measured shape)
 # learned scorer: 2 x (16*64 + 64*64 + 64) flops per scored move; dense bfloat16 matrix-core peak of MI355X
 MLP_FLOP_PER_ROW = 2 * (16 * 64 + 64 * 64 + 64)
 BF16_PEAK_TFLOPS = 2500.0
@@ -331,9 +331,9 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, w, plain):
         packed = {"products_per_wavefront": PACKED_P, "waves": PACKED_WAVES, "ms_to_plain_best": pk["ms"],
                   "iters": pk["iters"], "speedup": (plain_ms / pk["ms"]) if pk["ms"] else None,
                   "device_us_per_chain_iteration": pk["total_ms"] * 1e3 / max(pk["total_iters"], 1),
-                  "reason": "each wavefront scores its batch's products one after another while the workgroup's "
-                            "other wavefronts idle, and the batch region's LDS lowers occupancy: fewer wavefronts "
-                            "per SIMD issue work, which outweighs the shared selection and fallback passes"}
+                  "reason": "the shared selection and fallback passes save about a quarter of the wavefront "
+                            "passes, and the lockstep's workgroup barriers and per-product serial steps (state, "
+                            "move lists, scoring) cost about as much"}
     out = {
         "instances": n_inst, "chains": chains, "iters": iters, "chunk_iters": chunk,
         "plain_ms_to_best": plain_ms, "plain_iters_to_best": plain_it, "plain_total_ms": plain["total_ms"],

@@ -139,12 +139,12 @@ enum vns_option {
                               period yR(t) - min over s >= t of yR(s).  Setting it restarts every chain
                               from the initial solution.  The learned search, the speculative VND,
                               incremental pricing and vns_eval_learned take only 0 (VNS_EINVAL)       */
-    VNS_OPT_LEARNED_PACK = 20 /* learned VND only: P in 2..8 = a wavefront runs the VNDs of up to P products
-                              in lockstep (packed form), pricing their selections together in one pass
-                              and their fallbacks together in another; 0 or 1 (default 0) = one product
-                              at a time.  Moves, prices, records and counted evaluations are the same.
-                              Each wavefront then needs 2 KB + 2.1 KB per product of LDS, so fewer
-                              wavefronts per workgroup fit (vns_run returns VNS_EINVAL otherwise)      */
+    VNS_OPT_LEARNED_PACK = 20 /* learned VND only: P in 2..8 = a workgroup's wavefronts run the VNDs of up to
+                              P products in lockstep together (packed form), pricing their selections
+                              in shared passes and their fallbacks in shared passes; 0 or 1 (default 0)
+                              = one product per wavefront at a time.  Moves, prices, records and counted
+                              evaluations are the same.  The workgroup then needs 2 KB of LDS per
+                              wavefront and 2.1 KB per product                                       */
 };
 
 /* One GVNS iteration of one chain. */

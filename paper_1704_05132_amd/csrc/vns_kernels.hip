@@ -608,8 +608,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
     // learned search: this wavefront's tiles after the rows region (kept 16-byte aligned), and the scorer's
     // weight fragments
     const int rows_entries = run_rows_entries(a.lds_rows, W);
-    char *lbase = reinterpret_cast<char *>(s_rows + rows_entries) +
-                  wave * (PACK ? pack_wave_bytes(a.learned_pack) : kLearnedWaveBytes);
+    // (the packed form: one region for the workgroup)
+    char *lbase = reinterpret_cast<char *>(s_rows + rows_entries) + (PACK ? 0 : wave * kLearnedWaveBytes);
     LearnedLds L{reinterpret_cast<__bf16 *>(lbase), reinterpret_cast<uint16_t *>(lbase + 64 * 16 * 2)};
     mlp::Frags fr;
     if constexpr (LEARNED) mlp::load_frags(a.mlp, fr);
@@ -726,8 +726,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             }
             if (lane == 0) {
                 sh.nd = nd;
-                // wavefront w starts with product index w (the packed learned VND: with batch w)
-                sh.next_prod = PACK ? W * a.learned_pack : W;
+                sh.next_prod = W;   // wavefront w starts with product index w
             }
         }
         __syncthreads();
@@ -864,9 +863,10 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
             // are); the products of a split round are shared out over the chain's workgroups in fixed order.
             const bool dyn = vstep == W;
             if constexpr (PACK) {
-                // the packed learned VND: batches of up to P products, handed to wavefronts as they finish
+                // the packed learned VND: batches of up to P products, each searched by the whole workgroup
+                // (a split round's batches shared out over the chain's workgroups in fixed order)
                 const int P = a.learned_pack;
-                const PackLds PL = pack_lds(lbase, P);
+                const PackLds PL = pack_lds(lbase, W, P);
                 auto round_now = [&]() -> int32_t {
                     if constexpr (COOP) {
                         if (may_abandon)
@@ -874,9 +874,10 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     }
                     return coop_round;
                 };
-                for (int base = vfirst * P; base < nprod && !stale;) {
+                const int bfirst = dyn ? 0 : vfirst / W, bstep = dyn ? 1 : vstep / W;   // in batches
+                for (int base = bfirst * P; base < nprod && !stale; base += bstep * P) {
                     const int cnt = min(P, nprod - base);
-                    if (lane == 0) {
+                    if (threadIdx.x == 0) {
                         for (int i = 0; i < cnt; ++i) {
                             const int idx = base + i;
                             int p, e = -1;
@@ -895,7 +896,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                             pr.need_ident = e >= 0 ? 1 : 0;
                         }
                     }
-                    wave_sync_lds();
+                    __syncthreads();
                     if (!learned_vnd_packed(PL, cnt, rows_in_lds ? s_rows : nullptr, inst_rows, a.prod + ci.prod0, T,
                                             a.nb_list, a.n_nb, a.memo, fr, a.permille, evals, nb_evals, fallbacks,
                                             coop_round, round_now)) {
@@ -904,22 +905,17 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                     }
                     for (int i = 0; i < cnt; ++i) {
                         const PackProd &pr = PL.pk[i];
-                        if (lane == 0) {
+                        if (threadIdx.x == 0) {
                             s_work[pr.p] = pr.b;
                             s_work_cost[pr.p] = pr.cost;
                         }
-                        part += pr.cost - pr.c_cur;
-                        shk += pr.shk;
-                        vnd_err |= pr.err;
+                        if (wave == 0) {   // the per-wavefront sums, once
+                            part += pr.cost - pr.c_cur;
+                            shk += pr.shk;
+                            vnd_err |= pr.err;
+                        }
                     }
-                    wave_sync_lds();
-                    if (dyn) {
-                        int v = 0;
-                        if (lane == 0) v = atomicAdd(&sh.next_prod, P);
-                        base = __builtin_amdgcn_readfirstlane(__shfl(v, 0, 64));
-                    } else {
-                        base += vstep * P;
-                    }
+                    __syncthreads();
                 }
             } else {
             for (int idx = vfirst; idx < nprod && !stale;

@@ -1047,8 +1047,9 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
                                    "(VNS_OPT_DECODE = 0)");
     VNS_HIP(c, run_kernel_lds(kind, &static_lds, 0, c->model));
     const bool packed = c->permille > 0 && c->learned_pack > 1;
-    const int64_t learned =
-        c->permille > 0 ? (int64_t)waves * (packed ? pack_wave_bytes(c->learned_pack) : kLearnedWaveBytes) : 0;
+    const int64_t learned = c->permille <= 0 ? 0
+                            : packed         ? (int64_t)pack_region_bytes(waves, c->learned_pack)
+                                             : (int64_t)waves * kLearnedWaveBytes;
     const int64_t room = c->max_lds_per_wg - (int64_t)static_lds - learned;   // dynamic LDS left for rows
     const int64_t slices = (int64_t)waves * kTMax;                   // per-wave rows when the instance does not fit
     if (room < slices * (int64_t)sizeof(int2)) return fail(c, VNS_EINVAL, "not enough LDS for the search kernel");

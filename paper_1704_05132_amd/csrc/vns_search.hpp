@@ -262,16 +262,16 @@ __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 
 }
 
 // ---------------------------------------------------------------------------------------------------
-// The learned VND of several products at once, by one wavefront (packed form).  The products of a batch
-// step through Algorithm 1 in lockstep: per step every product still searching takes its next
-// neighbourhood (in list order, skipping one already priced without improvement on the current pattern when
-// the memo is on); each one's moves are scored and its best-ranked ones selected (learned_select, one
-// product at a time); then the selections of all of them, with the unchanged shaken patterns still to
-// price, are priced exactly in one pass; the products whose selection holds no improving move get their
-// whole neighbourhood priced, all of them in one pass again; and each applies its move.  Per product the
-// selections, prices, fallbacks, moves and counted evaluations are those of learned_best_move in the
-// one-product VND: only the packing of lanes differs.  A selection of a few moves no longer costs a whole
-// T-period pass of its own.
+// The learned VND of several products at once, by the workgroup's wavefronts together (packed form).  The
+// products of a batch step through Algorithm 1 in lockstep: per step every product still searching takes its
+// next neighbourhood (in list order, skipping one already priced without improvement on the current pattern
+// when the memo is on); the wavefronts share the products out, each building the move lists, scores and
+// selections of its own (learned_select); then the selections of all of them, with the unchanged shaken
+// patterns still to price, are priced exactly in one packed list over every lane of the workgroup; the
+// products whose selection holds no improving move get their whole neighbourhood priced, all of them in one
+// packed list again; and each applies its move.  Per product the selections, prices, fallbacks, moves and
+// counted evaluations are those of learned_best_move in the one-product VND: only the packing of lanes
+// differs, so a selection of a few moves no longer takes a whole T-period pass of its own.
 // ---------------------------------------------------------------------------------------------------
 struct PackProd {
     Bits b;                    // the product's current pattern
@@ -285,21 +285,24 @@ struct PackProd {
 };
 static_assert(sizeof(PackProd) == kPackProdBytes, "the packed region's layout");
 
-// One wavefront's LDS for the packed form: the feature tile, the batch's records, move lists, selections and
-// (when the instance's rows are not resident) staged rows.
+// The workgroup's LDS for the packed form: a feature tile per wavefront, a small control block, then per
+// product its record, move list, selection and (when the instance's rows are not resident) staged row.
 struct PackLds {
-    __bf16 *sx;      // [64][16]
+    __bf16 *sx;      // [W][64][16]
+    int32_t *ctl;    // [4]: the round count read at a step's start
     PackProd *pk;    // [P]
     uint16_t *list;  // [P][2 kTMax]
     uint16_t *sel;   // [P][2 kTMax]
     int2 *rows;      // [P][kTMax]
 };
 
-// The region of pack_wave_bytes(P) bytes at base, for batches of up to P products.
-__device__ __forceinline__ PackLds pack_lds(char *base, int P) {
+// The region of pack_region_bytes(W, P) bytes at base.
+__device__ __forceinline__ PackLds pack_lds(char *base, int W, int P) {
     PackLds L;
     L.sx = reinterpret_cast<__bf16 *>(base);
-    base += 64 * 16 * 2;
+    base += W * 64 * 16 * 2;
+    L.ctl = reinterpret_cast<int32_t *>(base);
+    base += 16;
     L.pk = reinterpret_cast<PackProd *>(base);
     base += P * sizeof(PackProd);
     L.list = reinterpret_cast<uint16_t *>(base);
@@ -318,18 +321,20 @@ __device__ __forceinline__ int pack_owner(const int (&off)[kPackMax + 1], int n,
     return i;
 }
 
-// Runs the batch L.pk[0 .. n-1] (p, b, cost, c_cur, need_ident set by the caller) to its local optima.  rows:
-// the instance's rows when resident in LDS, else null (inst_rows in device memory are staged per product).
-// prod: the instance's product parameters.  round_now() is read before each step and compared with `round`
-// after it: false means the round moved on and the batch was abandoned.
+// Runs the batch L.pk[0 .. n-1] (p, b, cost, c_cur, need_ident set by the caller before a barrier) to its
+// local optima; every thread of the workgroup calls it.  rows: the instance's rows when resident in LDS, else
+// null (inst_rows in device memory are staged per product).  prod: the instance's product parameters.
+// round_now() is read (by thread 0) at each step's start and compared with `round` at its end: false means
+// the round moved on and the batch was abandoned.  The evaluation counters are advanced in wavefront 0 only.
 template <class RoundNow>
 __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, const int2 *rows, const int2 *inst_rows,
                                                    const ProdParams *prod, int T, uint32_t nb_list, int n_nb, int memo,
                                                    const mlp::Frags &fr, int permille, int64_t &evals,
                                                    int64_t &nb_evals, int64_t &fallbacks, int32_t round,
                                                    RoundNow round_now) {
-    const int lane = threadIdx.x & 63;
-    if (lane == 0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, W = blockDim.x >> 6, nthr = blockDim.x;
+    const bool counter = wave == 0;
+    if (threadIdx.x == 0) {
         for (int i = 0; i < n; ++i) {
             PackProd &s = L.pk[i];
             s.q = 0;
@@ -344,14 +349,15 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
     if (!rows) {
         for (int i = 0; i < n; ++i) {
             const int p = L.pk[i].p;
-            for (int t = lane; t < T; t += 64) L.rows[i * kTMax + t] = inst_rows[p * T + t];
+            for (int t = threadIdx.x; t < T; t += nthr) L.rows[i * kTMax + t] = inst_rows[p * T + t];
         }
     }
-    wave_sync_lds();
+    __syncthreads();
     auto row_of = [&](int i, int p) -> const int2 * { return rows ? rows + p * T : L.rows + i * kTMax; };
+    __bf16 *sx = L.sx + wave * 64 * mlp::kF;
     for (;;) {
-        // 1. each product's next neighbourhood (lane 0 advances the states)
-        if (lane == 0) {
+        // 1. each product's next neighbourhood (thread 0 advances the states)
+        if (threadIdx.x == 0) {
             for (int i = 0; i < n; ++i) {
                 PackProd &s = L.pk[i];
                 s.nb = -1;
@@ -371,16 +377,17 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
                     }
                 }
             }
+            L.ctl[0] = round_now();
         }
-        wave_sync_lds();
+        __syncthreads();
         int stepping = 0;
         for (int i = 0; i < n; ++i) stepping += L.pk[i].nb >= 0 ? 1 : 0;
         if (stepping == 0) return true;
-        const int32_t r0 = round_now();
-        // 2. move lists, scores and selections, one product at a time
-        for (int i = 0; i < n; ++i) {
+        // 2. move lists, scores and selections: the stepping products shared out over the wavefronts
+        for (int i = 0, r = 0; i < n; ++i) {
             const int nb = L.pk[i].nb;
             if (nb < 0) continue;
+            if ((r++ % W) != wave) continue;
             const Bits b = L.pk[i].b;
             const int p = L.pk[i].p;
             const ProdParams pp = prod[p];
@@ -388,7 +395,7 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
             int nflip;
             bool fm;
             const int nitems = move_list(b, T, (uint32_t)nb, list, nflip, fm);
-            const int nsel = nitems > 0 ? learned_select(b, row_of(i, p), T, pp, nitems, nflip, fm, list, L.sx,
+            const int nsel = nitems > 0 ? learned_select(b, row_of(i, p), T, pp, nitems, nflip, fm, list, sx,
                                                          L.sel + i * 2 * kTMax, fr, permille, nullptr, nullptr)
                                         : 0;
             if (lane == 0) {
@@ -401,7 +408,7 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
                 s.fb = 0;
             }
         }
-        wave_sync_lds();
+        __syncthreads();
         // 3. every selection, and every unchanged pattern still to price, in one packed list
         int off[kPackMax + 1];
         off[0] = 0;
@@ -409,8 +416,8 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
         for (int i = 0; i < kPackMax; ++i)
             off[i + 1] = off[i] + ((i < n && L.pk[i].nb >= 0) ? L.pk[i].nsel + L.pk[i].need_ident : 0);
         const int total = off[kPackMax];
-        for (int basei = 0; basei < total; basei += 64) {
-            const int idx = basei + lane;
+        for (int basei = 0; basei < total; basei += nthr) {
+            const int idx = basei + (int)threadIdx.x;
             if (idx < total) {
                 const int i = pack_owner(off, n, idx), k = idx - off[i];
                 const int p = L.pk[i].p;
@@ -424,10 +431,11 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
                     atomicMin(&L.pk[i].best, ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
             }
         }
-        for (int i = 0; i < n; ++i) evals += L.pk[i].nb >= 0 ? L.pk[i].nsel : 0;
-        wave_sync_lds();
+        if (counter)
+            for (int i = 0; i < n; ++i) evals += L.pk[i].nb >= 0 ? L.pk[i].nsel : 0;
+        __syncthreads();
         // 4. the unchanged patterns' prices, and which selections hold no improving move
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             for (int i = 0; i < n; ++i) {
                 PackProd &s = L.pk[i];
                 if (s.nb < 0) continue;
@@ -441,13 +449,13 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
                 if (s.fb) s.best = kInfKey;
             }
         }
-        wave_sync_lds();
+        __syncthreads();
         // 5. fallback: the whole neighbourhoods of those products, in one packed list
 #pragma unroll
         for (int i = 0; i < kPackMax; ++i) off[i + 1] = off[i] + ((i < n && L.pk[i].nb >= 0 && L.pk[i].fb) ? L.pk[i].nitems : 0);
         const int ftotal = off[kPackMax];
-        for (int basei = 0; basei < ftotal; basei += 64) {
-            const int idx = basei + lane;
+        for (int basei = 0; basei < ftotal; basei += nthr) {
+            const int idx = basei + (int)threadIdx.x;
             if (idx < ftotal) {
                 const int i = pack_owner(off, n, idx), k = idx - off[i];
                 const int p = L.pk[i].p;
@@ -458,15 +466,17 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
                 if (c != kInf) atomicMin(&L.pk[i].best, ((unsigned long long)c << kSlotBits) | (unsigned long long)slot);
             }
         }
-        for (int i = 0; i < n; ++i) {
-            if (L.pk[i].nb < 0) continue;
-            evals += L.pk[i].fb ? L.pk[i].nitems : 0;
-            nb_evals += 1;
-            fallbacks += L.pk[i].fb;
+        if (counter) {
+            for (int i = 0; i < n; ++i) {
+                if (L.pk[i].nb < 0) continue;
+                evals += L.pk[i].fb ? L.pk[i].nitems : 0;
+                nb_evals += 1;
+                fallbacks += L.pk[i].fb;
+            }
         }
-        wave_sync_lds();
+        __syncthreads();
         // 6. each product's move, when it improves
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             for (int i = 0; i < n; ++i) {
                 PackProd &s = L.pk[i];
                 if (s.nb < 0) continue;
@@ -481,8 +491,8 @@ __device__ __forceinline__ bool learned_vnd_packed(const PackLds &L, int n, cons
                 ++s.q;
             }
         }
-        wave_sync_lds();
-        if (__builtin_amdgcn_readfirstlane(r0) != round) return false;
+        __syncthreads();
+        if (L.ctl[0] != round) return false;
     }
 }
 

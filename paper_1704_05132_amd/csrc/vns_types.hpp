@@ -109,7 +109,7 @@ struct RunArgs {
     int32_t lds_rows;       // int2 entries of dynamic LDS for an instance's rows: a chain whose instance has
                             // at most that many periods in total keeps them all in LDS for the whole launch
     int32_t permille;       // learned scorer: price the best-ranked permille/1000 of each neighbourhood; 0 = off
-    int32_t learned_pack;   // learned VND: > 1 = products per wavefront batch (packed form), else one at a time
+    int32_t learned_pack;   // learned VND: > 1 = products per workgroup batch (packed form), else one at a time
     const float *mlp;       // scorer parameters (5313 float32)
     float *log_x;           // move log: [log_cap][16] features, [log_cap] targets, count (null = off)
     float *log_y;
@@ -166,13 +166,13 @@ constexpr uint32_t kCoopSpinLimit = 1u << 28;   // and after this many polls (at
 // state.
 constexpr int kLearnedWaveBytes = 64 * 16 * 2 + 2 * kTMax * 2;
 static_assert(kLearnedWaveBytes % 16 == 0, "learned tiles stay 16-byte aligned");
-// The packed learned VND (VNS_OPT_LEARNED_PACK): batches of up to P <= kPackMax products per wavefront.  Its
-// per-wavefront region: the feature tile, then per product its record (kPackProdBytes), move list,
-// selection and staged row.
+// The packed learned VND (VNS_OPT_LEARNED_PACK): batches of up to P <= kPackMax products per workgroup.  Its
+// region: a feature tile per wavefront, a 16-byte control block, then per product its record
+// (kPackProdBytes), move list, selection and staged row.
 constexpr int kPackMax = 8;
 constexpr int kPackProdBytes = 128;
 constexpr int kPackPerProduct = kPackProdBytes + 2 * (2 * kTMax * 2) + kTMax * 8;
-__host__ __device__ inline int pack_wave_bytes(int P) { return 64 * 16 * 2 + P * kPackPerProduct; }
+__host__ __device__ inline int pack_region_bytes(int W, int P) { return W * 64 * 16 * 2 + 16 + P * kPackPerProduct; }
 static_assert(kPackPerProduct % 16 == 0, "packed regions stay 16-byte aligned");
 __host__ __device__ inline int run_rows_entries(int lds_rows, int waves) {
     const int e = lds_rows > waves * kTMax ? lds_rows : waves * kTMax;

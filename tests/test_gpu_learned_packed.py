@@ -1,10 +1,10 @@
 """GPU: the packed learned VND (VNS_OPT_LEARNED_PACK) against the one-product learned VND.
 
-The packed form runs the learned VNDs of up to P products in lockstep in one wavefront and prices their
-selections, and then their fallbacks, in shared passes.  Per product it must take exactly the same steps: so
-every record, solution and cost, and the counted exact evaluations, neighbourhood evaluations and fallbacks,
-equal the one-product search's (which the other learned tests check against the oracle's selection and
-fallback rules and local optimality).  Covered: P = 2, 3, 8; 1, 2 and 4 wavefronts; rows resident in LDS or
+The packed form runs the learned VNDs of up to P products in lockstep, all of a workgroup's wavefronts
+together, and prices their selections, and then their fallbacks, in shared passes.  Per product it must take
+exactly the same steps: so every record, solution and cost, and the counted exact evaluations, neighbourhood
+evaluations and fallbacks, equal the one-product search's (which the other learned tests check against the
+oracle's selection and fallback rules and local optimality).  Covered: P = 2, 3, 8; 1, 2 and 4 wavefronts; rows resident in LDS or
 staged per product; T <= 64 and T > 64; the memo of unchanged neighbourhoods; a selection of every move
 (permille 1000); speculative iterations; the first iteration (every product of x); uneven batches of
 instances; degenerate instances (one product, T = 1, no returns).
