@@ -46,8 +46,16 @@ hipError_t launch_mlp_score(const float *P, const float *X, int64_t n, float *ou
 hipError_t launch_mlp_grad(const float *P, const float *X, const float *y, const int64_t *idx, int64_t n, float *part,
                            float *grad_out, hipStream_t s);
 int64_t mlp_grad_partials(int64_t n);
-// One Adam step (step counts from 1) on P with moments m, v.
-hipError_t launch_adam(float *P, const float *grad, float *m, float *v, float lr, int64_t step, hipStream_t s);
+// Training rows of a minibatch: row r of it is (mul (start + r) + add) mod n of the training set.
+struct RowPerm {
+    uint64_t mul, add;
+    int64_t start, n;
+};
+// One training step (Adam step number `step`): the gradient of the minibatch's cnt rows (partials in part,
+// sized for mlp_grad_partials(cnt)), then in one kernel their fixed-order sum into grad_out (loss at
+// [5313]) and the Adam update of P, m, v.
+hipError_t launch_mlp_train_step(float *P, float *m, float *v, const float *X, const float *y, const RowPerm &perm,
+                                 int64_t cnt, float *part, float *grad_out, float lr, int64_t step, hipStream_t s);
 struct EvalLearnedArgs {
     const int32_t *cp_chain;
     const ChainInfo *chains;

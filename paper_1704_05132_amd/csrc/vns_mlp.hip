@@ -73,7 +73,7 @@ constexpr int kGradLd = 64 + 8;   // padded row (bfloat16) of the transposed til
 
 __global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ P, const float *__restrict__ X,
                                                  const float *__restrict__ y, const int64_t *__restrict__ idx,
-                                                 int64_t n, float inv_n, float *__restrict__ part) {
+                                                 RowPerm perm, int64_t n, float inv_n, float *__restrict__ part) {
     __shared__ __attribute__((aligned(16))) __bf16 sx[64 * kF];        // [row][feature]: forward input
     __shared__ __attribute__((aligned(16))) __bf16 xT[kF * kGradLd];   // [feature][row]
     __shared__ __attribute__((aligned(16))) __bf16 hT[kH * kGradLd];   // [unit][row]: relu(z1)
@@ -107,7 +107,11 @@ __global__ __launch_bounds__(64) void k_mlp_grad(const float *__restrict__ P, co
         // lane l stages row 64 tile + l (zeros past n: such rows have ds = 0 and add nothing)
         const int64_t r = tile * 64 + lane;
         const bool in = r < n;
-        const int64_t src = in ? (idx ? idx[r] : r) : 0;
+        const int64_t src = !in ? 0
+                            : idx ? idx[r]
+                            : perm.n > 0 ? (int64_t)(((unsigned __int128)perm.mul * (uint64_t)(perm.start + r) + perm.add) %
+                                                     (uint64_t)perm.n)
+                                         : r;
         const float yl = in ? y[src] : 0.f;
         const float4 *xs = reinterpret_cast<const float4 *>(X + src * kF);
 #pragma unroll
@@ -274,13 +278,19 @@ __global__ __launch_bounds__(256) void k_mlp_reduce(const float *__restrict__ pa
     out[e] = acc;
 }
 
-// Adam on the float32 master parameters.
-__global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, const float *__restrict__ grad, float *__restrict__ m,
-                                              float *__restrict__ v, float lr, float beta1, float beta2, float eps,
-                                              float corr1, float corr2) {
+// The fixed-order sum of the partial gradients (as k_mlp_reduce) and the Adam step on each parameter, in one
+// pass: thread e sums parameter e's partials, stores the gradient (and the loss at e = kParams) and updates
+// the parameter and its moments.
+__global__ __launch_bounds__(256) void k_mlp_reduce_adam(const float *__restrict__ part, int64_t nb, float *__restrict__ out,
+                                                         float *__restrict__ P, float *__restrict__ m,
+                                                         float *__restrict__ v, float lr, float beta1, float beta2,
+                                                         float eps, float corr1, float corr2) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= kParams) return;
-    const float g = grad[e];
+    if (e > kParams) return;
+    float g = 0.f;
+    for (int64_t b = 0; b < nb; ++b) g += part[b * (kParams + 1) + e];
+    out[e] = g;
+    if (e == kParams) return;
     const float mm = beta1 * m[e] + (1.f - beta1) * g;
     const float vv = beta2 * v[e] + (1.f - beta2) * g * g;
     m[e] = mm;
@@ -302,7 +312,8 @@ hipError_t launch_mlp_grad(const float *P, const float *X, const float *y, const
                            float *grad_out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int64_t nb = mlp_grad_partials(n);
-    hipLaunchKernelGGL(mlp::k_mlp_grad, dim3((unsigned)nb), dim3(64), 0, s, P, X, y, idx, n, 1.f / (float)n, part);
+    hipLaunchKernelGGL(mlp::k_mlp_grad, dim3((unsigned)nb), dim3(64), 0, s, P, X, y, idx, RowPerm{0, 0, 0, 0}, n,
+                       1.f / (float)n, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(mlp::k_mlp_reduce, dim3((mlp::kParams + 1 + 255) / 256), dim3(256), 0, s, part, nb, grad_out);
@@ -311,11 +322,18 @@ hipError_t launch_mlp_grad(const float *P, const float *X, const float *y, const
 
 int64_t mlp_grad_partials(int64_t n) { return std::min<int64_t>((n + 63) / 64, mlp::kGradWaves); }
 
-hipError_t launch_adam(float *P, const float *grad, float *m, float *v, float lr, int64_t step, hipStream_t s) {
+hipError_t launch_mlp_train_step(float *P, float *m, float *v, const float *X, const float *y, const RowPerm &perm,
+                                 int64_t cnt, float *part, float *grad_out, float lr, int64_t step, hipStream_t s) {
+    if (cnt <= 0) return hipSuccess;
+    const int64_t nb = mlp_grad_partials(cnt);
+    hipLaunchKernelGGL(mlp::k_mlp_grad, dim3((unsigned)nb), dim3(64), 0, s, P, X, y, nullptr, perm, cnt,
+                       1.f / (float)cnt, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-    hipLaunchKernelGGL(mlp::k_adam, dim3((mlp::kParams + 255) / 256), dim3(256), 0, s, P, grad, m, v, 1.f * lr, b1, b2,
-                       1e-8f, c1, c2);
+    hipLaunchKernelGGL(mlp::k_mlp_reduce_adam, dim3((mlp::kParams + 1 + 255) / 256), dim3(256), 0, s, part, nb, grad_out,
+                       P, m, v, lr, b1, b2, 1e-8f, c1, c2);
     return hipGetLastError();
 }
 

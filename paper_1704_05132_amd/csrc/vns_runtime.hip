@@ -1485,20 +1485,13 @@ extern "C" vns_status vns_mlp_grad(vns_ctx *c, const float *feats, const float *
     return record_mlp_time(c, n);
 }
 
-__global__ void k_batch_index(int64_t *idx, int64_t start, int64_t count, int64_t n, uint64_t mul, uint64_t add) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < count) idx[r] = (int64_t)(((unsigned __int128)mul * (uint64_t)(start + r) + add) % (uint64_t)n);
-}
-
 extern "C" vns_status vns_mlp_train(vns_ctx *c, const float *feats, const float *targets, int64_t n, int32_t epochs,
                                     int32_t batch, float lr, uint64_t seed, float *last_loss) {
     VNS_LIVE(c);
     if (n <= 0 || !feats || !targets || epochs < 0 || batch < 1 || !(lr > 0.f)) return fail(c, VNS_EINVAL, "bad arguments");
     Scoped<float> X, Y;
-    Scoped<int64_t> idx;
     VNS_HIP(c, dmalloc(&X.p, (size_t)n * mlp::kF));
     VNS_HIP(c, dmalloc(&Y.p, (size_t)n));
-    VNS_HIP(c, dmalloc(&idx.p, (size_t)batch));
     VNS_HIP(c, hipMemcpyAsync(X.p, feats, sizeof(float) * mlp::kF * (size_t)n, hipMemcpyHostToDevice, c->stream));
     VNS_HIP(c, hipMemcpyAsync(Y.p, targets, sizeof(float) * (size_t)n, hipMemcpyHostToDevice, c->stream));
     const int64_t bmax = std::min<int64_t>(batch, n);
@@ -1517,11 +1510,9 @@ extern "C" vns_status vns_mlp_train(vns_ctx *c, const float *feats, const float 
         const uint64_t add = state % (uint64_t)n;
         for (int64_t s0 = 0; s0 < n; s0 += bmax) {
             const int64_t cnt = std::min<int64_t>(bmax, n - s0);
-            hipLaunchKernelGGL(k_batch_index, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, c->stream, idx.p, s0, cnt, n,
-                               mul, add);
-            VNS_HIP(c, hipGetLastError());
-            VNS_HIP(c, launch_mlp_grad(c->d_mlp, X.p, Y.p, idx.p, cnt, gs.part.p, gs.grad.p, c->stream));
-            VNS_HIP(c, launch_adam(c->d_mlp, gs.grad.p, c->d_adam_m, c->d_adam_v, lr, ++c->adam_step, c->stream));
+            // the minibatch's rows (mul i + add) mod n, i = s0 .. s0 + cnt - 1, are computed in the gradient kernel
+            VNS_HIP(c, launch_mlp_train_step(c->d_mlp, c->d_adam_m, c->d_adam_v, X.p, Y.p, RowPerm{mul, add, s0, n}, cnt,
+                                             gs.part.p, gs.grad.p, lr, ++c->adam_step, c->stream));
         }
     }
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
