@@ -63,7 +63,8 @@ PACKED_P, PACKED_WAVES = 8, 2   # the packed learned search's batch and workgrou
 MLP_FLOP_PER_ROW = 2 * (16 * 64 + 64 * 64 + 64)
 BF16_PEAK_TFLOPS = 2500.0
 METRIC = "exact move-evals/s (int64 cost) + time-to-plain-best-cost, learned vs plain"
-SWEEP_LAUNCH = "k_eval: every chain, neighbourhoods flip zM + flip zR + shift, tuned chains per workgroup"
+SWEEP_LAUNCH = ("k_eval: every chain, neighbourhoods flip zM + flip zR + shift, tuned launch shape (chains per "
+                "workgroup, or pair ranges spread over the compute units)")
 SEARCH_LAUNCH = "search: every chain, the workload's iterations in one launch, tuned launch shape"
 
 
@@ -182,8 +183,11 @@ def sweep_steps(torch, vns, ctx, stream, steps, warmup):
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     achieved = psteps * OPS_PER_PERIOD_STEP / (sum(k_ms) / 1e3) / 1e12
+    wide = ctx.get_option(vns.OPT_EVAL_SPREAD) > 4   # the range form with 8-16 wavefronts per workgroup
     return {"steps": steps, "move_evals_per_step": evals // max(steps, 1), "device_ms": ms, "wall_s": wall,
-            "value": evals / (ms / 1e3), "unit": "move-evals/s", "kernel": "k_eval",
+            "value": evals / (ms / 1e3), "unit": "move-evals/s", "kernel": "k_eval_wide" if wide else "k_eval",
+            "launch_shape": {"spread": ctx.get_option(vns.OPT_EVAL_SPREAD),
+                             "group": ctx.get_option(vns.OPT_EVAL_GROUP)},
             "kernel_ms_mean": sum(k_ms) / len(k_ms), "kernel_ms_median": statistics.median(k_ms),
             "kernel_share": sum(k_ms) / ms, "achieved": achieved, "peak": VALU_PEAK_OPS / 1e12,
             "frac": achieved / (VALU_PEAK_OPS / 1e12)}
@@ -617,9 +621,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": sweep["device_ms"] / max(args.steps, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic", "config": config,
         "move_evals_per_step": sweep["move_evals_per_step"], "wall_s": sweep["wall_s"],
-        "roofline": {"kernel": "k_eval", "launch": SWEEP_LAUNCH, "bound": "alu", "achieved": sweep["achieved"],
+        "roofline": {"kernel": sweep["kernel"], "launch": SWEEP_LAUNCH, "bound": "alu", "achieved": sweep["achieved"],
                      "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s", "frac": sweep["frac"],
-                     "traffic": measured_traffic("k_eval", name, "sweep"),
+                     "traffic": measured_traffic(sweep["kernel"], name, "sweep"),
                      "kernel_ms_mean": sweep["kernel_ms_mean"], "ops_per_period_step": OPS_PER_PERIOD_STEP,
                      "accumulators": "int32 under the create-time bounds; costs int64"},
         "sweeps": {name: sweep},

@@ -139,12 +139,19 @@ enum vns_option {
                               period yR(t) - min over s >= t of yR(s).  Setting it restarts every chain
                               from the initial solution.  The learned search, the speculative VND,
                               incremental pricing and vns_eval_learned take only 0 (VNS_EINVAL)       */
-    VNS_OPT_LEARNED_PACK = 20 /* learned VND only: P in 2..8 = a workgroup's wavefronts run the VNDs of up to
+    VNS_OPT_LEARNED_PACK = 20, /* learned VND only: P in 2..8 = a workgroup's wavefronts run the VNDs of up to
                               P products in lockstep together (packed form), pricing their selections
                               in shared passes and their fallbacks in shared passes; 0 or 1 (default 0)
                               = one product per wavefront at a time.  Moves, prices, records and counted
                               evaluations are the same.  The workgroup then needs 2 KB of LDS per
                               wavefront and 2.1 KB per product                                       */
+    VNS_OPT_EVAL_SPREAD = 21 /* vns_eval_neighbourhood's launch shape: W in {4, 8, 12, 16} = the (chain,
+                              product) pairs of each instance, product by product, are split into
+                              near-equal ranges, 24 / W workgroups of W wavefronts per compute unit
+                              (one for W = 16), each pricing every move of its range (a range spans a
+                              few products when their rows fit its LDS); 0 (default) = one workgroup
+                              per product and group of VNS_OPT_EVAL_GROUP chains.  Same prices and
+                              argmins.  Not used with incremental pricing                             */
 };
 
 /* One GVNS iteration of one chain. */

@@ -4,7 +4,8 @@ The search kernel runs one workgroup per chain; how many wavefronts a workgroup 
 chain's products run their VND side by side), whether the neighbourhoods of one product's VND are priced
 side by side by a group of wavefronts (speculative VND, `spec`) and how much LDS it may use to keep an
 instance's rows resident trade occupancy against parallelism, and the best choice depends on K, T and the
-number of chains.  The pricing kernel's tuning knob is how many chains of an instance share one workgroup.  Results
+number of chains.  The pricing kernel's tuning knob is how many chains of an instance share one workgroup, or the
+range form with its wavefronts per workgroup (`spread`: the pairs split evenly over the compute units).  Results
 never depend on these choices (the kernels compute the same exact costs and trajectories); only time does.
 
 `tune_search` and `tune_eval` time each candidate on the actual workload with the library's own device
@@ -21,7 +22,7 @@ SEARCH_CANDIDATES = ([dict(waves=w, lds=l, spec=0, state=st) for w in (2, 4, 8) 
                      [dict(waves=w, lds=65536, spec=0, iters=m) for w, m in
                       ((8, 2), (8, 3), (8, 4), (4, 3), (4, 4), (4, 6), (4, 8), (4, 12), (3, 8), (3, 12), (2, 6),
                        (2, 8))])
-EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 3, 4, 5, 6, 8, 12, 16)]
+EVAL_CANDIDATES = [dict(group=g) for g in (1, 2, 3, 4, 5, 6, 8, 12, 16)] + [dict(spread=w) for w in (4, 8, 12, 16)]
 
 
 def signature(instances, chains: int) -> str:
@@ -86,12 +87,22 @@ def search_options(c: dict) -> dict:
     return opts
 
 
+def eval_options(c: dict) -> dict:
+    """Pricing-kernel options of a tuning choice: the range form (`spread`) or chains per workgroup (`group`)."""
+    from . import vns
+    opts = {vns.OPT_EVAL_SPREAD: int(c.get("spread", 0))}
+    if "group" in c:
+        opts[vns.OPT_EVAL_GROUP] = c["group"]
+    return opts
+
+
 def tune_eval(ctx, nb_mask: int = 7, reps: int = 5, candidates: Sequence[dict] = tuple(EVAL_CANDIDATES)):
-    """Median device time of a full pricing sweep of every chain of ctx for each chains-per-workgroup value."""
+    """Median device time of a full pricing sweep of every chain of ctx for each pricing launch shape."""
     from . import vns
 
     def measure(c):
-        ctx.set_option(vns.OPT_EVAL_GROUP, c["group"])
+        for opt, v in eval_options(c).items():
+            ctx.set_option(opt, v)
         ms = []
         for _ in range(reps):
             ctx.eval_neighbourhood(nb_mask, vns.ALL_CHAINS, slot_prices=False)
@@ -99,7 +110,8 @@ def tune_eval(ctx, nb_mask: int = 7, reps: int = 5, candidates: Sequence[dict] =
         return sorted(ms)[len(ms) // 2]
 
     best, timings = pick(candidates, measure)
-    ctx.set_option(vns.OPT_EVAL_GROUP, best["group"])
+    for opt, v in eval_options(best).items():
+        ctx.set_option(opt, v)
     return best, timings
 
 
@@ -126,6 +138,6 @@ class TuneTable:
         ch = e["choice"]
         for opt, v in search_options(ch).items():
             ctx.set_option(opt, v)
-        if "group" in ch:
-            ctx.set_option(vns.OPT_EVAL_GROUP, ch["group"])
+        for opt, v in eval_options(ch).items():
+            ctx.set_option(opt, v)
         return True

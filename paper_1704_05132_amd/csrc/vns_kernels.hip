@@ -84,12 +84,14 @@ struct EvalShared {
     int64_t out_off[kEvalPairs];
     int32_t off[kEvalPairs + 1];
     int32_t nswap[kEvalPairs];
+    uint8_t pidx[kEvalPairs];     // product index of each pair within the workgroup's products
     // the workgroup's moves, pair by pair (flips, then zM swaps, then zR swaps): pair << 9 | block << 7 | t
     uint16_t item[kEvalItems];
     int32_t tcount[kTMax];        // incremental pricing: moves per period, then their offsets
     int32_t decoded;              //   and the period-steps its batches ran, per lane
 };
 static_assert(kEvalPairs <= 128 && kTMax <= 128, "item packing");
+static_assert(kEvalPairs <= 64, "one wavefront scans the pairs' move counts");
 static_assert(kEvalGroup * 4 * kTMax <= kEvalItems, "one product of a full group of chains fits the item table");
 
 __device__ __forceinline__ uint16_t pack_item(int j, int blk, int t) { return (uint16_t)((j << 9) | (blk << 7) | t); }
@@ -99,7 +101,7 @@ __device__ __forceinline__ uint16_t pack_item(int j, int blk, int t) { return (u
 // lane reads those of its pair's product.
 template <int NW, int MODEL>
 __device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, int N, int T, const ProdParams &pp,
-                                           int nc, int np) {
+                                           int np) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int basei = wave * 64; basei < N; basei += blockDim.x) {
         const int idx = basei + lane;
@@ -113,7 +115,7 @@ __device__ __forceinline__ void eval_items(const EvalArgs &a, EvalShared &sh, in
         if (np == 1) {
             c = decode_cost<NW, MODEL>(mb, sh.row, T, pp);
         } else {
-            const int pi = j / nc;
+            const int pi = sh.pidx[j];
             c = decode_cost<NW, MODEL>(mb, sh.row + pi * T, T, sh.pp[pi]);
         }
         if (in) {
@@ -231,22 +233,37 @@ __device__ __forceinline__ void eval_items_inc(const EvalArgs &a, EvalShared &sh
     atomicAdd(&sh.decoded, decoded);
 }
 
+// Pair j of a pricing workgroup: its product index pi within the workgroup's products and its chain index ci
+// (from g0), in the rectangular form (j = pi * nc + ci) or the range form.
+__device__ __forceinline__ void eval_pair(const EvalWg &d, int j, int &pi, int &ci) {
+    if (d.G > 0) {
+        const int q = d.q0 + j;
+        pi = q / d.G - d.p;
+        ci = q - (q / d.G) * d.G;
+    } else {
+        pi = j / d.n;
+        ci = j - pi * d.n;
+    }
+}
+
 template <bool INC, int MODEL = 0>
 __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__restrict__ wg, EvalShared &sh,
                                           int4 *s_snap) {
     const EvalWg d = wg[blockIdx.x];
     if (d.n == 0) return;   // an empty entry (uniform for the workgroup)
-    const int g0 = d.g0, K = d.K, T = d.T, p = d.p, nc = d.n;
+    const int g0 = d.g0, K = d.K, T = d.T, p = d.p;
     const int np = INC ? 1 : max(d.np, 1);
-    const int n = nc * np;  // pairs: j = product index * nc + chain index
+    const int n = d.G > 0 ? d.n : d.n * np;   // pairs
     const ProdParams pp = a.prod[d.prod];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int t = threadIdx.x; t < np * T; t += blockDim.x) sh.row[t] = a.rows[d.row + t];
     if (np > 1)
         for (int q = threadIdx.x; q < np; q += blockDim.x) sh.pp[q] = a.prod[d.prod + q];
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const int pi = j / nc, ci = j - pi * nc;
+        int pi, ci;
+        eval_pair(d, j, pi, ci);
         const int64_t cp = d.cp + (int64_t)ci * K + pi;
+        sh.pidx[j] = (uint8_t)pi;
         sh.bits[j] = a.cur[cp];
         sh.cost[j] = a.cur_cost[cp];
         sh.F[j] = a.cstate[g0 + ci].F;
@@ -273,13 +290,16 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
             for (int l = threadIdx.x; l < 4 * T; l += blockDim.x) a.slot_price[sh.out_off[j] + l] = kInf;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int o = 0;
-        for (int j = 0; j < n; ++j) {
-            sh.off[j] = o;
-            o += nflip + sh.nswap[j];
+    if (wave == 0) {   // exclusive prefix of the pairs' move counts (n <= 64: one value per lane)
+        const int cnt = lane < n ? nflip + sh.nswap[lane] : 0;
+        int inc = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int up = __shfl_up(inc, d, 64);
+            inc += lane >= d ? up : 0;
         }
-        sh.off[n] = o;
+        if (lane < n) sh.off[lane] = inc - cnt;
+        if (lane == 63) sh.off[n] = inc;
     }
     __syncthreads();
     // the item table: flips (zM then zR), then each chain's valid swaps in period order; for incremental
@@ -362,13 +382,14 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
             eval_items_inc<4>(a, sh, snapA, snapB, N, T, pp);
     } else {
         if (T <= 64)
-            eval_items<2, MODEL>(a, sh, N, T, pp, nc, np);
+            eval_items<2, MODEL>(a, sh, N, T, pp, np);
         else
-            eval_items<4, MODEL>(a, sh, N, T, pp, nc, np);
+            eval_items<4, MODEL>(a, sh, N, T, pp, np);
     }
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        const int pi = j / nc, ci = j - pi * nc;
+        int pi, ci;
+        eval_pair(d, j, pi, ci);
         a.prod_key[d.cp + (int64_t)ci * K + pi] = sh.key[j];
     }
     if (threadIdx.x == 0) {
@@ -385,6 +406,13 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
 
 template <int MODEL>
 __global__ __launch_bounds__(256) void k_eval(EvalArgs a, const EvalWg *__restrict__ wg) {
+    __shared__ EvalShared sh;
+    eval_body<false, MODEL>(a, wg, sh, nullptr);
+}
+
+// The same with 512-1024-thread workgroups (the range form spread over the compute units).
+template <int MODEL>
+__global__ __launch_bounds__(1024) void k_eval_wide(EvalArgs a, const EvalWg *__restrict__ wg) {
     __shared__ EvalShared sh;
     eval_body<false, MODEL>(a, wg, sh, nullptr);
 }
@@ -1450,6 +1478,9 @@ static const void *by_model(int model) {
 }
 template <int M> struct PickInit { static const void *fn() { return reinterpret_cast<const void *>(&k_init_costs<M>); } };
 template <int M> struct PickEval { static const void *fn() { return reinterpret_cast<const void *>(&k_eval<M>); } };
+template <int M> struct PickEvalWide {
+    static const void *fn() { return reinterpret_cast<const void *>(&k_eval_wide<M>); }
+};
 template <int M> struct PickRun { static const void *fn() { return reinterpret_cast<const void *>(&k_run<M>); } };
 template <int M> struct PickCoop { static const void *fn() { return reinterpret_cast<const void *>(&k_run_coop<M>); } };
 
@@ -1460,12 +1491,14 @@ hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s, int model
     return hipLaunchKernel(by_model<PickInit>(model), dim3(n_chains), dim3(256), params, 0, s);
 }
 
-hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s, int model) {
+hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s, int model, int waves) {
     if (n_wg <= 0) return hipSuccess;
+    if (waves != 4 && waves != 8 && waves != 12 && waves != 16) return hipErrorInvalidValue;
     EvalArgs args = a;
     const EvalWg *w = wg;
     void *params[] = {&args, &w};
-    return hipLaunchKernel(by_model<PickEval>(model), dim3((unsigned)n_wg), dim3(256), params, 0, s);
+    const void *fn = waves == 4 ? by_model<PickEval>(model) : by_model<PickEvalWide>(model);
+    return hipLaunchKernel(fn, dim3((unsigned)n_wg), dim3(64 * waves), params, 0, s);
 }
 
 hipError_t launch_eval_prep(const EvalPrepArgs &a, hipStream_t s) {

@@ -78,7 +78,8 @@ struct EvalLearnedArgs {
 
 hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s, int model);
 hipError_t launch_eval_learned(const EvalLearnedArgs &a, int64_t cp_begin, int64_t n_cp, hipStream_t s);
-hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s, int model);
+// waves: 4 (k_eval) or 8, 12, 16 (k_eval_wide) wavefronts per workgroup.
+hipError_t launch_eval(const EvalArgs &a, const EvalWg *wg, int64_t n_wg, hipStream_t s, int model, int waves = 4);
 // The pricing table of a chain range and zeroed counters, built on the device (no host staging).
 hipError_t launch_eval_prep(const EvalPrepArgs &a, hipStream_t s);
 // Incremental pricing of the same sweep; lds_bytes of dynamic LDS hold each workgroup's base snapshots

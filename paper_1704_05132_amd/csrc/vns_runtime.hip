@@ -93,6 +93,8 @@ struct vns_ctx {
     int32_t trace = 1;
     int32_t run_waves = 8;
     int32_t eval_group = 4;
+    int32_t eval_spread = 0;              // pricing: wavefronts per workgroup of the range form (0 = off)
+    int32_t n_cu = 256;                   // compute units of the device (queried at create)
     int64_t run_lds_budget = 64 * 1024;   // bytes of LDS the search kernel may use for an instance's rows
     int32_t use_graph = 0;
     int64_t max_lds_per_wg = 65536;       // device limit on LDS per workgroup (queried at create)
@@ -153,8 +155,9 @@ struct vns_ctx {
     int64_t graph_key[5] = {-1, -1, -1, -1, -1};  // (iters, chains, waves, LDS bytes, trace buffer)
     EvalWg *d_eval_wg = nullptr;          // k_eval workgroup table of the last chain range priced
     int64_t eval_wg_n = 0;
-    int64_t eval_wg_key[4] = {-1, -1, -1, -1};  // (first chain, number of chains, group size, incremental) of
-                                                 // that table (incremental pricing takes one product per entry)
+    int64_t eval_wg_key[4] = {-1, -1, -1, -1};  // (first chain, number of chains, group size, form: 1
+                                                 // incremental, 2 + spread otherwise) of that table
+                                                 // (incremental pricing takes one product per entry)
 
     char *ws = nullptr;                   // caller-owned workspace (vns_bind_workspace), its size and flags
     size_t ws_bytes = 0;
@@ -456,6 +459,8 @@ extern "C" vns_status vns_create_batch(int32_t n_inst, const int32_t *K, const i
         int v = 0;
         VNS_CREATE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
         c->max_lds_per_wg = v;
+        VNS_CREATE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->n_cu = std::max(v, 1);
         VNS_CREATE_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, c->device));   // kHz
         c->coop_wait_ticks = (int64_t)((double)(v > 0 ? v : 100000) * 1000.0 * kCoopWaitSeconds);
     }
@@ -539,6 +544,11 @@ extern "C" vns_status vns_set_option(vns_ctx *c, int32_t key, int64_t v) {
             if (v < 1 || v > kEvalGroup) return fail(c, VNS_EINVAL, "eval group out of range");
             c->eval_group = (int32_t)v;
             return VNS_OK;
+        case VNS_OPT_EVAL_SPREAD:
+            if (v != 0 && v != 4 && v != 8 && v != 12 && v != 16)
+                return fail(c, VNS_EINVAL, "eval spread must be 0, 4, 8, 12 or 16");
+            c->eval_spread = (int32_t)v;
+            return VNS_OK;
         case VNS_OPT_RUN_LDS:
             if (v < 0 || v > kRunLdsMax) return fail(c, VNS_EINVAL, "search kernel LDS budget out of range");
             c->run_lds_budget = v;
@@ -620,6 +630,7 @@ extern "C" vns_status vns_get_option(const vns_ctx *c, int32_t key, int64_t *v) 
         case VNS_OPT_TRACE: *v = c->trace; return VNS_OK;
         case VNS_OPT_RUN_WAVES: *v = c->run_waves; return VNS_OK;
         case VNS_OPT_EVAL_GROUP: *v = c->eval_group; return VNS_OK;
+        case VNS_OPT_EVAL_SPREAD: *v = c->eval_spread; return VNS_OK;
         case VNS_OPT_RUN_LDS: *v = c->run_lds_budget; return VNS_OK;
         case VNS_OPT_GRAPH: *v = c->use_graph; return VNS_OK;
         case VNS_OPT_LEARNED: *v = c->permille; return VNS_OK;
@@ -800,13 +811,55 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
     const int32_t group = c->eval_inc ? std::max<int32_t>(1, std::min<int32_t>(c->eval_group,
                                                                               kSnapLdsMax / ((maxT + 1) * kSnapBytes)))
                                       : c->eval_group;
-    const int64_t key[4] = {g0, ng, group, c->eval_inc};
+    const int32_t spread = c->eval_inc ? 0 : c->eval_spread;
+    const int64_t key[4] = {g0, ng, group, c->eval_inc ? 1 : 2 + spread};
     EvalWg *d_tab = ws_tab ? reinterpret_cast<EvalWg *>(c->ws + wl.eval_off) : c->d_eval_wg;
     if (!(key[0] == c->eval_wg_key[0] && key[1] == c->eval_wg_key[1] && key[2] == c->eval_wg_key[2] &&
           key[3] == c->eval_wg_key[3])) {
         std::vector<EvalWg> tab;
         int32_t g = g0;
-        while (g < g0 + ng) {
+        // range form: 24 wavefronts per compute unit (the pricing kernel's register bound), so n_cu * (24 / spread)
+        // workgroups; each instance gets its share of them by pairs, split into near-equal ranges
+        double per = 1.0;
+        if (spread) {
+            int64_t pairs = 0;
+            for (int32_t h = g0; h < g0 + ng; ++h) pairs += c->chains[(size_t)h].K;
+            per = std::max(1.0, (double)pairs / ((double)c->n_cu * std::max(1, 24 / spread)));
+        }
+        while (spread && g < g0 + ng) {
+            const ChainInfo &ci = c->chains[(size_t)g];
+            int32_t G = 1;
+            while (g + G < g0 + ng && c->chains[(size_t)(g + G)].inst == ci.inst) ++G;
+            // a range's moves (at most 4T per pair) fit the item table, its products' rows the row buffer
+            const int64_t len_max = std::max<int64_t>(1, std::min<int64_t>(kEvalPairs, kEvalItems / (4 * ci.T)));
+            const int32_t span_max = std::max<int32_t>(1, std::min<int32_t>(kEvalProds, kTMax / ci.T));
+            const int64_t P = (int64_t)G * ci.K;
+            const int64_t nr = std::max<int64_t>(1, std::llround((double)P / per));
+            for (int64_t r = 0; r < nr; ++r) {
+                const int64_t q_end = P * (r + 1) / nr;
+                for (int64_t q = P * r / nr; q < q_end;) {
+                    int64_t len = std::min<int64_t>(len_max, q_end - q);
+                    const int32_t p0 = (int32_t)(q / G);
+                    if ((q + len - 1) / G - p0 + 1 > span_max) len = (int64_t)(p0 + span_max) * G - q;
+                    EvalWg w{};
+                    w.cp = ci.cp0 + p0;
+                    w.g0 = g;
+                    w.n = (int32_t)len;
+                    w.K = ci.K;
+                    w.T = ci.T;
+                    w.p = p0;
+                    w.prod = ci.prod0 + p0;
+                    w.row = c->prod_row[(size_t)(ci.prod0 + p0)];
+                    w.np = (int32_t)((q + len - 1) / G - p0 + 1);
+                    w.q0 = (int32_t)q;
+                    w.G = G;
+                    tab.push_back(w);
+                    q += len;
+                }
+            }
+            g += G;
+        }
+        while (!spread && g < g0 + ng) {
             const ChainInfo &ci = c->chains[(size_t)g];
             int32_t n = 1;
             while (n < group && g + n < g0 + ng && c->chains[(size_t)(g + n)].inst == ci.inst) ++n;
@@ -865,7 +918,7 @@ extern "C" vns_status vns_eval_neighbourhood(vns_ctx *c, uint32_t nb_mask, int32
         VNS_HIP(c, launch_eval_inc(ea, d_tab, c->eval_wg_n, (size_t)group * (size_t)(maxT + 1) * kSnapBytes,
                                    c->stream));
     else
-        VNS_HIP(c, launch_eval(ea, d_tab, c->eval_wg_n, c->stream, c->model));
+        VNS_HIP(c, launch_eval(ea, d_tab, c->eval_wg_n, c->stream, c->model, spread ? spread : 4));
     VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     ChainBestArgs cb{c->d_chains, c->d_cs, c->d_cur_cost, c->d_prod_key, c->d_prod_price, c->d_prod_slot,
                      c->d_best, c->d_best_slot, g0};
@@ -1076,7 +1129,6 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     bool coop = false;
     // x stays in device memory: no state region; the learned search keeps its per-wavefront tiles
     const size_t lds_coop = rows_bytes + (size_t)learned;
-    const bool coop_learned = kind == RunKind::kLearned || kind == RunKind::kLearnedPacked;
     if (best) {
         if (kind != RunKind::kPlain || c->use_graph || ra.log_x != nullptr || c->spec_iters > 1)
             return fail(c, VNS_EINVAL, "best-of-G runs the plain search alone: no learned scorer, speculative VND or "

@@ -181,15 +181,19 @@ __host__ __device__ inline int run_rows_entries(int lds_rows, int waves) {
 
 // One pricing workgroup: products p .. p+np-1 of chains g0 .. g0+n-1 of one instance (chains of an instance
 // are consecutive, their products K apart; its products' rows are consecutive).  n = 0: an empty entry.
-// Everything the workgroup needs to start is here, so its first loads do not wait on one another.
+// Range form (G > 0): the n (chain, product) pairs q0 .. q0+n-1 of the instance's G chains g0 .. g0+G-1,
+// numbered product-major (pair q: product q / G, chain g0 + q % G); p = q0 / G is the first product and np
+// the products the range spans.  Everything the workgroup needs to start is here, so its first loads do
+// not wait on one another.
 struct EvalWg {
     int64_t cp;      // (chain g0, product p) index into the solution arrays
-    int32_t g0, n;   // first chain, number of chains
+    int32_t g0, n;   // first chain, number of chains (range form: number of pairs)
     int32_t K, T;    // the instance's products and periods
     int32_t p;       // first product index within the instance
     int32_t prod;    // its global product index (ProdParams)
     int32_t row;     // offset of its row
     int32_t np;      // products (1, or more for short horizons)
+    int32_t q0, G;   // range form: first pair and the instance's chains; G = 0 otherwise
 };
 
 // The pricing workgroup table built on the device, for the allocation-free pricing call: entry i is the

@@ -23,6 +23,7 @@ OPT_CHAINS, OPT_KMAX, OPT_NB_LIST, OPT_TRACE, OPT_RUN_WAVES, OPT_EVAL_GROUP, OPT
 OPT_LEARNED, OPT_LOG, OPT_SPECULATE, OPT_SPEC_WAVES, OPT_STATE_LDS, OPT_VND_MEMO = 9, 10, 11, 12, 13, 14
 OPT_SPEC_ITERS, OPT_BEST_OF, OPT_BEST_OF_LITERAL, OPT_EVAL_INCREMENTAL, OPT_DECODE = 15, 16, 17, 18, 19
 OPT_LEARNED_PACK = 20
+OPT_EVAL_SPREAD = 21
 DECODE_STRICT, DECODE_DISPOSE = 1, 2
 MLP_PARAMS, MLP_FEATURES = 5313, 16
 ALL_CHAINS = -1

@@ -42,6 +42,14 @@ def test_search_options_map_every_key():
     assert autotune.search_options(dict(waves=4, iters=6)) == {vns.OPT_RUN_WAVES: 4, vns.OPT_SPEC_ITERS: 6}
 
 
+def test_eval_options_map_group_and_spread():
+    from paper_1704_05132_amd import vns
+    assert autotune.eval_options({"group": 5}) == {vns.OPT_EVAL_SPREAD: 0, vns.OPT_EVAL_GROUP: 5}
+    assert autotune.eval_options({"spread": 8}) == {vns.OPT_EVAL_SPREAD: 8}
+    assert autotune.eval_options(dict(waves=4, iters=12)) == {vns.OPT_EVAL_SPREAD: 0}
+    assert {c.get("spread") for c in autotune.EVAL_CANDIDATES} >= {4, 8, 12, 16}
+
+
 def test_candidates_cover_both_search_kernels():
     kinds = {c.get("spec", 0) for c in autotune.SEARCH_CANDIDATES}
     assert kinds == {0, 1}
