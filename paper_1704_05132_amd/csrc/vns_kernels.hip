@@ -83,7 +83,6 @@ struct EvalShared {
     int64_t cost[kEvalPairs];
     int64_t out_off[kEvalPairs];
     int32_t off[kEvalPairs + 1];
-    int32_t nswap[kEvalPairs];
     uint8_t pidx[kEvalPairs];     // product index of each pair within the workgroup's products
     // the workgroup's moves, pair by pair (flips, then zM swaps, then zR swaps): pair << 9 | block << 7 | t
     uint16_t item[kEvalItems];
@@ -274,24 +273,18 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
 
     const bool fm = a.nb_mask & 1u, fr = a.nb_mask & 2u, shift = a.nb_mask & 4u;
     const int nflip = (fm ? T : 0) + (fr ? T : 0);
-    // swap counts per chain
-    for (int j = wave; j < n; j += nw) {
-        int ns = 0;
-        if (shift) {
-            uint32_t vm[kWords], vr[kWords];
-            swap_valid(sh.bits[j].m, T, vm);
-            swap_valid(sh.bits[j].r, T, vr);
-            ns = popc_words(vm) + popc_words(vr);
+    // the pairs' move counts (one lane per pair, n <= 64) and their exclusive prefix, by wavefront 0
+    if (wave == 0) {
+        int cnt = 0;
+        if (lane < n) {
+            cnt = nflip;
+            if (shift) {
+                uint32_t vm[kWords], vr[kWords];
+                swap_valid(sh.bits[lane].m, T, vm);
+                swap_valid(sh.bits[lane].r, T, vr);
+                cnt += popc_words(vm) + popc_words(vr);
+            }
         }
-        if (lane == 0) sh.nswap[j] = ns;
-    }
-    if (a.slot_price) {  // every slot of the group starts as "not a priced move"
-        for (int j = 0; j < n; ++j)
-            for (int l = threadIdx.x; l < 4 * T; l += blockDim.x) a.slot_price[sh.out_off[j] + l] = kInf;
-    }
-    __syncthreads();
-    if (wave == 0) {   // exclusive prefix of the pairs' move counts (n <= 64: one value per lane)
-        const int cnt = lane < n ? nflip + sh.nswap[lane] : 0;
         int inc = cnt;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -300,6 +293,10 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
         }
         if (lane < n) sh.off[lane] = inc - cnt;
         if (lane == 63) sh.off[n] = inc;
+    }
+    if (a.slot_price) {  // every slot of the group starts as "not a priced move"
+        for (int j = 0; j < n; ++j)
+            for (int l = threadIdx.x; l < 4 * T; l += blockDim.x) a.slot_price[sh.out_off[j] + l] = kInf;
     }
     __syncthreads();
     // the item table: flips (zM then zR), then each chain's valid swaps in period order; for incremental
@@ -347,17 +344,24 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
             const int blk = fblk0 + (i >= T ? 1 : 0);
             it[i] = pack_item(j, blk, i - (i >= T ? T : 0));
         }
-        if (shift) {
+        if (shift) {   // valid swaps compacted in period order by ballots, the zM swaps first
             uint32_t vm[kWords], vr[kWords];
             swap_valid(sh.bits[j].m, T, vm);
             swap_valid(sh.bits[j].r, T, vr);
-            const int nm = popc_words(vm);
-            for (int t = lane; t < T - 1; t += 64) {
-                bool sm, sr;
-                const int pm = rank_bit(vm, t, sm);
-                const int pr = rank_bit(vr, t, sr);
-                if (sm) it[nflip + pm] = pack_item(j, 2, t);
-                if (sr) it[nflip + nm + pr] = pack_item(j, 3, t);
+            const uint64_t below = (1ull << lane) - 1ull;
+            int o = nflip;
+#pragma unroll
+            for (int z = 0; z < 2; ++z) {
+                for (int t0 = 0; t0 < T - 1; t0 += 64) {
+                    const int t = t0 + lane, w = t >> 5;
+                    uint32_t word = z ? vr[0] : vm[0];
+#pragma unroll
+                    for (int q = 1; q < kWords; ++q) word = w == q ? (z ? vr[q] : vm[q]) : word;
+                    const bool v = w < kWords && ((word >> (t & 31)) & 1u);   // bits past T - 2 are clear
+                    const uint64_t bal = __ballot(v);
+                    if (v) it[o + __popcll(bal & below)] = pack_item(j, 2 + z, t);
+                    o += __popcll(bal);
+                }
             }
         }
     }
