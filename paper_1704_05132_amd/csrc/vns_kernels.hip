@@ -344,26 +344,8 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
             const int blk = fblk0 + (i >= T ? 1 : 0);
             it[i] = pack_item(j, blk, i - (i >= T ? T : 0));
         }
-        if (shift) {   // valid swaps compacted in period order by ballots, the zM swaps first
-            uint32_t vm[kWords], vr[kWords];
-            swap_valid(sh.bits[j].m, T, vm);
-            swap_valid(sh.bits[j].r, T, vr);
-            const uint64_t below = (1ull << lane) - 1ull;
-            int o = nflip;
-#pragma unroll
-            for (int z = 0; z < 2; ++z) {
-                for (int t0 = 0; t0 < T - 1; t0 += 64) {
-                    const int t = t0 + lane, w = t >> 5;
-                    uint32_t word = z ? vr[0] : vm[0];
-#pragma unroll
-                    for (int q = 1; q < kWords; ++q) word = w == q ? (z ? vr[q] : vm[q]) : word;
-                    const bool v = w < kWords && ((word >> (t & 31)) & 1u);   // bits past T - 2 are clear
-                    const uint64_t bal = __ballot(v);
-                    if (v) it[o + __popcll(bal & below)] = pack_item(j, 2 + z, t);
-                    o += __popcll(bal);
-                }
-            }
-        }
+        if (shift)   // each chain's valid swaps in period order, the zM swaps first
+            compact_swaps(sh.bits[j], T, it + nflip, [j](int z, int t) { return pack_item(j, 2 + z, t); });
     }
     __syncthreads();
 

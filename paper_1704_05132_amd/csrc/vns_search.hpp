@@ -53,35 +53,39 @@ __device__ __forceinline__ int popc_words(const uint32_t (&v)[kWords]) {
     return n;
 }
 
-// Rank of bit t among the set bits of v, and whether it is set.
-__device__ __forceinline__ int rank_bit(const uint32_t (&v)[kWords], int t, bool &set) {
-    const int jt = t >> 5;
-    const uint32_t below = (1u << (t & 31)) - 1u;
-    int r = 0;
-    set = false;
+// One wavefront lists the valid swaps of b in period order, the zM swaps first, compacted by ballots:
+// out[i] = item(z, t) for the i-th swap (z = 0 for zM, 1 for zR, t its first period).  Returns how many there
+// are (wave-uniform).  The caller synchronises the wavefront before reading out.  (The swap masks stay in
+// this function: passed by reference into another, the compiler kept them as per-thread arrays and moved
+// them to LDS, 32 bytes per thread.)
+template <class Item>
+__device__ __forceinline__ int compact_swaps(const Bits &b, int T, uint16_t *out, Item item) {
+    uint32_t vm[kWords], vr[kWords];
+    swap_valid(b.m, T, vm);
+    swap_valid(b.r, T, vr);
+    const int lane = threadIdx.x & 63;
+    const uint64_t below = (1ull << lane) - 1ull;
+    int o = 0;
 #pragma unroll
-    for (int j = 0; j < kWords; ++j) {
-        r += (j < jt) ? __popc(v[j]) : (j == jt ? __popc(v[j] & below) : 0);
-        set |= (j == jt) && ((v[j] >> (t & 31)) & 1u);
+    for (int z = 0; z < 2; ++z) {
+        for (int t0 = 0; t0 < T - 1; t0 += 64) {
+            const int t = t0 + lane, w = t >> 5;
+            uint32_t word = z ? vr[0] : vm[0];
+#pragma unroll
+            for (int q = 1; q < kWords; ++q) word = w == q ? (z ? vr[q] : vm[q]) : word;
+            const bool v = w < kWords && ((word >> (t & 31)) & 1u);   // bits past T - 2 are clear
+            const uint64_t bal = __ballot(v);
+            if (v) out[o + __popcll(bal & below)] = item(z, t);
+            o += __popcll(bal);
+        }
     }
-    return r;
+    return o;
 }
 
 // One wavefront writes the local slots of the valid swaps of b (zM swaps, then zR swaps) to list and
 // returns how many there are.  The caller synchronises the wavefront before reading the list.
-__device__ __forceinline__ int build_swap_list(const Bits &b, int T, uint16_t *list, int lane) {
-    uint32_t vm[kWords], vr[kWords];
-    swap_valid(b.m, T, vm);
-    swap_valid(b.r, T, vr);
-    const int nm = popc_words(vm);
-    for (int t = lane; t < T - 1; t += 64) {
-        bool sm, sr;
-        const int pm = rank_bit(vm, t, sm);
-        const int pr = rank_bit(vr, t, sr);
-        if (sm) list[pm] = (uint16_t)(2 * T + t);
-        if (sr) list[nm + pr] = (uint16_t)(3 * T + t);
-    }
-    return nm + popc_words(vr);
+__device__ __forceinline__ int build_swap_list(const Bits &b, int T, uint16_t *list) {
+    return compact_swaps(b, T, list, [T](int z, int t) { return (uint16_t)((2 + z) * T + t); });
 }
 
 
@@ -98,7 +102,7 @@ __device__ __forceinline__ int move_list(const Bits &b, int T, uint32_t nb, uint
     nflip = (nb & 3u) ? T : 0;
     int nswap = 0;
     if (nb & 4u) {
-        nswap = build_swap_list(b, T, list, lane);
+        nswap = build_swap_list(b, T, list);
         wave_sync_lds();
     }
     return nflip + nswap;
