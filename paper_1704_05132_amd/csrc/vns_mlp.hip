@@ -53,7 +53,7 @@ __global__ __launch_bounds__(64) void k_mlp_score(const float *__restrict__ P, c
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if ((tile + gridDim.x) * 64 < n) fetch(tile + gridDim.x);
-        const float s = forward64(sx, fr);   // ends with a wavefront barrier: sx may be rewritten
+        const float s = forward64<4>(sx, fr);   // ends with a wavefront barrier: sx may be rewritten
         const int64_t row = tile * 64 + lane;
         if (row < n) out[row] = s;
     }

@@ -85,13 +85,15 @@ __device__ __forceinline__ void load_frags(const float *__restrict__ P, Frags &f
 
 // Scores of 64 rows whose features sit in sx ([64][16] bfloat16).  Every lane of the wavefront must call it;
 // lane l receives the score of row l.  When z1 / z2 are given, the pre-activations of the two hidden layers
-// (float32, [64][64] row-major) are stored there as well.
+// (float32, [64][64] row-major) are stored there as well.  UNROLL groups of 16 rows are interleaved (more
+// independent matrix-core work in flight, more registers); the fused search kernels use 1.
+template <int UNROLL = 1>
 __device__ __forceinline__ float forward64(const __bf16 *sx, const Frags &fr, float *z1 = nullptr,
                                            float *z2 = nullptr) {
     const int lane = threadIdx.x & 63, c = lane & 15, g = lane >> 4;
     const bf8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
     float mine = 0.f;
-#pragma unroll 1
+#pragma unroll UNROLL
     for (int nt = 0; nt < 4; ++nt) {       // 16 moves at a time
         const int row = 16 * nt + c;
         const bf8 x = g < 2 ? *reinterpret_cast<const bf8 *>(sx + row * kF + 8 * g) : zero8;
