@@ -357,7 +357,10 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, w, plain):
                    "achieved": score_rows * MLP_FLOP_PER_ROW / (score_ms / 1e3) / 1e12, "peak": BF16_PEAK_TFLOPS,
                    "unit": "TFLOP/s",
                    "frac": score_rows * MLP_FLOP_PER_ROW / (score_ms / 1e3) / 1e12 / BF16_PEAK_TFLOPS,
-                   "flop_per_row": MLP_FLOP_PER_ROW},
+                   "flop_per_row": MLP_FLOP_PER_ROW,
+                   # its bytes: a 64-byte float32 feature row in, a 4-byte score out (152 flops per byte, under
+                   # the 312 at which the matrix cores and HBM balance, so HBM is the lower roof)
+                   "hbm_GBps": score_rows * 68 / (score_ms / 1e3) / 1e9, "hbm_frac": score_rows * 68 / (score_ms / 1e3) / 8e12},
         "note": "device time of the search launches only; scorer training is reported separately",
     }
     # where the time goes, per GVNS iteration of every chain (whole runs, chunked as above)
