@@ -959,14 +959,47 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 bool improved = true;
                 int passes = 0;
                 uint32_t clean = 0;   // neighbourhoods priced without improvement since the last applied move
+                // short horizons: consecutive neighbourhoods priced side by side in one pass when they fit 64 lanes
+                const bool multi = !LEARNED && !a.log_x && !a.memo && 2 * T + 1 <= 64;
                 while (improved && !stale) {
                     if (++passes > kMaxPasses) {
                         vnd_err = 1;
                         break;
                     }
                     improved = false;
-                    for (int q = 0; q < a.n_nb; ++q) {
-                        if (a.memo && ((clean >> q) & 1u)) continue;   // same pattern: nothing to find
+                    for (int q = 0; q < a.n_nb;) {
+                        if (multi) {
+                            int32_t rnow = coop_round;
+                            if constexpr (COOP) {
+                                if (may_abandon)
+                                    rnow = __hip_atomic_load(&a.coop_ctl[g].round, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT);
+                            }
+                            int used = 1;
+                            const bool id = need_ident;
+                            const uint64_t key = wave_best_move_multi<2, MODEL>(b, row, T, pp, a.nb_list, q, a.n_nb,
+                                                                                sh.list[wave], id, cost, evals, used);
+                            if (id) {
+                                shk += cost - c_cur;
+                                need_ident = false;
+                            }
+                            if (key != kInfKey) {   // improving by construction
+                                apply_move(b, (int)(key & ((1u << kSlotBits) - 1)), T);
+                                cost = (int64_t)(key >> kSlotBits);
+                                improved = true;
+                            }
+                            q += used;
+                            wave_sync_lds();
+                            if (__builtin_amdgcn_readfirstlane(rnow) != coop_round) {
+                                stale = true;
+                                break;
+                            }
+                            continue;
+                        }
+                        if (a.memo && ((clean >> q) & 1u)) {   // same pattern: nothing to find
+                            ++q;
+                            continue;
+                        }
                         // the round counter, read before the evaluation and looked at after it, so that the
                         // load's latency is hidden behind the pricing
                         int32_t rnow = coop_round;
@@ -1021,6 +1054,7 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                         }
                         // a move changes the pattern: every earlier pricing is stale
                         clean = applied ? 0u : (clean | (1u << q));
+                        ++q;
                         wave_sync_lds();
                         if (__builtin_amdgcn_readfirstlane(rnow) != coop_round) {
                             stale = true;
@@ -1355,8 +1389,9 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
 
 }  // namespace
 
+// Bounded to 128 registers: four wavefronts per SIMD for every decode reading.
 template <int MODEL>
-__global__ __launch_bounds__(512) void k_run(RunArgs a) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_run(RunArgs a) {
     __shared__ RunShared sh;
     __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];

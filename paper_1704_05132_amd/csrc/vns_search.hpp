@@ -159,6 +159,74 @@ __device__ __forceinline__ uint64_t wave_best_move(const Bits &b, const int2 *ro
     return wave_min_u64(best);
 }
 
+// Several consecutive neighbourhoods q0, q0 + 1, ... (at most three, of the n_nb in nb_list) of one pattern
+// priced side by side in one wavefront pass, for horizons short enough that their moves, and the unchanged
+// pattern with `ident`, fit 64 lanes (at most one of them may hold swaps: one list).  In Algorithm 1's order
+// the first neighbourhood whose best move beats `cost` is the one the VND takes; those after it were priced on
+// the pattern before that move, so they are dropped.  Returns that best key (kInfKey when none improves), sets
+// *used to the neighbourhoods consumed and counts evaluations for those only, so the moves and counts equal
+// one neighbourhood at a time.  With `ident`, cost is set to the unchanged pattern's price first.
+template <int NW, int MODEL = 0>
+__device__ __forceinline__ uint64_t wave_best_move_multi(const Bits &b, const int2 *row, int T, const ProdParams &pp,
+                                                         uint32_t nb_list, int q0, int n_nb, uint16_t *list,
+                                                         bool ident, int64_t &cost, int64_t &evals, int &used) {
+    const int lane = threadIdx.x & 63;
+    // the segments: neighbourhood k's moves at lanes [o_k, o_k + n_k)
+    int n0 = 0, n1 = 0, n2 = 0, f0 = 0, f1 = 0, f2 = 0, r = 0, sk = -1;
+    bool m0 = false, m1 = false, m2 = false;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (q0 + k >= n_nb) break;
+        const uint32_t nb = (nb_list >> (4 * (q0 + k))) & 0xFu;
+        const int nflip = (nb & 3u) ? T : 0;
+        int nsw = 0;
+        if (nb & 4u) {
+            if (sk >= 0) break;   // one swap list per pass
+            uint32_t vm[kWords], vr[kWords];
+            swap_valid(b.m, T, vm);
+            swap_valid(b.r, T, vr);
+            nsw = popc_words(vm) + popc_words(vr);
+        }
+        const int n = nflip + nsw;
+        if (k > 0 && n0 + n1 + n + (ident ? 1 : 0) > 64) break;
+        if (nb & 4u) sk = k;
+        if (k == 0) { n0 = n; f0 = nflip; m0 = nb & 1u; }
+        if (k == 1) { n1 = n; f1 = nflip; m1 = nb & 1u; }
+        if (k == 2) { n2 = n; f2 = nflip; m2 = nb & 1u; }
+        r = k + 1;
+    }
+    if (sk >= 0) {
+        build_swap_list(b, T, list);
+        wave_sync_lds();
+    }
+    const int o1 = n0, o2 = n0 + n1, total = n0 + n1 + n2;
+    const int seg = (lane >= o1) + (lane >= o2);
+    const int local = lane - (seg == 0 ? 0 : seg == 1 ? o1 : o2);
+    const int nflip = seg == 0 ? f0 : seg == 1 ? f1 : f2;
+    const bool fm = seg == 0 ? m0 : seg == 1 ? m1 : m2;
+    const int slot = lane < total ? (local < nflip ? (fm ? local : T + local) : (int)list[local - nflip]) : -1;
+    Bits mb = b;
+    if (slot >= 0) {
+        const int blk = (slot >= T) + (slot >= 2 * T) + (slot >= 3 * T);
+        xor_move<NW>(mb, blk, slot - blk * T);
+    }
+    const int64_t c = decode_cost<NW, MODEL>(mb, row, T, pp);
+    if (ident) cost = __shfl(c, total & 63, 64);
+    const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (k >= r) break;
+        const uint64_t best = wave_min_u64(seg == k && lane < total ? key : kInfKey);
+        evals += k == 0 ? n0 : k == 1 ? n1 : n2;
+        if (best != kInfKey && (int64_t)(best >> kSlotBits) < cost) {
+            used = k + 1;
+            return best;
+        }
+    }
+    used = r;
+    return kInfKey;
+}
+
 // Per-wavefront LDS of the learned search: the scorer's feature tile and the selected moves.
 struct LearnedLds {
     __bf16 *sx;        // [64][16]
