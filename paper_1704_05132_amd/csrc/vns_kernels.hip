@@ -542,7 +542,7 @@ struct SpecShared {
     int32_t next;         // next product index to hand out
 };
 
-template <bool SPEC, bool LEARNED, bool COOP = false, int MODEL = 0, bool PACK = false>
+template <bool SPEC, bool LEARNED, bool COOP = false, int MODEL = 0, bool PACK = false, bool MULTI = false>
 __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecShared &sp, int2 *s_rows) {
     static_assert(!PACK || LEARNED, "the packed form is the learned VND's");
     static_assert(!(SPEC && LEARNED), "the speculative VND prices whole neighbourhoods");
@@ -960,7 +960,8 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
                 int passes = 0;
                 uint32_t clean = 0;   // neighbourhoods priced without improvement since the last applied move
                 // short horizons: consecutive neighbourhoods priced side by side in one pass when they fit 64 lanes
-                const bool multi = !LEARNED && !a.log_x && !a.memo && 2 * T + 1 <= 64;
+                // (a kernel of its own, so that the others keep their registers)
+                const bool multi = MULTI && !a.log_x && !a.memo && T <= kMultiMaxT;
                 while (improved && !stale) {
                     if (++passes > kMaxPasses) {
                         vnd_err = 1;
@@ -1389,13 +1390,22 @@ __device__ __forceinline__ void run_chain(const RunArgs &a, RunShared &sh, SpecS
 
 }  // namespace
 
-// Bounded to 128 registers: four wavefronts per SIMD for every decode reading.
 template <int MODEL>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_run(RunArgs a) {
+__global__ __launch_bounds__(512) void k_run(RunArgs a) {
     __shared__ RunShared sh;
     __shared__ SpecShared sp;
     extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
     run_chain<false, false, false, MODEL>(a, sh, sp, s_rows);
+}
+
+// The same for batches with short horizons (up to kMultiMaxT): consecutive neighbourhoods priced side by side.
+// Bounded to 128 registers: four wavefronts per SIMD for every decode reading.
+template <int MODEL>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_run_short(RunArgs a) {
+    __shared__ RunShared sh;
+    __shared__ SpecShared sp;
+    extern __shared__ __attribute__((aligned(16))) int2 s_rows[];
+    run_chain<false, false, false, MODEL, false, true>(a, sh, sp, s_rows);
 }
 
 __global__ __launch_bounds__(1024) void k_run_spec(RunArgs a) {
@@ -1503,6 +1513,9 @@ template <int M> struct PickEvalWide {
     static const void *fn() { return reinterpret_cast<const void *>(&k_eval_wide<M>); }
 };
 template <int M> struct PickRun { static const void *fn() { return reinterpret_cast<const void *>(&k_run<M>); } };
+template <int M> struct PickRunShort {
+    static const void *fn() { return reinterpret_cast<const void *>(&k_run_short<M>); }
+};
 template <int M> struct PickCoop { static const void *fn() { return reinterpret_cast<const void *>(&k_run_coop<M>); } };
 
 hipError_t launch_init(const InitArgs &a, int n_chains, hipStream_t s, int model) {
@@ -1552,6 +1565,7 @@ static const void *run_kernel(RunKind kind, int model) {
         case RunKind::kSpec: return reinterpret_cast<const void *>(&k_run_spec);
         case RunKind::kLearned: return reinterpret_cast<const void *>(&k_run_learned);
         case RunKind::kLearnedPacked: return reinterpret_cast<const void *>(&k_run_learned_packed);
+        case RunKind::kPlainShort: return by_model<PickRunShort>(model);
         default: return by_model<PickRun>(model);
     }
 }

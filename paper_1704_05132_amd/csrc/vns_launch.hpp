@@ -33,7 +33,9 @@ struct ChainBestArgs {
 };
 
 // Variants of the search kernel: sequential VND, speculative VND, learned VND.
-enum class RunKind { kPlain = 0, kSpec = 1, kLearned = 2, kLearnedPacked = 3 };
+// kPlainShort: the plain search kernel with consecutive neighbourhoods priced side by side in one pass at
+// horizons up to kMultiMaxT (launched when an instance has one; the same moves and counts as kPlain).
+enum class RunKind { kPlain = 0, kSpec = 1, kLearned = 2, kLearnedPacked = 3, kPlainShort = 4 };
 
 // Static LDS bytes of a search kernel variant, and permission for it to request dynamic_bytes more.
 // model: the decode reading (kModelStrict | kModelDispose; the plain sequential VND only).

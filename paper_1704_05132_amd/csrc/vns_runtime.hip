@@ -1098,7 +1098,11 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     if (c->model != 0 && kind != RunKind::kPlain)
         return fail(c, VNS_EINVAL, "the learned search and the speculative VND take only the default decode reading "
                                    "(VNS_OPT_DECODE = 0)");
-    VNS_HIP(c, run_kernel_lds(kind, &static_lds, 0, c->model));
+    // the one-workgroup plain search has a variant for batches with a short horizon
+    int32_t min_T = kTMax;
+    for (int32_t i = 0; i < c->n_inst; ++i) min_T = std::min<int32_t>(min_T, c->T[(size_t)i]);
+    const RunKind run_k = (kind == RunKind::kPlain && min_T <= kMultiMaxT) ? RunKind::kPlainShort : kind;
+    VNS_HIP(c, run_kernel_lds(run_k, &static_lds, 0, c->model));
     const bool packed = c->permille > 0 && c->learned_pack > 1;
     const int64_t learned = c->permille <= 0 ? 0
                             : packed         ? (int64_t)pack_region_bytes(waves, c->learned_pack)
@@ -1120,7 +1124,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
     const size_t rows_bytes = (size_t)run_rows_entries(ra.lds_rows, waves) * sizeof(int2);
     ra.state_off = state_bytes > 0 ? (int32_t)(rows_bytes + (size_t)learned) : -1;
     const size_t lds = rows_bytes + (size_t)learned + (size_t)state_bytes;
-    VNS_HIP(c, run_kernel_lds(kind, &static_lds, lds, c->model));
+    VNS_HIP(c, run_kernel_lds(run_k, &static_lds, lds, c->model));
     // speculative iterations: plain search without the move log (a discarded iteration's moves must not be
     // logged), not captured, and every workgroup of the launch resident at once
     // best-of-G (Algorithm 2): the same cooperative launch with G workgroups per chain, one per random stream
@@ -1200,13 +1204,13 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         VNS_HIP(c, launch_run_coop(ra, (int)G, waves, lds_coop, c->d_iter, c->stream, kind, c->model));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     } else if (c->use_graph) {
-        const int64_t key[5] = {iters, G, waves * 4 + (int64_t)kind, (int64_t)lds, (int64_t)(intptr_t)ra.trace};
+        const int64_t key[5] = {iters, G, waves * 8 + (int64_t)run_k, (int64_t)lds, (int64_t)(intptr_t)ra.trace};
         bool same = true;
         for (int i = 0; i < 5; ++i) same = same && key[i] == c->graph_key[i];
         if (!same || !c->graph_exec) {
             drop_graph(c);
             VNS_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            hipError_t le = launch_run(ra, kind, (int)G, waves, lds, c->d_iter, c->stream, c->model);
+            hipError_t le = launch_run(ra, run_k, (int)G, waves, lds, c->d_iter, c->stream, c->model);
             hipGraph_t gr = nullptr;
             hipError_t ce = hipStreamEndCapture(c->stream, &gr);
             if (le != hipSuccess) {
@@ -1223,7 +1227,7 @@ extern "C" vns_status vns_run(vns_ctx *c, int32_t iters) {
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     } else {
         VNS_HIP(c, hipEventRecord(c->ev0, c->stream));
-        VNS_HIP(c, launch_run(ra, kind, (int)G, waves, lds, c->d_iter, c->stream, c->model));
+        VNS_HIP(c, launch_run(ra, run_k, (int)G, waves, lds, c->d_iter, c->stream, c->model));
         VNS_HIP(c, hipEventRecord(c->ev1, c->stream));
     }
     std::vector<ChainState> cs((size_t)G);

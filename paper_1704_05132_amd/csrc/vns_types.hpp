@@ -23,6 +23,7 @@ constexpr int kEvalGroup = 16;
 constexpr int kEvalPairs = 64;    // (chain, product) pairs one pricing workgroup may price
 constexpr int kEvalProds = 8;     //   of at most this many products (short horizons: their rows share LDS)
 constexpr int kEvalItems = 8192;  //   and at most this many moves
+constexpr int kMultiMaxT = 31;          // search: neighbourhoods priced side by side when 2T + 1 lanes fit a wavefront
 constexpr int kEvalTargetMoves = 1024;  // moves a pricing workgroup should get (4 passes of its 256 lanes)
 constexpr int kEvalShortT = 32;         //   by pricing several products when T is at most this
 constexpr int kSnapBytes = 24;          // incremental pricing: base state per chain and period (int4 + int2)
