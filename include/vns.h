@@ -281,7 +281,7 @@ vns_status vns_eval_neighbourhood(vns_ctx *ctx, uint32_t nb_mask, int32_t chain,
  * the same arguments, outputs (host pointers) and results, but it allocates nothing, on the device or on the
  * host.  Its scratch (evaluation counters, per-product argmin keys, the table of pricing workgroups, built on
  * the device, and the slot-price staging) lives in one static 8 MiB device array per GPU, held until the
- * process ends.  Limits: 48 bytes per (chain, product) priced, plus 8 bytes per slot when slot_price is
+ * process ends.  Limits: 56 bytes per (chain, product) priced, plus 8 bytes per slot when slot_price is
  * requested, plus 16 KiB, within the 8 MiB (for example every slot of one chain of 300 x 52, or the argmins
  * of 64 chains of 100 x 52); a larger request returns VNS_EINVAL without running.  Every call on a GPU shares
  * that GPU's array and it keeps the last call's contents (the call clears what must start at zero): calls

@@ -973,7 +973,7 @@ extern "C" vns_status vns_eval_neighbourhood_noalloc(vns_ctx *c, uint32_t nb_mas
     const size_t sp_bytes = slot_price ? align256(sizeof(int64_t) * (size_t)n_slots) : 0;
     if (ctr_bytes + key_bytes + tab_bytes + sp_bytes > kScratchBytes)
         return fail(c, VNS_EINVAL, "vns_eval_neighbourhood_noalloc: the chains priced need more than its 8 MiB static "
-                                   "scratch (48 bytes per (chain, product), plus 8 per slot with slot prices); "
+                                   "scratch (56 bytes per (chain, product), plus 8 per slot with slot prices); "
                                    "price fewer chains per call or use vns_eval_neighbourhood");
     unsigned char *base = static_cast<unsigned char *>(scratch_of(c->device));
     if (!base) return fail(c, VNS_EDEVICE, "the static scratch of this GPU has no device address");

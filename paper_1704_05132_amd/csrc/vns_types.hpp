@@ -196,6 +196,7 @@ struct EvalWg {
     int32_t np;      // products (1, or more for short horizons)
     int32_t q0, G;   // range form: first pair and the instance's chains; G = 0 otherwise
 };
+static_assert(sizeof(EvalWg) == 48, "the allocation-free pricing call documents 48 + 8 bytes per pair");
 
 // The pricing workgroup table built on the device, for the allocation-free pricing call: entry i is the
 // (chain, product) cp_begin + i; a chain leads a group when it is the first of its instance in the range or
