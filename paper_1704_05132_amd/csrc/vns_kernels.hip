@@ -157,8 +157,10 @@ __device__ __forceinline__ void base_snapshot(const Bits &b, const int2 *row, in
 // Moves sorted by first changed period, 64 at a time: every lane of a batch starts from the base's state
 // before the batch's first period t0 (a move changes nothing before its own first period, so its decode
 // there equals the base's) and the lanes step through the same periods, reading rows and setup bits at a
-// uniform position as the full decode does.  Every fourth period each lane checks whether it has rejoined
-// the base (or turned infeasible); the batch ends when all have, or at the horizon.
+// uniform position as the full decode does: single periods up to a multiple of 8, then blocks of 8 in the
+// full decode's form (two chunks of four, the setup words chosen once per block), then single periods to the
+// horizon.  Before each block every lane checks whether it has rejoined the base (or turned infeasible); the
+// batch ends when all have, or at the horizon.
 template <int NW>
 __device__ __forceinline__ void eval_items_inc(const EvalArgs &a, EvalShared &sh, const int4 *snapA, const int2 *snapB,
                                                int N, int T, const ProdParams &pp) {
@@ -190,38 +192,55 @@ __device__ __forceinline__ void eval_items_inc(const EvalArgs &a, EvalShared &sh
         }
         bool done = !in;
         int64_t c = kInf;
-        int tau = t0;
-        int2 row = sh.row[t0];
-        for (; tau < T; ++tau) {
-            if (tau > t0 && ((tau - t0) & 3) == 0) {
-                if (!done) {
-                    if (s.bad) {   // infeasible: kInf
+        // the lane's setup word w (w wave-uniform)
+        auto word = [&](const uint32_t (&v)[kWords], int w) {
+            uint32_t x = v[0];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) x = w == q ? v[q] : x;
+            return (int32_t)x;
+        };
+        // before period tau: has this lane rejoined the base (its cost is then known) or turned infeasible?
+        // True when every lane of the batch is done.
+        auto check = [&](int tau) -> bool {
+            if (!done) {
+                if (s.bad) {   // infeasible: kInf
+                    done = true;
+                } else if (tau > t1) {
+                    const int4 sa = snapA[j * (T + 1) + tau];
+                    if (sa.x == s.lim && sa.y == s.XR && sa.z == s.lsR && sa.w == enc_last(s)) {   // rejoined
+                        const int2 sb = snapB[j * (T + 1) + tau];
+                        const int64_t dA1 = (int64_t)s.A1 - sb.x, dA2 = (int64_t)s.A2 - sb.y;
+                        c = sh.cost[j] + (int64_t)pp.kM * dnM + (int64_t)pp.kR * dnR - (int64_t)pp.hM * (dA1 + dA2) +
+                            (int64_t)pp.hR * dA1;
                         done = true;
-                    } else if (tau > t1) {
-                        const int4 sa = snapA[j * (T + 1) + tau];
-                        if (sa.x == s.lim && sa.y == s.XR && sa.z == s.lsR && sa.w == enc_last(s)) {   // rejoined
-                            const int2 sb = snapB[j * (T + 1) + tau];
-                            const int64_t dA1 = (int64_t)s.A1 - sb.x, dA2 = (int64_t)s.A2 - sb.y;
-                            c = sh.cost[j] + (int64_t)pp.kM * dnM + (int64_t)pp.kR * dnR -
-                                (int64_t)pp.hM * (dA1 + dA2) + (int64_t)pp.hR * dA1;
-                            done = true;
-                        }
                     }
                 }
-                if (!__any(!done)) break;
             }
-            const int2 next = sh.row[tau + 1 < T ? tau + 1 : tau];   // the next period's row, read ahead
+            return !__any(!done);
+        };
+        auto single = [&](int tau) {
             const int w = tau >> 5;
-            uint32_t m = mb.m[0], r = mb.r[0];
-#pragma unroll
-            for (int q = 1; q < NW; ++q) {
-                m = w == q ? mb.m[q] : m;
-                r = w == q ? mb.r[q] : r;
+            decode_step(s, __builtin_amdgcn_sbfe(word(mb.m, w), tau & 31, 1),
+                        __builtin_amdgcn_sbfe(word(mb.r, w), tau & 31, 1), tau, sh.row[tau]);
+        };
+        int tau = t0;
+        bool all = false;
+        for (; tau < T && (tau & 7) != 0; ++tau) single(tau);
+        int2 ca[4], cb[4];
+        for (; tau + 8 <= T; tau += 8) {
+            if (tau > t0 && check(tau)) {
+                all = true;
+                break;
             }
-            decode_step(s, __builtin_amdgcn_sbfe((int32_t)m, tau & 31, 1), __builtin_amdgcn_sbfe((int32_t)r, tau & 31, 1),
-                        tau, row);
-            row = next;
+            load_chunk(sh.row, tau, ca);
+            load_chunk(sh.row, tau + 4, cb);
+            const int w = tau >> 5;   // a block of 8 never crosses a setup word
+            const int32_t m = word(mb.m, w), r = word(mb.r, w);
+            decode_chunk(s, m, r, tau, ca);
+            decode_chunk(s, m, r, tau + 4, cb);
         }
+        if (!all && tau < T && tau > t0 && (tau & 7) == 0) all = check(tau);
+        for (; !all && tau < T; ++tau) single(tau);
         if (!done) c = decode_finish<NW>(s, mb, T, pp);   // decoded to the horizon (kInf when infeasible)
         if (in) {
             decoded += tau - t0;                           // period-steps this lane's batch ran
