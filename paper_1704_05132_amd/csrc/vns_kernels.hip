@@ -335,13 +335,18 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, const EvalWg *__res
             sh.tcount[t] = cnt;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {   // exclusive prefix over the periods
-            int o = 0;
-            for (int t = 0; t < T; ++t) {
-                const int c = sh.tcount[t];
-                sh.tcount[t] = o;
-                o += c;
+        if (wave == 0) {   // exclusive prefix over the periods (T <= 128: two per lane)
+            const int c0 = 2 * lane < T ? sh.tcount[2 * lane] : 0;
+            const int c1 = 2 * lane + 1 < T ? sh.tcount[2 * lane + 1] : 0;
+            int inc = c0 + c1;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int up = __shfl_up(inc, d, 64);
+                inc += lane >= d ? up : 0;
             }
+            const int ex = inc - c0 - c1;
+            if (2 * lane < T) sh.tcount[2 * lane] = ex;
+            if (2 * lane + 1 < T) sh.tcount[2 * lane + 1] = ex + c0;
         }
         __syncthreads();
         for (int t = threadIdx.x; t < T; t += blockDim.x) {
