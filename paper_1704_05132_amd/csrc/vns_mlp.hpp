@@ -8,8 +8,8 @@
 //   setup period > t (T if none).
 // Parameters (float32 master copy, 5313 values): W1 [16][64] row-major, b1 [64], W2 [64][64], b2 [64],
 // W3 [64], b3.  The forward pass rounds weights and every layer's input to bfloat16 (nearest even); the
-// products are accumulated in float32 by v_mfma_f32_16x16x32_bf16 (layers 1 and 2) and by float32 dot
-// products (layer 3).
+// products are accumulated in float32 by v_mfma_f32_16x16x32_bf16 (all three layers; the training pass
+// takes layer 3 as float32 dot products).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -54,6 +54,7 @@ struct Frags {
     f4 b1[4];         // [hidden tile]: b1[16mt + 4g + e]
     f4 b2[4];         // [output tile]: b2[16mo + 4g + e]
     bf2 w3[4][2];     // [output tile][pair]: W3[16mo + 4g + 2pair + (0, 1)] in bfloat16
+    bf8 w3a[2];       // [k-slice]: every row of layer 3's A operand is W3, inputs pi(kt, 8g..8g+7)
     float b3;
 };
 
@@ -80,6 +81,10 @@ __device__ __forceinline__ void load_frags(const float *__restrict__ P, Frags &f
                 fr.w2t[mt][kt][e] = (__bf16)P[oW2 + in * kH + 16 * mt + c];
             }
     }
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) fr.w3a[kt][e] = (__bf16)P[oW3 + 32 * kt + 16 * (e >> 2) + 4 * g + (e & 3)];
     fr.b3 = P[oB3];
 }
 
@@ -116,20 +121,32 @@ __device__ __forceinline__ float forward64(const __bf16 *sx, const Frags &fr, fl
                 h[kt][4 + e] = hi[0];
                 h[kt][4 + e + 1] = hi[1];
             }
-        float acc3 = 0.f;
+        f4 d2[4];
 #pragma unroll
         for (int mo = 0; mo < 4; ++mo) {
-            f4 d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][0], h[0], fr.b2[mo], 0, 0, 0);
-            d2 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][1], h[1], d2, 0, 0, 0);
-            if (z2) *reinterpret_cast<f4 *>(z2 + row * kH + 16 * mo + 4 * g) = d2;
-            // layer 3: bfloat16 activations against bfloat16 W3, two products per v_dot2 (float32 sum)
-            acc3 = __builtin_amdgcn_fdot2_f32_bf16(relu_pack(d2[0], d2[1]), fr.w3[mo][0], acc3, false);
-            acc3 = __builtin_amdgcn_fdot2_f32_bf16(relu_pack(d2[2], d2[3]), fr.w3[mo][1], acc3, false);
+            d2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][0], h[0], fr.b2[mo], 0, 0, 0);
+            d2[mo] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w2t[mo][1], h[1], d2[mo], 0, 0, 0);
+            if (z2) *reinterpret_cast<f4 *>(z2 + row * kH + 16 * mo + 4 * g) = d2[mo];
         }
-        // layer 3: sum the four lane groups' partial dot products of each column; lane 16 nt + c keeps it
-        acc3 += __shfl_xor(acc3, 16, 64);
-        acc3 += __shfl_xor(acc3, 32, 64);
-        mine = nt == g ? acc3 : mine;
+        // layer 3 on the matrix cores as well: layer 2's D fragments are its B fragments (order pi, as layer 2
+        // takes layer 1's), and every row of A is W3, so every row of D is the 16 moves' scores and lane
+        // 16 g + c holds move c's in each element
+        bf8 h2[2];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int e = 0; e < 4; e += 2) {
+                const bf2 lo = relu_pack(d2[2 * kt][e], d2[2 * kt][e + 1]);
+                const bf2 hi = relu_pack(d2[2 * kt + 1][e], d2[2 * kt + 1][e + 1]);
+                h2[kt][e] = lo[0];
+                h2[kt][e + 1] = lo[1];
+                h2[kt][4 + e] = hi[0];
+                h2[kt][4 + e + 1] = hi[1];
+            }
+        const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
+        f4 d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w3a[0], h2[0], zero4, 0, 0, 0);
+        d3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr.w3a[1], h2[1], d3, 0, 0, 0);
+        mine = nt == g ? d3[0] : mine;   // lane 16 nt + c keeps move c's score
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
