@@ -307,9 +307,41 @@ __device__ __forceinline__ uint64_t learned_best_move(const Bits &b, const int2 
     }
     // 1-2. scores of every move and the best-ranked ones
     const int n_sel = learned_select(b, row, T, pp, nitems, nflip, fm, list, L.sx, L.sel, fr, permille, score_out, sel_out);
+    evals += n_sel;
+    if (nitems + (ident ? 1 : 0) <= 128) {
+        // 3-4 together: when the whole neighbourhood (and the unchanged pattern) takes at most two wavefront
+        // passes, every move is priced at once, since pricing only the selection costs one pass of the same
+        // latency and most evaluations fall back (about three in four here); the selection's best and,
+        // should it not improve, the whole neighbourhood's best come from the same exact prices, as the two
+        // steps below would give them
+        uint64_t best_sel = kInfKey, best_all = kInfKey;
+        int64_t idc = 0;
+        const int total = nitems + (ident ? 1 : 0);
+        for (int basei = 0; basei < total; basei += 64) {
+            const int idx = basei + lane;
+            const int slot = idx < nitems ? item_slot(idx, nflip, fm, T, list) : -1;
+            bool selected = false;
+            for (int r = 0; r < n_sel; ++r) selected |= slot >= 0 && slot == (int)L.sel[r];
+            Bits mb = b;
+            if (slot >= 0) apply_move(mb, slot, T);
+            const int64_t c = decode_cost(mb, row, T, pp);
+            if (idx == nitems) idc = c;
+            const uint64_t key = (slot >= 0 && c != kInf) ? (((uint64_t)c << kSlotBits) | (uint64_t)slot) : kInfKey;
+            best_all = key < best_all ? key : best_all;
+            best_sel = (selected && key < best_sel) ? key : best_sel;
+        }
+        if (ident) cost = __shfl(idc, nitems & 63, 64);
+        best_sel = wave_min_u64(best_sel);
+        if (best_sel != kInfKey && (int64_t)(best_sel >> kSlotBits) < cost) {
+            fallback = 0;
+            return best_sel;
+        }
+        fallback = 1;   // the whole neighbourhood, exactly (already priced)
+        evals += nitems;
+        return wave_min_u64(best_all);
+    }
     // 3. exact prices of the selection (and of the unchanged pattern)
     const int total = n_sel + (ident ? 1 : 0);
-    evals += n_sel;
     uint64_t best = kInfKey;
     int64_t idc = 0;
     for (int basei = 0; basei < total; basei += 64) {
