@@ -377,10 +377,11 @@ def learned_vs_plain(args, vns, stream, table, key, name, insts, w, plain):
     out["per_iteration"] = {"plain": per_it(plain), "learned": per_it(lrn)}
     if packed is not None:
         out["packed"] = packed
-    out["reason"] = ("a learned neighbourhood evaluation scores every move (MFMA), prices the best-ranked share "
-                     "exactly with one move per lane over all T periods (the same decode latency as pricing the "
-                     "whole neighbourhood) and prices the whole neighbourhood again when none of them improves "
-                     "(fallback_share); exact pricing runs near the int32 peak, so fewer exact evaluations do not "
+    out["reason"] = ("a learned neighbourhood evaluation scores every move (MFMA) and then needs the exact prices "
+                     "of the best-ranked share, with one move per lane over all T periods (the same decode latency "
+                     "as pricing the whole neighbourhood), and of the whole neighbourhood when none of them "
+                     "improves (fallback_share; both come from one pricing when the neighbourhood fits two "
+                     "wavefront passes); exact pricing runs near the int32 peak, so fewer exact evaluations do not "
                      "buy back the scoring and the fallbacks")
     if n_inst == 1:
         out["plain_best_F"] = int(B[0])
