@@ -568,7 +568,7 @@ def main():
         print(kernel_source_hash())
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; a multi-GPU run is not part of it (use --gpus 1)",
+        print("bench.py: the benchmark runs on one GPU; a multi-GPU run is not supported (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
