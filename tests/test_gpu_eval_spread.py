@@ -7,6 +7,7 @@ price exactly what the default form prices:
   * a batch of uneven instances (T = 1, 12, 24, 33, 52, 65, 104, 128), with ranges that cross products and
     ranges cut at a product's end, against the oracle and the default form;
   * one chain of a batch, the decode readings, the counted evaluations, the 4096-instance set's argmins;
+  * the workgroup table in a caller-bound workspace with stale contents;
   * option rules (values, incremental pricing keeps its own shape).
 """
 import sys
@@ -192,3 +193,28 @@ def test_option_rules(vns):
         same(ctx.eval_neighbourhood(7), base)
         ctx.set_option(vns.OPT_EVAL_INCREMENTAL, 0)
         same(ctx.eval_neighbourhood(7), base)
+
+
+@pytest.mark.parametrize("spread", [4, 16])
+def test_bound_workspace(vns, spread):
+    """The range form's workgroup table in a caller-bound workspace (stale contents) equals own buffers."""
+    import torch
+    insts = uneven_batch()
+    chains = 3
+    with vns.Context(insts, seed=8, chains=chains) as a, vns.Context(insts, seed=8, chains=chains) as b:
+        for ctx in (a, b):
+            ctx.bind_stream(torch.cuda.current_stream())
+            ctx.run(5)
+            ctx.set_option(vns.OPT_EVAL_SPREAD, spread)
+        flags = vns.WS_EVAL_PRICES
+        buf = torch.empty(b.workspace_bytes(flags), dtype=torch.uint8, device="cuda")
+        b.bind_workspace(buf, flags)
+        buf.fill_(0x5A)
+        torch.cuda.synchronize()
+        ea, eb = a.eval_neighbourhood(7), b.eval_neighbourhood(7)
+        for k in ea:
+            assert (ea[k] == eb[k]).all(), k
+        oa, ob = a.eval_neighbourhood(6, 7), b.eval_neighbourhood(6, 7)
+        for k in oa:
+            assert (oa[k] == ob[k]).all(), k
+        b.bind_workspace(None, 0)
